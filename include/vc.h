@@ -1,0 +1,160 @@
+/*
+ * vc.h -- C ABI of the MI355X vertex-cover search library (libvc.so).
+ *
+ * The library solves the two problems of the paper's problem statement (paper §II-A):
+ *   - Minimum Vertex Cover (MVC): the smallest set S of vertices such that every edge has an
+ *     endpoint in S. vc_mvc returns |S| and one such S.
+ *   - Parameterized Vertex Cover (PVC): given k, a vertex cover with at most k vertices if
+ *     one exists. vc_pvc returns yes/no and, on yes, a cover of size <= k.
+ * Both run the paper's hybrid branch-and-reduce traversal (§IV-A) on one GPU: a persistent
+ * grid in which every workgroup walks a sub-tree with its own stack in device memory and
+ * shares branches through a global worklist; intermediate graphs are degree arrays over one
+ * read-only CSR copy of the input (§IV-B).
+ *
+ * Graph format (all entry points): simple undirected graph (§II-A) in int32 CSR.
+ *   n          number of vertices, 0 <= n < 2^31
+ *   nnz        number of stored entries = 2|E| (every edge appears in both rows)
+ *   row_ptr    n+1 entries, row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col_idx    nnz entries; row v holds the neighbours of v, strictly ascending, no v itself,
+ *              and u in row v  <=>  v in row u.
+ * An input that breaks any of these rules is rejected with VC_ERR_INVALID_GRAPH; nothing is
+ * repaired. Vertices of degree 0 never enter a returned cover.
+ *
+ * Threading: one call at a time per context. Separate contexts may be used concurrently.
+ * Ownership: every pointer argument stays owned by the caller; the library keeps no
+ * reference after a call returns. The context owns its device workspace (kept and grown
+ * across calls) and, if it created one, its HIP stream.
+ * Errors: every entry point returns VC_OK (0) or a negative VC_ERR_* code. On error the
+ * output arguments are left untouched and vc_last_error() describes the failure.
+ */
+#ifndef VC_H
+#define VC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------- */
+#define VC_OK 0
+#define VC_ERR_INVALID_GRAPH (-1) /* CSR breaks the format above (first offending row named) */
+#define VC_ERR_INVALID_ARG (-2)   /* NULL pointer, k < 0, bad option, graph too large for LDS */
+#define VC_ERR_NO_MEMORY (-3)     /* stacks + worklist do not fit in free device memory */
+#define VC_ERR_BUDGET (-4)        /* node budget exhausted before the search ended */
+#define VC_ERR_DEVICE (-5)        /* a HIP runtime call failed, or no usable device */
+#define VC_ERR_INTERNAL (-6)      /* a device-side invariant failed (stack overflow, or a
+                                     returned cover failed edge-by-edge verification) */
+
+/* ---- option flags (vc_options.flags) -------------------------------------------------- */
+#define VC_OPT_NO_DEGREE_ONE 0x1  /* ablation: switch off the degree-one rule */
+#define VC_OPT_NO_TRIANGLE 0x2    /* ablation: switch off the degree-two-triangle rule */
+#define VC_OPT_NO_HIGH_DEGREE 0x4 /* ablation: switch off the high-degree rule (this also
+                                     switches off the |E| > r^2 prune, which relies on it) */
+#define VC_OPT_NO_EDGE_PRUNE 0x8  /* ablation: switch off the |E| > r^2 prune */
+
+typedef struct vc_ctx vc_ctx;
+
+typedef struct {
+  int32_t n;
+  int32_t nnz;
+  const int32_t *row_ptr; /* n+1 entries */
+  const int32_t *col_idx; /* nnz entries */
+} vc_graph;
+
+/* Launch and search knobs; a zeroed struct (or NULL) means "choose automatically". */
+typedef struct {
+  int32_t wg_size;      /* threads per workgroup, a multiple of 64 up to 1024; 0 = auto
+                           (the occupancy rule of §IV-E) */
+  int32_t num_wg;       /* workgroups in the persistent grid; 0 = as many as are co-resident;
+                           larger values are clamped to the co-resident maximum */
+  int32_t wl_capacity;  /* global worklist entries (rounded up to a power of two); 0 = auto */
+  int32_t wl_threshold; /* a branch is donated to the worklist only while it holds fewer than
+                           this many entries (§IV-A); 0 = auto; -1 = never donate (every
+                           workgroup keeps its whole sub-tree on its own stack) */
+  int64_t node_budget;  /* stop with VC_ERR_BUDGET after about this many nodes; 0 = none */
+  int32_t flags;        /* VC_OPT_* */
+  int32_t reserved[5];  /* must be zero */
+} vc_options;
+
+/* Per-call statistics. A search-tree node is one visit: a node is taken from the stack or
+ * the worklist (or continued in place) and the reduction rules run on it. */
+typedef struct {
+  int64_t nodes;          /* nodes visited, all workgroups */
+  int64_t wg_nodes_max;   /* most nodes visited by one workgroup */
+  int64_t wg_nodes_min;   /* fewest nodes visited by one workgroup */
+  int64_t stack_pushes;   /* deferred children kept on a workgroup's own stack */
+  int64_t stack_pops;
+  int64_t wl_enqueues;    /* deferred children donated to the worklist */
+  int64_t wl_dequeues;    /* worklist entries taken (the root included) */
+  int32_t max_stack_depth;
+  int32_t greedy_size;    /* MVC: size of the greedy cover that seeds the bound; PVC: -1 */
+  int32_t wg_size;
+  int32_t num_wg;
+  int32_t wl_capacity;
+  int32_t wl_threshold;
+  int32_t depth_cap;      /* stack entries provisioned per workgroup */
+  int32_t n;
+  double kernel_ms;       /* traversal kernel time (HIP events on the context stream) */
+  double greedy_ms;       /* greedy kernel time (MVC) */
+  double total_ms;        /* wall clock of the whole call */
+} vc_stats;
+
+/* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to run on, or NULL
+ * for a stream owned by the context. */
+int vc_create(vc_ctx **ctx_out, int device, void *hip_stream);
+
+/* Release the context, its workspace and its own stream. NULL is accepted. */
+int vc_destroy(vc_ctx *ctx);
+
+/* Text of a status code. */
+const char *vc_strerror(int status);
+
+/* Description of the last failure on this context ("" if none). Valid until the next call. */
+const char *vc_last_error(const vc_ctx *ctx);
+
+/* Library version, "major.minor.patch". */
+const char *vc_version(void);
+
+/* MVC (paper §II-A, §II-B, §IV-A). `g` holds HOST pointers. On success *size_out = tau(G) and,
+ * if cover_out is not NULL, cover_out[v] = 1 for the n vertices of one minimum cover
+ * (any minimum cover may be returned), 0 elsewhere. `opts` and `stats` may be NULL. */
+int vc_mvc(vc_ctx *ctx, const vc_graph *g, const vc_options *opts, int32_t *size_out,
+           uint8_t *cover_out, vc_stats *stats);
+
+/* PVC (paper §II-A; search differences in §II-B and §IV-A). `g` holds HOST pointers; k >= 0.
+ * On success *yes_out = 1 and *size_out = |S| <= k with cover_out[v] = 1 on S, or
+ * *yes_out = 0, *size_out = -1 and cover_out all zero. `opts` and `stats` may be NULL. */
+int vc_pvc(vc_ctx *ctx, const vc_graph *g, int32_t k, const vc_options *opts,
+           int32_t *yes_out, int32_t *size_out, uint8_t *cover_out, vc_stats *stats);
+
+/* Device-resident forms of vc_mvc / vc_pvc: `g->row_ptr` and `g->col_idx` are DEVICE
+ * pointers on the context's device and `cover_dev` (n bytes, may be NULL) is written in
+ * device memory. The call runs on the context stream, after work already queued on it, and
+ * returns when the search has finished. Size and yes/no are returned in host memory. */
+int vc_mvc_device(vc_ctx *ctx, const vc_graph *g, const vc_options *opts, int32_t *size_out,
+                  uint8_t *cover_dev, vc_stats *stats);
+int vc_pvc_device(vc_ctx *ctx, const vc_graph *g, int32_t k, const vc_options *opts,
+                  int32_t *yes_out, int32_t *size_out, uint8_t *cover_dev, vc_stats *stats);
+
+/* The greedy approximation that seeds MVC's bound (paper §II-B, §IV-E), on the GPU with one
+ * workgroup: apply the degree-one and degree-two-triangle rules, put a vertex of maximum
+ * degree (smallest id on ties) in the cover, repeat until no edge is left. DEVICE graph
+ * pointers; `cover_dev` (n bytes, may be NULL) in device memory; size in host memory. */
+int vc_greedy_device(vc_ctx *ctx, const vc_graph *g, int32_t *size_out, uint8_t *cover_dev);
+
+/* The reduction rules of one search-tree node (paper §II-B, parallel rules §IV-D), applied
+ * until the graph stops changing, exactly as the traversal applies them, by one workgroup.
+ * DEVICE pointers: `deg_dev` (n int32, in/out) is a degree array (degree of each vertex, -1
+ * for vertices already in the cover) consistent with the CSR; *s_inout (host) is the cover
+ * size so far. `bound` is the largest cover size still of interest (MVC: best - 1, PVC: k);
+ * the passes stop early once the cover size exceeds it. `flags` takes VC_OPT_NO_* bits. */
+int vc_reduce_device(vc_ctx *ctx, const vc_graph *g, int32_t *deg_dev, int32_t *s_inout,
+                     int64_t bound, int32_t flags);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VC_H */

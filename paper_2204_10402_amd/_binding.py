@@ -1,0 +1,272 @@
+"""ctypes binding of libvc.so (include/vc.h). Argument marshalling only: every step of the
+search runs in the library's HIP kernels. PyTorch, when used, only supplies device memory and
+the stream."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libvc.so")
+
+OK = 0
+ERR_INVALID_GRAPH = -1
+ERR_INVALID_ARG = -2
+ERR_NO_MEMORY = -3
+ERR_BUDGET = -4
+ERR_DEVICE = -5
+ERR_INTERNAL = -6
+
+OPT_NO_DEGREE_ONE = 0x1
+OPT_NO_TRIANGLE = 0x2
+OPT_NO_HIGH_DEGREE = 0x4
+OPT_NO_EDGE_PRUNE = 0x8
+
+# Every function include/vc.h declares.
+EXPORTS = (
+    "vc_create", "vc_destroy", "vc_strerror", "vc_last_error", "vc_version",
+    "vc_mvc", "vc_pvc", "vc_mvc_device", "vc_pvc_device", "vc_greedy_device",
+    "vc_reduce_device",
+)
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("wg_size", ctypes.c_int32), ("num_wg", ctypes.c_int32),
+                ("wl_capacity", ctypes.c_int32), ("wl_threshold", ctypes.c_int32),
+                ("node_budget", ctypes.c_int64), ("flags", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 5)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("nodes", ctypes.c_int64), ("wg_nodes_max", ctypes.c_int64),
+                ("wg_nodes_min", ctypes.c_int64), ("stack_pushes", ctypes.c_int64),
+                ("stack_pops", ctypes.c_int64), ("wl_enqueues", ctypes.c_int64),
+                ("wl_dequeues", ctypes.c_int64), ("max_stack_depth", ctypes.c_int32),
+                ("greedy_size", ctypes.c_int32), ("wg_size", ctypes.c_int32),
+                ("num_wg", ctypes.c_int32), ("wl_capacity", ctypes.c_int32),
+                ("wl_threshold", ctypes.c_int32), ("depth_cap", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
+                ("greedy_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+
+
+@dataclass
+class Options:
+    """Launch and search knobs of vc_options (0 = automatic)."""
+    wg_size: int = 0
+    num_wg: int = 0
+    wl_capacity: int = 0
+    wl_threshold: int = 0
+    node_budget: int = 0
+    flags: int = 0
+
+    def _c(self) -> _Options:
+        o = _Options()
+        o.wg_size, o.num_wg = self.wg_size, self.num_wg
+        o.wl_capacity, o.wl_threshold = self.wl_capacity, self.wl_threshold
+        o.node_budget, o.flags = self.node_budget, self.flags
+        return o
+
+
+@dataclass
+class Result:
+    size: int               # MVC: minimum cover size; PVC: cover size or -1
+    yes: bool               # PVC decision (True for MVC)
+    cover: object           # numpy uint8[n] (host calls) or the caller's device tensor
+    stats: dict = field(default_factory=dict)
+
+
+class VCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libvc.so. Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing; build it with `python -m paper_2204_10402_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    gp, op, sp = ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Stats)
+    sig = {
+        "vc_create": ([ctypes.POINTER(vp), ctypes.c_int, vp], ctypes.c_int),
+        "vc_destroy": ([vp], ctypes.c_int),
+        "vc_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "vc_last_error": ([vp], ctypes.c_char_p),
+        "vc_version": ([], ctypes.c_char_p),
+        "vc_mvc": ([vp, gp, op, i32p, vp, sp], ctypes.c_int),
+        "vc_pvc": ([vp, gp, i32, op, i32p, i32p, vp, sp], ctypes.c_int),
+        "vc_mvc_device": ([vp, gp, op, i32p, vp, sp], ctypes.c_int),
+        "vc_pvc_device": ([vp, gp, i32, op, i32p, i32p, vp, sp], ctypes.c_int),
+        "vc_greedy_device": ([vp, gp, i32p, vp], ctypes.c_int),
+        "vc_reduce_device": ([vp, gp, vp, i32p, i64, i32], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _stats_dict(s: _Stats) -> dict:
+    return {name: getattr(s, name) for name, _ in _Stats._fields_}
+
+
+def _host_graph(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(g.col_idx, dtype=np.int32)
+    cg = _Graph(int(g.n), int(ci.size), rp.ctypes.data, ci.ctypes.data if ci.size else None)
+    return cg, (rp, ci)
+
+
+def _device_graph(row_ptr, col_idx):
+    import torch
+    for t, name in ((row_ptr, "row_ptr"), (col_idx, "col_idx")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32 \
+                or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous int32 device tensor")
+    n = row_ptr.numel() - 1
+    if n < 0:
+        raise ValueError("row_ptr must hold n+1 entries")
+    return _Graph(n, col_idx.numel(), row_ptr.data_ptr(),
+                  col_idx.data_ptr() if col_idx.numel() else None)
+
+
+class Solver:
+    """One library context (device workspace + HIP stream).
+
+    ``stream``: None for a stream owned by the context, or a ``torch.cuda.Stream`` to run on.
+    Device-form calls order themselves after the work queued on torch's current stream.
+    """
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = load_library()
+        self._ctx = ctypes.c_void_p()
+        self._stream = stream
+        handle = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        rc = self._lib.vc_create(ctypes.byref(self._ctx), int(device), handle)
+        if rc != OK:
+            raise VCError(rc, f"vc_create failed: {self._lib.vc_strerror(rc).decode()}")
+        self.device = device
+
+    def close(self):
+        if self._ctx:
+            self._lib.vc_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if rc != OK:
+            detail = self._lib.vc_last_error(self._ctx).decode()
+            raise VCError(rc, f"{what}: {self._lib.vc_strerror(rc).decode()}: {detail}")
+
+    def _order_after_torch(self):
+        import torch
+        cur = torch.cuda.current_stream(self.device)
+        if self._stream is None or self._stream.cuda_stream != cur.cuda_stream:
+            cur.synchronize()
+
+    @staticmethod
+    def _opts(options):
+        return ctypes.byref(options._c()) if options is not None else None
+
+    # ---- host-memory graphs -------------------------------------------------------------
+
+    def mvc(self, g, options: Options | None = None) -> Result:
+        cg, keep = _host_graph(g)
+        cover = np.zeros(max(g.n, 1), np.uint8)
+        size = ctypes.c_int32()
+        st = _Stats()
+        rc = self._lib.vc_mvc(self._ctx, ctypes.byref(cg), self._opts(options),
+                              ctypes.byref(size), cover.ctypes.data, ctypes.byref(st))
+        self._check(rc, "vc_mvc")
+        return Result(size.value, True, cover[:g.n], _stats_dict(st))
+
+    def pvc(self, g, k: int, options: Options | None = None) -> Result:
+        cg, keep = _host_graph(g)
+        cover = np.zeros(max(g.n, 1), np.uint8)
+        size, yes = ctypes.c_int32(), ctypes.c_int32()
+        st = _Stats()
+        rc = self._lib.vc_pvc(self._ctx, ctypes.byref(cg), int(k), self._opts(options),
+                              ctypes.byref(yes), ctypes.byref(size), cover.ctypes.data,
+                              ctypes.byref(st))
+        self._check(rc, "vc_pvc")
+        return Result(size.value, bool(yes.value), cover[:g.n], _stats_dict(st))
+
+    # ---- device-memory graphs (torch tensors) --------------------------------------------
+
+    def mvc_device(self, row_ptr, col_idx, cover=None, options: Options | None = None) -> Result:
+        cg = _device_graph(row_ptr, col_idx)
+        self._order_after_torch()
+        size = ctypes.c_int32()
+        st = _Stats()
+        rc = self._lib.vc_mvc_device(self._ctx, ctypes.byref(cg), self._opts(options),
+                                     ctypes.byref(size),
+                                     cover.data_ptr() if cover is not None else None,
+                                     ctypes.byref(st))
+        self._check(rc, "vc_mvc_device")
+        return Result(size.value, True, cover, _stats_dict(st))
+
+    def pvc_device(self, row_ptr, col_idx, k: int, cover=None,
+                   options: Options | None = None) -> Result:
+        cg = _device_graph(row_ptr, col_idx)
+        self._order_after_torch()
+        size, yes = ctypes.c_int32(), ctypes.c_int32()
+        st = _Stats()
+        rc = self._lib.vc_pvc_device(self._ctx, ctypes.byref(cg), int(k), self._opts(options),
+                                     ctypes.byref(yes), ctypes.byref(size),
+                                     cover.data_ptr() if cover is not None else None,
+                                     ctypes.byref(st))
+        self._check(rc, "vc_pvc_device")
+        return Result(size.value, bool(yes.value), cover, _stats_dict(st))
+
+    def greedy_device(self, row_ptr, col_idx, cover=None) -> int:
+        cg = _device_graph(row_ptr, col_idx)
+        self._order_after_torch()
+        size = ctypes.c_int32()
+        rc = self._lib.vc_greedy_device(self._ctx, ctypes.byref(cg), ctypes.byref(size),
+                                        cover.data_ptr() if cover is not None else None)
+        self._check(rc, "vc_greedy_device")
+        return size.value
+
+    def reduce_device(self, row_ptr, col_idx, deg, s: int, bound: int, flags: int = 0) -> int:
+        """Reduction rules in place on the int32 device tensor ``deg``; returns the new s."""
+        cg = _device_graph(row_ptr, col_idx)
+        self._order_after_torch()
+        sv = ctypes.c_int32(int(s))
+        rc = self._lib.vc_reduce_device(self._ctx, ctypes.byref(cg), deg.data_ptr(),
+                                        ctypes.byref(sv), int(bound), int(flags))
+        self._check(rc, "vc_reduce_device")
+        return sv.value
+
+
+def version() -> str:
+    return load_library().vc_version().decode()

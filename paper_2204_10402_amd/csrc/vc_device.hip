@@ -1,0 +1,966 @@
+// vc_device.hip -- HIP kernels for gfx950 (MI355X) of the hybrid vertex-cover traversal.
+//
+// Method (paper §IV): a persistent grid; every workgroup walks a sub-tree of the
+// branch-and-reduce search tree depth first with its own stack in device memory, and hands
+// branches to a global worklist while the worklist holds fewer entries than a threshold
+// (§IV-A). An intermediate graph is a degree array over one read-only CSR (§IV-B): one int32
+// per vertex holding its degree, or -1 once the vertex is in the cover, followed by the cover
+// size s (the |S| counter of §IV-B) and a pending branch vertex (see below).
+//
+// gfx950 mapping:
+//  - the node being worked on lives in LDS; every rule pass, the max-degree search and the
+//    vertex removals read and update it there (LDS atomics for degree decrements);
+//  - vertices are processed in 64-vertex chunks, one chunk per wavefront at a time; a
+//    ballot over the chunk yields the candidates, and each candidate's CSR row is then
+//    scanned by the whole wavefront (coalesced 64-wide loads from the L2-resident CSR);
+//  - the maximum-degree vertex and the degree sum come from one pass reduced with DPP row
+//    operations inside each wavefront and one LDS step across wavefronts;
+//  - a deferred child is stored as its parent's reduced degree array plus the vertex whose
+//    neighbourhood it removes (the "pending" vertex); the removal is done in LDS by whoever
+//    takes the child, so a branch costs one plain copy of the node out and one copy back in,
+//    and no global-memory atomics touch node data;
+//  - the worklist is a bounded ring of node slots with per-slot lap tickets; producers and
+//    consumers synchronise through agent-scope atomics, so a node written on one XCD is seen
+//    correctly by a workgroup on another;
+//  - termination: a counter of outstanding sub-trees (queued, or held by a workgroup) is
+//    raised before a node is published and lowered when a workgroup has finished the whole
+//    sub-tree it took; the search is over when it reads zero (§IV-C).
+//
+// Rule semantics (paper §II-B, parallel tie-breaks §IV-D): each rule is one pass that decides
+// from the degree array as it stood at the start of the pass (decisions are marked with a
+// flag bit that leaves the degree bits untouched), then removes every marked vertex at once.
+// The passes run degree-one, degree-two-triangle, high-degree, and repeat until a whole round
+// changes nothing or s exceeds the bound.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vc_internal.h"
+
+namespace vc {
+
+constexpr int32_t kSent = -1;
+constexpr int32_t kFlag = 0x40000000;     // "decided this pass" mark on a live entry
+constexpr int32_t kDegMask = 0x3FFFFFFF;  // degree bits of a live entry
+constexpr int kMaxWaves = 16;             // 1024 threads
+
+// ---- scoped atomics ------------------------------------------------------------------------
+
+__device__ __forceinline__ int32_t* ctr_i32(const Params& p, int slot) {
+  return p.ctr + slot * kCounterStride;
+}
+__device__ __forceinline__ unsigned long long* ctr_u64(const Params& p, int slot) {
+  return reinterpret_cast<unsigned long long*>(p.ctr + slot * kCounterStride);
+}
+__device__ __forceinline__ int32_t load_relaxed(int32_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long load_relaxed(unsigned long long* a) {
+  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_acquire(uint32_t* a) {
+  return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_release(uint32_t* a, uint32_t v) {
+  __hip_atomic_store(a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_relaxed(int32_t* a, int32_t v) {
+  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int32_t fetch_add(int32_t* a, int32_t v) {
+  return __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long fetch_add(unsigned long long* a,
+                                                        unsigned long long v) {
+  return __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- wavefront-64 reductions (DPP row operations + lane reads) -----------------------------
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp(uint32_t x) {
+  return static_cast<uint32_t>(
+      __builtin_amdgcn_update_dpp(static_cast<int>(x), static_cast<int>(x), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
+  const uint32_t lo = dpp<CTRL>(static_cast<uint32_t>(x));
+  const uint32_t hi = dpp<CTRL>(static_cast<uint32_t>(x >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror. After
+// the four steps every lane of a 16-lane row holds the row's result.
+constexpr int kDppQuadSwap1 = 0xB1;
+constexpr int kDppQuadSwap2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+
+__device__ __forceinline__ int32_t wave_sum(int32_t x) {
+  uint32_t u = static_cast<uint32_t>(x);
+  u += dpp<kDppQuadSwap1>(u);
+  u += dpp<kDppQuadSwap2>(u);
+  u += dpp<kDppHalfMirror>(u);
+  u += dpp<kDppMirror>(u);
+  const uint32_t r = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), 0)) +
+                     static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), 16)) +
+                     static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), 32)) +
+                     static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), 48));
+  return static_cast<int32_t>(r);
+}
+
+__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
+  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), lane));
+  const uint32_t hi =
+      static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x >> 32), lane));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ __forceinline__ uint64_t wave_max(uint64_t x) {
+  x = umax64(x, dpp64<kDppQuadSwap1>(x));
+  x = umax64(x, dpp64<kDppQuadSwap2>(x));
+  x = umax64(x, dpp64<kDppHalfMirror>(x));
+  x = umax64(x, dpp64<kDppMirror>(x));
+  return umax64(umax64(readlane64(x, 0), readlane64(x, 16)),
+                umax64(readlane64(x, 32), readlane64(x, 48)));
+}
+
+__device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x) & 63; }
+__device__ __forceinline__ int wave_id() { return static_cast<int>(threadIdx.x) >> 6; }
+__device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll(static_cast<long long>(m)) - 1; }
+__device__ __forceinline__ int bcast(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
+
+// ---- per-workgroup LDS control block ------------------------------------------------------
+
+struct Ctrl {
+  int32_t flag_epoch;  // epoch of the last decide step that marked a vertex
+  int32_t status;      // broadcast of a result computed by thread 0
+  uint32_t slot;
+  uint32_t lap;
+  int32_t best;        // broadcast of the global best size (MVC)
+  int32_t stop;        // broadcast of the found / abort flags
+  int32_t err;         // broadcast: the input graph was rejected
+  int32_t pad;
+  uint64_t red_key[kMaxWaves];
+  int32_t red_sum[kMaxWaves];
+};
+
+// ---- node operations on the LDS degree array -------------------------------------------------
+// st[0..n) degrees (kSent = in cover), st[n] = s, st[n+1] = pending vertex (-1 = none).
+
+struct Node {
+  int32_t* st;
+  int n;
+  const int32_t* __restrict__ rp;
+  const int32_t* __restrict__ ci;
+};
+
+// Remove every marked vertex (paper §IV-B): each live unmarked neighbour of a marked vertex
+// loses one degree per marked neighbour, then marked vertices become kSent and s grows by
+// their number. Called right after a barrier that ends a decide step.
+__device__ void apply_marks(const Node& nd) {
+  const int lane = lane_id();
+  const int n = nd.n;
+  int32_t* st = nd.st;
+  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
+    const int v = base + lane;
+    const int32_t d = v < n ? st[v] : kSent;
+    uint64_t m = __builtin_amdgcn_ballot_w64(d >= 0 && (d & kFlag));
+    while (m) {
+      const int f = base + first_lane(m);
+      m &= m - 1;
+      const int beg = nd.rp[f], end = nd.rp[f + 1];
+      for (int j = beg + lane; j < end; j += 64) {
+        const int x = nd.ci[j];
+        const int32_t dx = st[x];
+        if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
+      }
+    }
+  }
+  __syncthreads();
+  int cnt = 0;
+  for (int v = threadIdx.x; v < n; v += blockDim.x) {
+    const int32_t d = st[v];
+    if (d >= 0 && (d & kFlag)) {
+      st[v] = kSent;
+      ++cnt;
+    }
+  }
+  cnt = wave_sum(cnt);
+  if (lane == 0 && cnt) atomicAdd(&st[n], cnt);
+  __syncthreads();
+}
+
+// Degree-one rule (§II-B): v with one live neighbour u puts u in the cover; of two adjacent
+// degree-one vertices only the smaller id is removed, and a shared neighbour once (§IV-D).
+__device__ void decide_degree_one(const Node& nd, Ctrl& c, int epoch) {
+  const int lane = lane_id();
+  const int n = nd.n;
+  int32_t* st = nd.st;
+  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
+    const int v = base + lane;
+    const int32_t d = v < n ? st[v] : kSent;
+    uint64_t m = __builtin_amdgcn_ballot_w64(d >= 0 && (d & kDegMask) == 1);
+    while (m) {
+      const int cv = base + first_lane(m);
+      m &= m - 1;
+      const int beg = nd.rp[cv], end = nd.rp[cv + 1];
+      int u = -1;
+      for (int j = beg; j < end; j += 64) {
+        const int x = j + lane < end ? nd.ci[j + lane] : -1;
+        const uint64_t live = __builtin_amdgcn_ballot_w64(x >= 0 && st[x] >= 0);
+        if (live) {
+          u = bcast(x, first_lane(live));
+          break;
+        }
+      }
+      if (u >= 0) {
+        const int32_t du = st[u] & kDegMask;
+        if ((du != 1 || u < cv) && lane == 0) {
+          atomicOr(&st[u], kFlag);
+          c.flag_epoch = epoch;
+        }
+      }
+    }
+  }
+}
+
+// Degree-two-triangle rule (§II-B): v with live neighbours u, w and uw an edge puts u and w in
+// the cover; among degree-two vertices of one triangle only the smallest id fires (§IV-D).
+__device__ void decide_triangle(const Node& nd, Ctrl& c, int epoch) {
+  const int lane = lane_id();
+  const int n = nd.n;
+  int32_t* st = nd.st;
+  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
+    const int v = base + lane;
+    const int32_t d = v < n ? st[v] : kSent;
+    uint64_t m = __builtin_amdgcn_ballot_w64(d >= 0 && (d & kDegMask) == 2);
+    while (m) {
+      const int cv = base + first_lane(m);
+      m &= m - 1;
+      const int beg = nd.rp[cv], end = nd.rp[cv + 1];
+      int a = -1, b = -1;
+      for (int j = beg; j < end && b < 0; j += 64) {
+        const int x = j + lane < end ? nd.ci[j + lane] : -1;
+        uint64_t live = __builtin_amdgcn_ballot_w64(x >= 0 && st[x] >= 0);
+        while (live && b < 0) {
+          const int y = bcast(x, first_lane(live));
+          live &= live - 1;
+          if (a < 0) a = y; else b = y;
+        }
+      }
+      if (b < 0) continue;  // cannot happen for a consistent degree array
+      // is b in row a? rows are sorted ascending; scan a's row 64 entries at a time
+      const int abeg = nd.rp[a], aend = nd.rp[a + 1];
+      bool adjacent = false;
+      for (int j = abeg; j < aend; j += 64) {
+        const int x = j + lane < aend ? nd.ci[j + lane] : 0x7FFFFFFF;
+        if (__builtin_amdgcn_ballot_w64(x == b)) {
+          adjacent = true;
+          break;
+        }
+        const int last = nd.ci[(j + 63 < aend ? j + 63 : aend - 1)];
+        if (last > b) break;
+      }
+      if (!adjacent) continue;
+      const int32_t da = st[a] & kDegMask, db = st[b] & kDegMask;
+      const bool blocked = (da == 2 && a < cv) || (db == 2 && b < cv);
+      if (!blocked && lane == 0) {
+        atomicOr(&st[a], kFlag);
+        atomicOr(&st[b], kFlag);
+        c.flag_epoch = epoch;
+      }
+    }
+  }
+}
+
+// High-degree rule (§II-B): a vertex whose degree exceeds r = bound - s is in every cover of
+// size <= bound (bound = best - 1 for MVC, k for PVC).
+__device__ void decide_high_degree(const Node& nd, Ctrl& c, int epoch, int64_t r) {
+  int32_t* st = nd.st;
+  for (int v = threadIdx.x; v < nd.n; v += blockDim.x) {
+    const int32_t d = st[v];
+    if (d >= 0 && static_cast<int64_t>(d & kDegMask) > r) {
+      st[v] = d | kFlag;
+      c.flag_epoch = epoch;
+    }
+  }
+}
+
+// The reduction rules until the graph stops changing (§II-B, §IV-D), or until s > bound.
+// Precondition: the node in LDS is consistent and visible to the whole workgroup.
+__device__ void reduce_node(const Node& nd, Ctrl& c, int64_t bound, int rules, int& epoch) {
+  const int n = nd.n;
+  int32_t* st = nd.st;
+  for (;;) {
+    const int32_t s0 = st[n];
+    if (s0 > bound) return;
+    if (rules & kRuleDeg1) {
+      ++epoch;
+      decide_degree_one(nd, c, epoch);
+      __syncthreads();
+      if (c.flag_epoch == epoch) {
+        apply_marks(nd);
+        if (st[n] > bound) return;
+      }
+    }
+    if (rules & kRuleTri) {
+      ++epoch;
+      decide_triangle(nd, c, epoch);
+      __syncthreads();
+      if (c.flag_epoch == epoch) {
+        apply_marks(nd);
+        if (st[n] > bound) return;
+      }
+    }
+    if (rules & kRuleHigh) {
+      ++epoch;
+      decide_high_degree(nd, c, epoch, bound - st[n]);
+      __syncthreads();
+      if (c.flag_epoch == epoch) apply_marks(nd);
+    }
+    if (st[n] == s0) return;
+  }
+}
+
+// One pass over the degree array: the sum of live degrees (= 2|E|) and the live vertex of
+// maximum degree, smallest id on ties (§IV-B). Results are the same in every thread.
+__device__ void max_degree_and_sum(const Node& nd, Ctrl& c, int& vmax, int& dmax,
+                                   int32_t& degsum) {
+  const int n = nd.n;
+  const int32_t* st = nd.st;
+  uint64_t key = 0;
+  int32_t sum = 0;
+  for (int v = threadIdx.x; v < n; v += blockDim.x) {
+    const int32_t d = st[v];
+    if (d >= 0) {
+      sum += d;
+      key = umax64(key, (static_cast<uint64_t>(static_cast<uint32_t>(d)) << 32) |
+                            static_cast<uint32_t>(~static_cast<uint32_t>(v)));
+    }
+  }
+  key = wave_max(key);
+  sum = wave_sum(sum);
+  if (lane_id() == 0) {
+    c.red_key[wave_id()] = key;
+    c.red_sum[wave_id()] = sum;
+  }
+  __syncthreads();
+  key = 0;
+  sum = 0;
+  const int waves = blockDim.x >> 6;
+  for (int w = 0; w < waves; ++w) {
+    key = umax64(key, c.red_key[w]);
+    sum += c.red_sum[w];
+  }
+  vmax = static_cast<int>(~static_cast<uint32_t>(key));
+  dmax = static_cast<int>(key >> 32);
+  degsum = sum;
+}
+
+// Mark every live neighbour of v (the "N(v) in the cover" child, §II-B) and remove them.
+__device__ void remove_neighbourhood(const Node& nd, int v) {
+  int32_t* st = nd.st;
+  const int lane = lane_id();
+  if (wave_id() == 0) {
+    const int beg = nd.rp[v], end = nd.rp[v + 1];
+    for (int j = beg + lane; j < end; j += 64) {
+      const int x = nd.ci[j];
+      if (st[x] >= 0) st[x] |= kFlag;  // distinct x per lane: plain read-modify-write
+    }
+  }
+  __syncthreads();
+  apply_marks(nd);
+}
+
+// Mark v alone (the "v in the cover" child, §II-B) and remove it.
+__device__ void remove_vertex(const Node& nd, int v) {
+  if (threadIdx.x == 0) nd.st[v] |= kFlag;
+  __syncthreads();
+  apply_marks(nd);
+}
+
+// Copy a node between LDS and device memory, 16 bytes per thread per step. The same thread
+// always handles the same words, so a node written to the workgroup's own stack is read back
+// by the threads that wrote it. `pending` replaces word n+1 on the way out.
+__device__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int stride, int n,
+                           int pending) {
+  const int4* s4 = reinterpret_cast<const int4*>(st);
+  int4* d4 = reinterpret_cast<int4*>(dst);
+  const int q = (n + 1) >> 2, r = (n + 1) & 3;
+  for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) {
+    int4 x = s4[i];
+    if (i == q) {
+      if (r == 0) x.x = pending;
+      else if (r == 1) x.y = pending;
+      else if (r == 2) x.z = pending;
+      else x.w = pending;
+    }
+    d4[i] = x;
+  }
+}
+
+__device__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stride) {
+  const int4* s4 = reinterpret_cast<const int4*>(src);
+  int4* d4 = reinterpret_cast<int4*>(st);
+  for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
+}
+
+__device__ __forceinline__ void backoff(int& spins) {
+  if (spins < 8) ++spins;
+  for (int i = 0; i < spins; ++i) __builtin_amdgcn_s_sleep(8);
+}
+
+// ---- global worklist -----------------------------------------------------------------------
+// A bounded ring of q_cap node slots (a power of two). Ticket t uses slot t % cap in lap
+// t / cap; seq[slot] = 2*lap means free for lap `lap`, 2*lap + 1 means filled in lap `lap`.
+// `count` is the number of entries producers have reserved and consumers have not: a
+// consumer only takes a ticket after lowering a positive count, so it never waits for a
+// node that will not come. A producer raises the outstanding-work counter before it
+// reserves, so that counter can read zero only when nothing is queued or held.
+
+// Thread 0 tries to reserve a slot for a donated node; returns 1 with c.slot/c.lap set, 0 if
+// the worklist is at its threshold, -1 if the search is being stopped.
+__device__ int enqueue_reserve(const Params& p, Ctrl& c) {
+  int32_t* count = ctr_i32(p, kQCount);
+  const int32_t seen = load_relaxed(count);
+  if (seen >= static_cast<int32_t>(p.q_threshold)) return 0;
+  fetch_add(ctr_i32(p, kWork), 1);
+  const int32_t before = fetch_add(count, 1);  // cannot exceed cap: threshold + num_wg <= cap
+  if (before + 1 > load_relaxed(ctr_i32(p, kQMaxCount))) atomicMax(ctr_i32(p, kQMaxCount), before + 1);
+  const unsigned long long t = fetch_add(ctr_u64(p, kQTail), 1ull);
+  const uint32_t slot = static_cast<uint32_t>(t) & (p.q_cap - 1);
+  const uint32_t lap = static_cast<uint32_t>(t / p.q_cap);
+  int spins = 0;
+  while (load_acquire(p.seq + slot) != 2u * lap) {
+    if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) return -1;
+    backoff(spins);
+  }
+  c.slot = slot;
+  c.lap = lap;
+  return 1;
+}
+
+// Whole workgroup: donate the node in LDS (with `pending` as its branch vertex). Returns true
+// if the worklist took it.
+__device__ bool try_enqueue(const Params& p, const Node& nd, Ctrl& c, int pending) {
+  if (threadIdx.x == 0) c.status = enqueue_reserve(p, c);
+  __syncthreads();
+  const int status = c.status;
+  if (status != 1) return false;  // at threshold, or stopping: keep the node locally
+  const uint32_t slot = c.slot, lap = c.lap;
+  node_store(p.payload + static_cast<size_t>(slot) * p.stride, nd.st, p.stride, nd.n, pending);
+  __threadfence();  // make this thread's part of the node visible at agent scope
+  __syncthreads();
+  if (threadIdx.x == 0) store_release(p.seq + slot, 2u * lap + 1u);
+  return true;
+}
+
+// Whole workgroup: take a node from the worklist into LDS. Returns 1 on success, 0 when the
+// whole search is finished, -1 when it is being stopped.
+__device__ int dequeue(const Params& p, const Node& nd, Ctrl& c) {
+  int spins = 0;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      int status = 2;  // nothing available yet: retry
+      int32_t* count = ctr_i32(p, kQCount);
+      if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) {
+        status = -1;
+      } else if (load_relaxed(count) > 0) {
+        if (fetch_add(count, -1) > 0) {
+          const unsigned long long h = fetch_add(ctr_u64(p, kQHead), 1ull);
+          const uint32_t slot = static_cast<uint32_t>(h) & (p.q_cap - 1);
+          const uint32_t lap = static_cast<uint32_t>(h / p.q_cap);
+          int wait = 0;
+          status = 1;
+          while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
+            if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) {
+              status = -1;
+              break;
+            }
+            backoff(wait);
+          }
+          c.slot = slot;
+          c.lap = lap;
+        } else {
+          fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
+        }
+      }
+      if (status == 2 && load_relaxed(ctr_i32(p, kWork)) == 0) status = 0;  // all done
+      if (status == 2) backoff(spins);
+      c.status = status;
+    }
+    __syncthreads();
+    const int status = c.status;
+    if (status == 1) {
+      const uint32_t slot = c.slot, lap = c.lap;
+      node_load(nd.st, p.payload + static_cast<size_t>(slot) * p.stride, p.stride);
+      __syncthreads();
+      if (threadIdx.x == 0) store_release(p.seq + slot, 2u * (lap + 1u));
+      return 1;
+    }
+    if (status != 2) return status;
+    __syncthreads();  // every thread has read c.status before thread 0 writes it again
+  }
+}
+
+// ---- kernels ---------------------------------------------------------------------------------
+
+// Zero the control lines, mark every worklist slot free, publish slot 0 (the root, written by
+// prepare_kernel) and the single outstanding sub-tree it stands for.
+__global__ void init_kernel(Params p, DevResult* res) {
+  for (int i = threadIdx.x; i < kNumCounters * kCounterStride; i += blockDim.x) p.ctr[i] = 0;
+  for (uint32_t i = threadIdx.x; i < p.q_cap; i += blockDim.x) p.seq[i] = (i == 0) ? 1u : 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *ctr_i32(p, kQCount) = 1;
+    *ctr_u64(p, kQHead) = 0;
+    *ctr_u64(p, kQTail) = 1;
+    *ctr_i32(p, kWork) = 1;
+    *ctr_u64(p, kBestKey) = ~0ull;
+    *ctr_i32(p, kErrRow) = 0x7FFFFFFF;
+    char* r = reinterpret_cast<char*>(res);
+    for (size_t i = 0; i < sizeof(DevResult); ++i) r[i] = 0;
+  }
+}
+
+// Check the CSR (simple undirected graph, §II-A) and write the root node -- the input's
+// degree array, s = 0, no pending vertex -- into worklist slot 0. Every read is bounds-checked
+// before it is made, so a malformed input cannot send a thread out of its arrays.
+__global__ void prepare_kernel(Params p) {
+  const int n = p.n;
+  int32_t* root = p.payload;
+  int32_t local_sum = 0;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < p.stride;
+       v += gridDim.x * blockDim.x) {
+    if (v >= n) {
+      root[v] = (v == n + 1) ? -1 : 0;
+      continue;
+    }
+    const int beg = p.rp[v], end = p.rp[v + 1];
+    bool bad = (v == 0 && beg != 0) || (v == n - 1 && end != p.nnz) || beg < 0 || end < beg ||
+               end > p.nnz;
+    if (!bad) {
+      int prev = -1;
+      for (int j = beg; j < end && !bad; ++j) {
+        const int u = p.ci[j];
+        if (u < 0 || u >= n || u == v || u <= prev) {
+          bad = true;
+          break;
+        }
+        prev = u;
+        // the reverse entry v must be in row u
+        const int ub = p.rp[u], ue = p.rp[u + 1];
+        if (ub < 0 || ue < ub || ue > p.nnz) {
+          bad = true;
+          break;
+        }
+        int lo = ub, hi = ue;
+        while (lo < hi) {
+          const int mid = lo + ((hi - lo) >> 1);
+          if (p.ci[mid] < v) lo = mid + 1; else hi = mid;
+        }
+        if (lo >= ue || p.ci[lo] != v) bad = true;
+      }
+    }
+    if (bad) atomicMin(ctr_i32(p, kErrRow), v);
+    const int32_t d = bad ? 0 : end - beg;
+    root[v] = d;
+    local_sum += d;
+  }
+  local_sum = wave_sum(local_sum);
+  if (lane_id() == 0 && local_sum) atomicAdd(ctr_i32(p, kEdges0), local_sum);
+}
+
+// Greedy approximation (§II-B, used as the initial best and the stack depth bound, §IV-E):
+// degree-one and degree-two-triangle rules, then a maximum-degree vertex into the cover, until
+// no edge is left. One workgroup. Its cover is the last cover buffer.
+__global__ void __launch_bounds__(1024) greedy_kernel(Params p, DevResult* res) {
+  extern __shared__ int4 lds4[];
+  __shared__ Ctrl c;
+  int32_t* st = reinterpret_cast<int32_t*>(lds4);
+  if (threadIdx.x == 0) {
+    const int32_t err_row = load_relaxed(ctr_i32(p, kErrRow));
+    res->err_row = err_row;
+    res->edges0 = load_relaxed(ctr_i32(p, kEdges0)) / 2;
+    res->greedy = 0;
+    c.err = err_row != 0x7FFFFFFF;
+    c.flag_epoch = -1;
+  }
+  __syncthreads();
+  if (c.err) return;
+  const Node nd{st, p.n, p.rp, p.ci};
+  node_load(st, p.payload, p.stride);  // the root written by prepare_kernel
+  __syncthreads();
+  int epoch = 0;
+  const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
+  for (;;) {
+    reduce_node(nd, c, unbounded, kRuleDeg1 | kRuleTri, epoch);
+    int vmax, dmax;
+    int32_t degsum;
+    max_degree_and_sum(nd, c, vmax, dmax, degsum);
+    if (degsum == 0) break;
+    remove_vertex(nd, vmax);
+  }
+  const int s = st[p.n];
+  uint8_t* cov = p.covers + static_cast<size_t>(p.greedy_slot) * p.cover_stride;
+  for (int v = threadIdx.x; v < p.n; v += blockDim.x) cov[v] = st[v] == kSent;
+  if (threadIdx.x == 0) {
+    *ctr_u64(p, kBestKey) =
+        (static_cast<unsigned long long>(s) << 32) | static_cast<uint32_t>(p.greedy_slot);
+    res->greedy = s;
+  }
+}
+
+// The hybrid traversal (§IV-A, Fig. 4; PVC differences in §IV-A, termination §IV-C).
+template <bool PVC>
+__global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
+  extern __shared__ int4 lds4[];
+  __shared__ Ctrl c;
+  int32_t* st = reinterpret_cast<int32_t*>(lds4);
+  const int n = p.n;
+  const int wg = blockIdx.x;
+  const int tid = threadIdx.x;
+  const Node nd{st, n, p.rp, p.ci};
+
+  if (tid == 0) {
+    c.err = load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF ||
+            load_relaxed(ctr_i32(p, kEdges0)) == 0;
+    c.flag_epoch = -1;
+  }
+  __syncthreads();
+  if (c.err) {
+    if (tid == 0) p.wg_stats[wg] = WgStats{0, 0, 0, 0, 0, 0, 0};
+    return;
+  }
+
+  int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * p.stride;
+  int sp = 0;             // entries on this workgroup's stack
+  bool have = false;      // a node is in LDS and still to be visited
+  bool holding = false;   // this workgroup holds a sub-tree taken from the worklist
+  int epoch = 0;
+  int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0;
+  int max_depth = 0;
+  int64_t budget_mark = 0;
+
+  for (;;) {
+    // node header: global flags and the current best, read once and broadcast
+    if (tid == 0) {
+      c.stop = load_relaxed(ctr_i32(p, kAbort)) | (PVC ? load_relaxed(ctr_i32(p, kFound)) : 0);
+      c.best = PVC ? 0 : static_cast<int32_t>(load_relaxed(ctr_u64(p, kBestKey)) >> 32);
+    }
+    __syncthreads();
+    if (c.stop) break;
+
+    if (!have) {
+      if (sp > 0) {
+        --sp;
+        node_load(st, stack + static_cast<size_t>(sp) * p.stride, p.stride);
+        ++pops;
+        __syncthreads();
+      } else {
+        if (holding) {
+          if (tid == 0) fetch_add(ctr_i32(p, kWork), -1);
+          holding = false;
+        }
+        const int got = dequeue(p, nd, c);
+        if (got != 1) break;
+        holding = true;
+        ++dequeues;
+      }
+      const int pending = st[n + 1];
+      if (pending >= 0) {
+        __syncthreads();  // every thread has read the pending vertex
+        if (tid == 0) st[n + 1] = -1;
+        remove_neighbourhood(nd, pending);
+      }
+      have = true;
+    }
+
+    ++nodes;
+    if (p.node_budget > 0 && nodes - budget_mark >= p.budget_chunk) {
+      if (tid == 0) {
+        const unsigned long long total =
+            fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
+        if (static_cast<int64_t>(total) + (nodes - budget_mark) >= p.node_budget)
+          store_relaxed(ctr_i32(p, kAbort), 1);
+      }
+      budget_mark = nodes;
+    }
+
+    const int64_t bound = PVC ? p.k : static_cast<int64_t>(c.best) - 1;
+    reduce_node(nd, c, bound, p.rules, epoch);
+
+    // stopping condition (§II-B): no cover of size <= bound below this node if r < 0 or
+    // |E| > r^2 (every remaining degree is <= r once the high-degree rule has run)
+    const int32_t s = st[n];
+    const int64_t r = bound - s;
+    if (r < 0) {
+      have = false;
+      continue;
+    }
+    int vmax, dmax;
+    int32_t degsum;
+    max_degree_and_sum(nd, c, vmax, dmax, degsum);
+    const int64_t edges = degsum / 2;
+    if ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > r * r) {
+      have = false;
+      continue;
+    }
+    if (edges == 0) {  // a vertex cover of size s
+      if (tid == 0) {
+        if (PVC) {
+          c.status = atomicCAS(ctr_i32(p, kFound), 0, wg + 1) == 0;
+        } else {
+          const unsigned long long key =
+              (static_cast<unsigned long long>(s) << 32) | static_cast<uint32_t>(wg);
+          c.status = atomicMin(ctr_u64(p, kBestKey), key) > key;
+        }
+      }
+      __syncthreads();
+      if (c.status) {
+        uint8_t* cov = p.covers + static_cast<size_t>(wg) * p.cover_stride;
+        for (int v = tid; v < n; v += blockDim.x) cov[v] = st[v] == kSent;
+      }
+      have = false;
+      continue;
+    }
+
+    // branch on v_max (§II-B): defer the N(v_max) child, continue with the v_max child
+    const bool donated = p.q_threshold > 0 && try_enqueue(p, nd, c, vmax);
+    if (donated) {
+      ++enqueues;
+    } else {
+      if (sp >= p.depth_cap) {  // cannot happen: the depth bound of §IV-E holds
+        if (tid == 0) {
+          atomicMax(ctr_i32(p, kError), 1);
+          store_relaxed(ctr_i32(p, kAbort), 1);
+        }
+        break;
+      }
+      node_store(stack + static_cast<size_t>(sp) * p.stride, st, p.stride, n, vmax);
+      ++sp;
+      ++pushes;
+      if (sp > max_depth) max_depth = sp;
+      __syncthreads();  // the copy has read the node before it changes below
+    }
+    remove_vertex(nd, vmax);
+  }
+
+  if (tid == 0) {
+    if (p.node_budget > 0 && nodes > budget_mark)
+      fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
+    p.wg_stats[wg] = WgStats{nodes, pushes, pops, enqueues, dequeues, max_depth, 0};
+  }
+}
+
+// Sum / max / min over a 256-thread workgroup through shared memory.
+template <typename Op>
+__device__ int64_t block_reduce_256(int64_t v, int64_t* buf, Op op) {
+  buf[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (static_cast<int>(threadIdx.x) < h) buf[threadIdx.x] = op(buf[threadIdx.x], buf[threadIdx.x + h]);
+    __syncthreads();
+  }
+  const int64_t r = buf[0];
+  __syncthreads();
+  return r;
+}
+
+// Pick the answer, copy its cover out, gather the statistics. One workgroup of 256.
+__global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_t* cover_out,
+                                                       DevResult* res) {
+  __shared__ int32_t src_sh;
+  __shared__ int64_t buf[256];
+  if (threadIdx.x == 0) {
+    const int32_t err_row = *ctr_i32(p, kErrRow);
+    const int32_t edges0 = *ctr_i32(p, kEdges0) / 2;
+    res->err_row = err_row;
+    res->edges0 = edges0;
+    res->aborted = *ctr_i32(p, kAbort);
+    res->error = *ctr_i32(p, kError);
+    res->q_max_count = *ctr_i32(p, kQMaxCount);
+    res->uncovered = 0;
+    res->cover_count = 0;
+    int32_t src = -2;  // -2: no cover (all zero), else index of the cover buffer
+    if (err_row == 0x7FFFFFFF) {
+      if (edges0 == 0) {
+        res->size = 0;
+        res->yes = 1;
+      } else if (pvc) {
+        const int32_t f = *ctr_i32(p, kFound);
+        res->yes = f != 0;
+        res->size = -1;
+        if (f) src = f - 1;
+      } else {
+        const unsigned long long key = *ctr_u64(p, kBestKey);
+        res->size = static_cast<int32_t>(key >> 32);
+        res->yes = 1;
+        src = static_cast<int32_t>(key & 0xFFFFFFFFull);
+      }
+    }
+    src_sh = src;
+  }
+  __syncthreads();
+  const int32_t src = src_sh;
+  if (cover_out) {
+    const uint8_t* from =
+        src >= 0 ? p.covers + static_cast<size_t>(src) * p.cover_stride : nullptr;
+    for (int v = threadIdx.x; v < p.n; v += blockDim.x) cover_out[v] = from ? from[v] : 0;
+  }
+  int64_t nodes = 0, pushes = 0, pops = 0, enq = 0, deq = 0, mx = 0, mn = INT64_MAX, depth = 0;
+  const int nwg = p.num_wg;  // every traversal workgroup writes its slot, also on early exit
+  for (int w = threadIdx.x; w < nwg; w += blockDim.x) {
+    const WgStats s = p.wg_stats[w];
+    nodes += s.nodes;
+    pushes += s.pushes;
+    pops += s.pops;
+    enq += s.enqueues;
+    deq += s.dequeues;
+    mx = s.nodes > mx ? s.nodes : mx;
+    mn = s.nodes < mn ? s.nodes : mn;
+    depth = s.max_depth > depth ? s.max_depth : depth;
+  }
+  auto add = [](int64_t a, int64_t b) { return a + b; };
+  auto hi = [](int64_t a, int64_t b) { return a > b ? a : b; };
+  auto lo = [](int64_t a, int64_t b) { return a < b ? a : b; };
+  nodes = block_reduce_256(nodes, buf, add);
+  pushes = block_reduce_256(pushes, buf, add);
+  pops = block_reduce_256(pops, buf, add);
+  enq = block_reduce_256(enq, buf, add);
+  deq = block_reduce_256(deq, buf, add);
+  mx = block_reduce_256(mx, buf, hi);
+  mn = block_reduce_256(mn, buf, lo);
+  depth = block_reduce_256(depth, buf, hi);
+  if (threadIdx.x == 0) {
+    res->nodes = nodes;
+    res->pushes = pushes;
+    res->pops = pops;
+    res->enqueues = enq;
+    res->dequeues = deq;
+    res->wg_nodes_max = mx;
+    res->wg_nodes_min = nwg ? mn : 0;
+    res->max_depth = static_cast<int32_t>(depth);
+  }
+}
+
+// Check a cover edge by edge and count its vertices.
+__global__ void verify_kernel(Params p, const uint8_t* cover, DevResult* res) {
+  if (*ctr_i32(p, kErrRow) != 0x7FFFFFFF) return;  // rejected input: nothing to check
+  int32_t bad = 0, ones = 0;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < p.n; v += gridDim.x * blockDim.x) {
+    if (cover[v]) {
+      ++ones;
+      continue;
+    }
+    for (int j = p.rp[v]; j < p.rp[v + 1]; ++j) bad += cover[p.ci[j]] == 0;
+  }
+  bad = wave_sum(bad);
+  ones = wave_sum(ones);
+  if (lane_id() == 0) {
+    if (bad) atomicAdd(&res->uncovered, bad);
+    if (ones) atomicAdd(&res->cover_count, ones);
+  }
+}
+
+// The reduction rules of one node, alone, on a degree array in device memory (one workgroup).
+__global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, int32_t* s,
+                                                      int64_t bound, DevResult* res) {
+  extern __shared__ int4 lds4[];
+  __shared__ Ctrl c;
+  int32_t* st = reinterpret_cast<int32_t*>(lds4);
+  if (threadIdx.x == 0) {
+    const int32_t err_row = load_relaxed(ctr_i32(p, kErrRow));
+    res->err_row = err_row;
+    c.err = err_row != 0x7FFFFFFF;
+  }
+  __syncthreads();
+  if (c.err) return;  // rejected input: leave the degree array alone
+  for (int v = threadIdx.x; v < p.stride; v += blockDim.x)
+    st[v] = v < p.n ? deg[v] : (v == p.n ? *s : (v == p.n + 1 ? -1 : 0));
+  if (threadIdx.x == 0) c.flag_epoch = -1;
+  __syncthreads();
+  const Node nd{st, p.n, p.rp, p.ci};
+  int epoch = 0;
+  reduce_node(nd, c, bound, p.rules, epoch);
+  for (int v = threadIdx.x; v < p.n; v += blockDim.x) deg[v] = st[v];
+  if (threadIdx.x == 0) *s = st[p.n];
+}
+
+// ---- launchers ---------------------------------------------------------------------------------
+
+hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream) {
+  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, stream, p, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_prepare(const Params& p, hipStream_t stream) {
+  const int threads = 256;
+  int blocks = (p.stride + threads - 1) / threads;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(prepare_kernel, dim3(blocks), dim3(threads), 0, stream, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_greedy(const Params& p, int32_t wg_size, DevResult* res, hipStream_t stream) {
+  const size_t lds = static_cast<size_t>(p.stride) * sizeof(int32_t);
+  hipLaunchKernelGGL(greedy_kernel, dim3(1), dim3(wg_size), lds, stream, p, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_traverse(bool pvc, const Params& p, int32_t wg_size, hipStream_t stream) {
+  const size_t lds = static_cast<size_t>(p.stride) * sizeof(int32_t);
+  Params args = p;
+  void* kargs[] = {&args};
+  const void* fn = pvc ? reinterpret_cast<const void*>(&traverse_kernel<true>)
+                       : reinterpret_cast<const void*>(&traverse_kernel<false>);
+  return hipLaunchCooperativeKernel(fn, dim3(p.num_wg), dim3(wg_size), kargs,
+                                    static_cast<unsigned int>(lds), stream);
+}
+
+hipError_t launch_finalize(bool pvc, const Params& p, uint8_t* cover_out, DevResult* res,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, stream, p, pvc ? 1 : 0, cover_out,
+                     res);
+  return hipGetLastError();
+}
+
+hipError_t launch_verify(const Params& p, const uint8_t* cover, DevResult* res,
+                         hipStream_t stream) {
+  const int threads = 256;
+  int blocks = (p.n + threads - 1) / threads;
+  if (blocks < 1) blocks = 1;
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(verify_kernel, dim3(blocks), dim3(threads), 0, stream, p, cover, res);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
+                         int64_t bound, DevResult* res, hipStream_t stream) {
+  const size_t lds = static_cast<size_t>(p.stride) * sizeof(int32_t);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(wg_size), lds, stream, p, deg, s, bound, res);
+  return hipGetLastError();
+}
+
+hipError_t traverse_occupancy(bool pvc, int32_t wg_size, size_t lds_bytes, int* blocks_per_cu) {
+  const void* fn = pvc ? reinterpret_cast<const void*>(&traverse_kernel<true>)
+                       : reinterpret_cast<const void*>(&traverse_kernel<false>);
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, wg_size, lds_bytes);
+}
+
+hipError_t set_lds_limit(size_t lds_bytes) {
+  const void* fns[] = {reinterpret_cast<const void*>(&traverse_kernel<true>),
+                       reinterpret_cast<const void*>(&traverse_kernel<false>),
+                       reinterpret_cast<const void*>(&greedy_kernel),
+                       reinterpret_cast<const void*>(&reduce_kernel)};
+  for (const void* fn : fns) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       static_cast<int>(lds_bytes));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace vc

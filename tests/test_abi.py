@@ -1,0 +1,85 @@
+"""The C-ABI library: it loads, exports every function include/vc.h declares, and its
+host-only entry points behave. No compute call is made here (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2204_10402_amd as vc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "vc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(vc_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return vc.load_library()
+
+
+def test_header_matches_binding():
+    assert declared_functions() == sorted(vc.EXPORTS)
+
+
+def test_every_declared_symbol_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_strerror_and_version(lib):
+    assert vc.version().count(".") == 2
+    for code, word in ((vc.OK, "ok"), (vc.ERR_INVALID_GRAPH, "graph"), (vc.ERR_BUDGET, "budget"),
+                       (vc.ERR_DEVICE, "device"), (vc.ERR_INTERNAL, "internal"),
+                       (vc.ERR_NO_MEMORY, "memory"), (vc.ERR_INVALID_ARG, "argument")):
+        assert word in lib.vc_strerror(code).decode().lower()
+    assert lib.vc_last_error(None).decode() == ""
+
+
+def test_null_arguments(lib):
+    assert lib.vc_create(None, 0, None) == vc.ERR_INVALID_ARG
+    assert lib.vc_destroy(None) == vc.OK
+    assert lib.vc_mvc(None, None, None, None, None, None) == vc.ERR_INVALID_ARG
+
+
+def test_struct_layouts_match_header():
+    # sizes implied by include/vc.h on LP64
+    from paper_2204_10402_amd import _binding as b
+    assert ctypes.sizeof(b._Graph) == 24
+    assert ctypes.sizeof(b._Options) == 48
+    assert ctypes.sizeof(b._Stats) == 7 * 8 + 8 * 4 + 3 * 8
+
+
+def test_no_gpu_means_device_error(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    ctx = ctypes.c_void_p()
+    assert lib.vc_create(ctypes.byref(ctx), 0, None) == vc.ERR_DEVICE
+    assert not ctx.value
+
+
+def test_binding_fails_loudly_without_library(tmp_path):
+    from paper_2204_10402_amd import _binding as b
+    saved = b._lib
+    b._lib = None
+    try:
+        with pytest.raises(ImportError):
+            b.load_library(str(tmp_path / "missing.so"))
+    finally:
+        b._lib = saved
+
+
+def test_product_package_does_not_use_oracle():
+    pkg = os.path.join(ROOT, "paper_2204_10402_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "vc_oracle" not in text and "liboracle" not in text, f

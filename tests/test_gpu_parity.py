@@ -1,0 +1,377 @@
+"""Parity of the HIP path (libvc.so, called through the C ABI) with the CPU oracle.
+
+The bar (integer work, exact): MVC size and PVC decision identical to the oracle on every
+instance; every returned cover verified edge by edge here as well as in the library; the
+greedy cover and the reduction-rule fixpoint identical to the oracle's, vertex by vertex;
+node counts identical where the tree does not depend on the schedule (one workgroup that
+never donates; PVC instances whose answer is no).
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import graphs as G
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def solver(torch_cuda):
+    import paper_2204_10402_amd as vc
+    s = vc.Solver(0)
+    yield s
+    s.close()
+
+
+def single_wg():
+    import paper_2204_10402_amd as vc
+    return vc.Options(num_wg=1, wl_threshold=-1)
+
+
+def check_cover(g, cover, size):
+    cover = np.asarray(cover)
+    assert cover.shape == (g.n,)
+    assert set(np.unique(cover).tolist()) <= {0, 1}
+    assert oracle.is_cover(g, cover)
+    assert int(cover.sum()) == size
+
+
+def golden():
+    with open(os.path.join(GOLDEN, "oracle_answers.json")) as f:
+        return json.load(f)["results"]
+
+
+# ---- small graphs: answers, covers and node counts ----------------------------------------
+
+@pytest.mark.parametrize("seed", range(40))
+def test_small_mvc_and_pvc(solver, oracle_lib, seed):
+    n = 5 + seed % 14
+    g = G.random_small(n, 20000 + seed) if seed % 2 else G.erdos_renyi(n, 0.3, 20000 + seed)
+    tau, _ = oracle.tau_by_definition(g)
+    r = solver.mvc(g)
+    assert r.size == tau
+    check_cover(g, r.cover, tau)
+    for k in (max(tau - 2, 0), tau - 1, tau, tau + 1):
+        if k < 0:
+            continue
+        p = solver.pvc(g, k)
+        assert p.yes == (k >= tau)
+        if p.yes:
+            check_cover(g, p.cover, p.size)
+            assert p.size <= k
+        else:
+            assert p.size == -1 and int(p.cover.sum()) == 0
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_single_workgroup_node_parity(solver, oracle_lib, seed):
+    """One workgroup that never donates visits the oracle's tree in the oracle's order."""
+    g = G.erdos_renyi(30 + 7 * seed, 0.12 + 0.01 * (seed % 5), 300 + seed)
+    o = oracle.mvc(g)
+    r = solver.mvc(g, single_wg())
+    assert (r.size, r.stats["nodes"], r.stats["greedy_size"]) == (o.size, o.nodes, o.greedy)
+    check_cover(g, r.cover, o.size)
+    for k in (o.size - 1, o.size):
+        op = oracle.pvc(g, k)
+        gp = solver.pvc(g, k, single_wg())
+        assert (gp.yes, gp.stats["nodes"]) == (op.yes, op.nodes)
+
+
+def test_c1_er60(solver, oracle_lib):
+    """MVC on G(60, 0.10), seed 0, plain method (one persistent launch, all workgroups)."""
+    g = G.erdos_renyi(60, 0.10, 0)
+    o = oracle.mvc(g)
+    r = solver.mvc(g)
+    assert r.size == o.size == 37
+    check_cover(g, r.cover, o.size)
+    assert r.stats["greedy_size"] == o.greedy
+    one = solver.mvc(g, single_wg())
+    assert one.stats["nodes"] == o.nodes
+
+
+@pytest.mark.parametrize("rules", [0x1, 0x2, 0x4, 0x8, 0x3])
+def test_ablation_flags(solver, oracle_lib, rules):
+    """Switching rules off leaves tau unchanged; single-workgroup node counts follow the
+    oracle with the same rules switched off."""
+    import paper_2204_10402_amd as vc
+    mask = oracle.ALL
+    if rules & vc.OPT_NO_DEGREE_ONE:
+        mask &= ~oracle.RULE_DEG1
+    if rules & vc.OPT_NO_TRIANGLE:
+        mask &= ~oracle.RULE_TRI
+    if rules & vc.OPT_NO_HIGH_DEGREE:
+        mask &= ~(oracle.RULE_HIGH | oracle.PRUNE_EDGES)
+    if rules & vc.OPT_NO_EDGE_PRUNE:
+        mask &= ~oracle.PRUNE_EDGES
+    for seed in range(4):
+        g = G.erdos_renyi(40, 0.12, 700 + seed)
+        o = oracle.mvc(g, rules=mask)
+        r = solver.mvc(g, vc.Options(num_wg=1, wl_threshold=-1, flags=rules))
+        assert (r.size, r.stats["nodes"]) == (o.size, o.nodes)
+        assert solver.mvc(g, vc.Options(flags=rules)).size == o.size
+
+
+# ---- reduction rules and greedy: vertex-by-vertex parity --------------------------------
+
+def random_consistent_state(g, rng, frac):
+    """A degree array of the graph with a random vertex set already in the cover."""
+    removed = rng.random(g.n) < frac
+    deg = np.zeros(g.n, np.int32)
+    for v in range(g.n):
+        if removed[v]:
+            deg[v] = -1
+        else:
+            nb = g.neighbors(v)
+            deg[v] = int(np.sum(~removed[nb]))
+    return deg, int(removed.sum())
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_reduce_fixpoint_parity(solver, oracle_lib, torch_cuda, seed):
+    torch = torch_cuda
+    rng = np.random.default_rng(900 + seed)
+    n = [12, 40, 63, 64, 65, 130, 200, 700][seed % 8]
+    g = G.random_small(n, 900 + seed) if n <= 40 else G.erdos_renyi(n, float(rng.uniform(0.02, 0.1)), seed)
+    deg, s = random_consistent_state(g, rng, float(rng.uniform(0.0, 0.4)))
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx.copy() if g.nnz else np.zeros(1, np.int32)).cuda()[:g.nnz]
+    for bound, flags in ((10**9, 0x4), (s + n // 3, 0), (s + 2, 0), (s, 0), (s - 1, 0),
+                         (s + n // 4, 0x1), (s + n // 4, 0x2)):
+        mask = oracle.ALL
+        if flags & 0x1:
+            mask &= ~oracle.RULE_DEG1
+        if flags & 0x2:
+            mask &= ~oracle.RULE_TRI
+        if flags & 0x4:
+            mask &= ~(oracle.RULE_HIGH | oracle.PRUNE_EDGES)
+        od, os_ = oracle.reduce(g, deg, s, bound, mask)
+        dd = torch.from_numpy(deg.copy()).cuda()
+        gs = solver.reduce_device(rp, ci, dd, s, bound, flags)
+        assert gs == os_, (bound, flags)
+        assert np.array_equal(dd.cpu().numpy(), od), (bound, flags)
+
+
+@pytest.mark.parametrize("n,p,seed", [(60, 0.1, 0), (150, 0.08, 1), (500, 0.02, 2),
+                                      (2000, 0.004, 3), (5000, 0.0016, 4)])
+def test_greedy_parity(solver, oracle_lib, torch_cuda, n, p, seed):
+    torch = torch_cuda
+    g = G.erdos_renyi(n, p, seed)
+    size, cover = oracle.greedy(g)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    out = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    assert solver.greedy_device(rp, ci, out) == size
+    assert np.array_equal(out.cpu().numpy(), cover)
+
+
+def test_greedy_planted_full_size(solver, oracle_lib, torch_cuda):
+    torch = torch_cuda
+    g = G.planted_cover(5000, 400, 40000, 0.75, 0)
+    size, cover = oracle.greedy(g)
+    out = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+    got = solver.greedy_device(torch.from_numpy(g.row_ptr).cuda(),
+                               torch.from_numpy(g.col_idx).cuda(), out)
+    assert got == size and np.array_equal(out.cpu().numpy(), cover)
+
+
+# ---- full-size workloads -----------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_planted_pvc_full_size(solver, oracle_lib, torch_cuda, seed):
+    """PVC on planted-cover graphs, n = 5000, |C| = 400, 40,000 edges, k = 400 and 399, through
+    the device-resident entry point the benchmark times."""
+    torch = torch_cuda
+    ans = {(r["seed"], r["k"]): r for r in golden() if r["workload"] == "pvc_planted"}
+    g = G.planted_cover(5000, 400, 40000, 0.75, seed)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    for k in (400, 399):
+        cover = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+        r = solver.pvc_device(rp, ci, k, cover)
+        want = ans[(seed, k)]
+        assert r.yes == want["yes"]
+        # the answer is "no" at 399: the tree cannot depend on the schedule
+        if not want["yes"]:
+            assert r.stats["nodes"] == want["nodes"]
+            assert int(cover.sum().item()) == 0
+        else:
+            check_cover(g, cover.cpu().numpy(), r.size)
+            assert r.size <= k
+        h = solver.pvc(g, k)
+        assert h.yes == want["yes"]
+
+
+@pytest.mark.parametrize("workload,seed", [("mvc_reg120", s) for s in range(8)] +
+                         [("mvc_er150", s) for s in range(8)])
+def test_hard_mvc_full_size(solver, oracle_lib, workload, seed):
+    """MVC on random 5-regular n=120 and G(150, 0.08), seeds 0-7: deep imbalanced trees that
+    exercise donation and termination. tau must equal the oracle's (stored by
+    tests/golden/make_oracle_answers.py)."""
+    want = {(r["workload"], r["seed"]): r for r in golden()}[(workload, seed)]
+    g = G.random_regular(120, 5, seed) if workload == "mvc_reg120" else G.erdos_renyi(150, 0.08, seed)
+    r = solver.mvc(g)
+    assert r.size == want["size"]
+    assert r.stats["greedy_size"] == want["greedy"]
+    check_cover(g, r.cover, want["size"])
+    assert r.stats["nodes"] > 0
+
+
+def test_hard_pvc_no_node_parity(solver, oracle_lib):
+    """PVC k = tau - 1 (no instance): every workgroup schedule visits the same tree."""
+    want = {(r["workload"], r["seed"]): r for r in golden()}[("mvc_reg120", 3)]
+    g = G.random_regular(120, 5, 3)
+    o = oracle.pvc(g, want["size"] - 1)
+    r = solver.pvc(g, want["size"] - 1)
+    assert not o.yes and not r.yes
+    assert r.stats["nodes"] == o.nodes
+    y = solver.pvc(g, want["size"])
+    assert y.yes and y.size <= want["size"]
+    check_cover(g, y.cover, y.size)
+
+
+# ---- edge cases -----------------------------------------------------------------------------
+
+def test_edge_cases(solver, oracle_lib):
+    import paper_2204_10402_amd as vc
+    e = G.empty(7)
+    assert solver.mvc(e).size == 0 and int(solver.mvc(e).cover.sum()) == 0
+    p = solver.pvc(e, 0)
+    assert p.yes and p.size == 0
+    assert solver.mvc(G.empty(0)).size == 0
+    one = G.path(2)
+    assert solver.mvc(one).size == 1
+    assert not solver.pvc(one, 0).yes and solver.pvc(one, 1).yes
+    k5 = G.complete(5)
+    r = solver.pvc(k5, 10**6)  # k far above n
+    assert r.yes and r.size <= 5
+    check_cover(k5, r.cover, r.size)
+    with pytest.raises(vc.VCError) as ei:
+        solver.pvc(k5, -1)
+    assert ei.value.code == vc.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("n", [63, 64, 65, 127, 128, 129, 191, 1000, 1025])
+def test_ragged_sizes(solver, oracle_lib, n):
+    g = G.disjoint_union(G.cycle(n // 2 + 3), G.path(n - n // 2 - 3)) if n > 8 else G.path(n)
+    want = (n // 2 + 3 + 1) // 2 + (n - n // 2 - 3) // 2
+    r = solver.mvc(g)
+    assert r.size == want
+    check_cover(g, r.cover, want)
+
+
+def test_large_n_near_lds_limit(solver, oracle_lib):
+    """n = 29,034: the node takes ~113 KB of LDS (one workgroup per CU)."""
+    g = G.disjoint_union(G.star(29000), G.petersen(), G.cycle(11), G.complete(12))
+    want = 1 + 6 + 6 + 11
+    r = solver.mvc(g)
+    assert r.size == want
+    check_cover(g, r.cover, want)
+    p = solver.pvc(g, want - 1)
+    assert not p.yes
+
+
+def invalid_graphs():
+    good = G.path(5)
+    rp, ci = good.row_ptr.copy(), good.col_idx.copy()
+    cases = []
+    a = ci.copy(); a[0] = 9          # out of range
+    cases.append(("out_of_range", rp.copy(), a, 0))
+    a = ci.copy(); a[0] = 0          # self-loop in row 0
+    cases.append(("self_loop", rp.copy(), a, 0))
+    # asymmetric: drop the reverse entry of edge 3-4 by rewriting row 4 to point at 2
+    a = ci.copy(); a[-1] = 2
+    cases.append(("asymmetric", rp.copy(), a, 3))
+    # unsorted row 1 (entries 0,2 -> 2,0)
+    a = ci.copy(); a[1], a[2] = a[2], a[1]
+    cases.append(("unsorted", rp.copy(), a, 0))  # row 0's reverse lookup fails first
+    # duplicate neighbour: row 2 holds 1,3 -> 1,1
+    a = ci.copy(); a[4] = a[3]
+    cases.append(("duplicate", rp.copy(), a, 2))
+    r = rp.copy(); r[2] = 7          # row_ptr not monotone
+    cases.append(("row_ptr", r, ci.copy(), 1))
+    return cases
+
+
+@pytest.mark.parametrize("name,rp,ci,first_row", invalid_graphs(), ids=lambda x: x if isinstance(x, str) else "")
+def test_invalid_graph_rejected(solver, name, rp, ci, first_row):
+    import paper_2204_10402_amd as vc
+
+    class Raw:
+        pass
+    g = Raw()
+    g.n, g.row_ptr, g.col_idx = 5, rp, ci
+    for call in (lambda: solver.mvc(g), lambda: solver.pvc(g, 3)):
+        with pytest.raises(vc.VCError) as ei:
+            call()
+        assert ei.value.code == vc.ERR_INVALID_GRAPH
+        assert f"row {first_row} " in str(ei.value)
+    # the context still works afterwards
+    assert solver.mvc(G.path(5)).size == 2
+
+
+def test_node_budget(solver, oracle_lib):
+    import paper_2204_10402_amd as vc
+    g = G.random_regular(120, 5, 0)
+    with pytest.raises(vc.VCError) as ei:
+        solver.mvc(g, vc.Options(node_budget=20000))
+    assert ei.value.code == vc.ERR_BUDGET
+    assert solver.mvc(G.cycle(9)).size == 5
+
+
+def test_bad_options(solver):
+    import paper_2204_10402_amd as vc
+    for o in (vc.Options(wg_size=100), vc.Options(num_wg=-1), vc.Options(flags=0x100),
+              vc.Options(wl_threshold=-2)):
+        with pytest.raises(vc.VCError) as ei:
+            solver.mvc(G.path(4), o)
+        assert ei.value.code == vc.ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("opts", [dict(wl_capacity=1), dict(wl_capacity=1, wl_threshold=1),
+                                  dict(num_wg=3), dict(num_wg=7, wl_threshold=1),
+                                  dict(wg_size=128), dict(wg_size=256, num_wg=64),
+                                  dict(wg_size=1024)])
+def test_launch_knobs_keep_answers(solver, oracle_lib, opts):
+    import paper_2204_10402_amd as vc
+    g = G.erdos_renyi(90, 0.1, 5)
+    o = oracle.mvc(g)
+    r = solver.mvc(g, vc.Options(**opts))
+    assert r.size == o.size
+    check_cover(g, r.cover, o.size)
+    pn = solver.pvc(g, o.size - 1, vc.Options(**opts))
+    assert not pn.yes and pn.stats["nodes"] == oracle.pvc(g, o.size - 1).nodes
+
+
+def test_device_entry_matches_host_entry(solver, oracle_lib, torch_cuda):
+    torch = torch_cuda
+    g = G.erdos_renyi(100, 0.08, 11)
+    o = oracle.mvc(g)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    cov = torch.zeros(g.n, dtype=torch.uint8, device="cuda")
+    r = solver.mvc_device(rp, ci, cov)
+    assert r.size == o.size
+    check_cover(g, cov.cpu().numpy(), o.size)
+
+
+def test_context_reuse_across_sizes(solver, oracle_lib):
+    for g in (G.erdos_renyi(200, 0.02, 1), G.path(7), G.erdos_renyi(1500, 0.0015, 2),
+              G.complete(12), G.erdos_renyi(70, 0.1, 3), G.planted_cover(3000, 300, 6000, 0.75, 5),
+              G.erdos_renyi(120, 0.05, 4)):
+        o = oracle.mvc(g)
+        r = solver.mvc(g)
+        assert r.size == o.size
+        check_cover(g, r.cover, o.size)
