@@ -53,6 +53,8 @@ extern "C" {
 #define VC_OPT_NO_HIGH_DEGREE 0x4 /* ablation: switch off the high-degree rule (this also
                                      switches off the |E| > r^2 prune, which relies on it) */
 #define VC_OPT_NO_EDGE_PRUNE 0x8  /* ablation: switch off the |E| > r^2 prune */
+#define VC_OPT_PROFILE 0x10       /* run the instrumented traversal kernel, which charges shader
+                                     clock cycles to activities (vc_stats.cycles) */
 
 typedef struct vc_ctx vc_ctx;
 
@@ -99,6 +101,12 @@ typedef struct {
   double kernel_ms;       /* traversal kernel time (HIP events on the context stream) */
   double greedy_ms;       /* greedy kernel time (MVC) */
   double total_ms;        /* wall clock of the whole call */
+  /* With VC_OPT_PROFILE, shader-clock cycles summed over the workgroups (paper §V-D):
+   * [0] taking nodes (stack pops, worklist dequeues, waiting for work), [1] reduction rules,
+   * [2] branching (max-degree pass, stopping test, removing v_max or N(v_max)),
+   * [3] deferring children (stack pushes, worklist enqueues), [4] other (flags, bound,
+   * recording covers), [5] the whole kernel. Zero without VC_OPT_PROFILE. */
+  int64_t cycles[6];
 } vc_stats;
 
 /* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to run on, or NULL

@@ -25,6 +25,8 @@ OPT_NO_DEGREE_ONE = 0x1
 OPT_NO_TRIANGLE = 0x2
 OPT_NO_HIGH_DEGREE = 0x4
 OPT_NO_EDGE_PRUNE = 0x8
+OPT_PROFILE = 0x10
+ACTIVITIES = ("acquire", "reduce", "branch", "donate", "other", "total")
 
 # Every function include/vc.h declares.
 EXPORTS = (
@@ -55,7 +57,8 @@ class _Stats(ctypes.Structure):
                 ("num_wg", ctypes.c_int32), ("wl_capacity", ctypes.c_int32),
                 ("wl_threshold", ctypes.c_int32), ("depth_cap", ctypes.c_int32),
                 ("n", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
-                ("greedy_ms", ctypes.c_double), ("total_ms", ctypes.c_double)]
+                ("greedy_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("cycles", ctypes.c_int64 * 6)]
 
 
 @dataclass
@@ -126,7 +129,9 @@ def load_library(path: str = LIB_PATH):
 
 
 def _stats_dict(s: _Stats) -> dict:
-    return {name: getattr(s, name) for name, _ in _Stats._fields_}
+    d = {name: getattr(s, name) for name, _ in _Stats._fields_ if name != "cycles"}
+    d["cycles"] = dict(zip(ACTIVITIES, list(s.cycles)))
+    return d
 
 
 def _host_graph(g):

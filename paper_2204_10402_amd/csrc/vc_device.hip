@@ -156,28 +156,132 @@ struct Node {
   const int32_t* __restrict__ ci;
 };
 
+// ---- wavefront building blocks ---------------------------------------------------------------
+
+// Inclusive prefix sum over the 64 lanes: DPP row shifts inside each 16-lane row, then row
+// broadcasts (row_bcast:15 to rows 1 and 3, row_bcast:31 to rows 2 and 3).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t dpp_or_zero(int32_t x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xF, false);
+}
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
+  x += dpp_or_zero<0x111, 0xF>(x);  // row_shr:1
+  x += dpp_or_zero<0x112, 0xF>(x);  // row_shr:2
+  x += dpp_or_zero<0x114, 0xF>(x);  // row_shr:4
+  x += dpp_or_zero<0x118, 0xF>(x);  // row_shr:8
+  x += dpp_or_zero<0x142, 0xA>(x);  // row_bcast:15
+  x += dpp_or_zero<0x143, 0xC>(x);  // row_bcast:31
+  return x;
+}
+
+__device__ __forceinline__ int shfl(int x, int src_lane) {
+  return __builtin_amdgcn_ds_bpermute(src_lane << 2, x);
+}
+
+// Index of the k-th (from 0) set bit of m; m must have more than k set bits.
+__device__ __forceinline__ int kth_set_bit(uint64_t m, int k) {
+  int pos = 0;
+  uint32_t w = static_cast<uint32_t>(m);
+  int c = __popc(w);
+  if (k >= c) {
+    k -= c;
+    pos = 32;
+    w = static_cast<uint32_t>(m >> 32);
+  }
+#pragma unroll
+  for (int half = 16; half > 0; half >>= 1) {
+    c = __popc(w & ((1u << half) - 1u));
+    if (k >= c) {
+      k -= c;
+      pos += half;
+      w >>= half;
+    }
+  }
+  return pos;
+}
+
+// Walk the CSR rows [beg, end) held by the lanes of a wavefront (empty where beg >= end) as one
+// list, 64 consecutive entries per step, so rows of any length keep every lane busy and
+// neighbouring lanes read neighbouring entries. fn(j, tag) runs for entry j, with `tag` the
+// value the row's owner lane passed in. Eight steps are issued together to keep several loads
+// in flight. All cross-lane moves happen in uniform control flow.
+template <typename Fn>
+__device__ __forceinline__ void wave_expand_rows(int beg, int end, int tag, Fn fn) {
+  const int lane = lane_id();
+  const int len = end > beg ? end - beg : 0;
+  const int incl = wave_incl_scan(len);
+  const int excl = incl - len;
+  const int total = __builtin_amdgcn_readlane(incl, 63);
+  constexpr int kUnroll = 8;
+  for (int t0 = 0; t0 < total; t0 += 64 * kUnroll) {
+    int js[kUnroll], tags[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      js[u] = -1;
+      if (t0 + u * 64 < total) {  // uniform: only as many steps as the rows need
+        const int t = t0 + u * 64 + lane;
+        int i = 0;  // largest lane with excl <= t: the owner, whose row is not empty
+#pragma unroll
+        for (int step = 32; step > 0; step >>= 1) {
+          const int probe = shfl(excl, i + step);
+          i += probe <= t ? step : 0;
+        }
+        const int ob = shfl(beg, i);
+        const int oe = shfl(excl, i);
+        tags[u] = shfl(tag, i);
+        if (t < total) js[u] = ob + (t - oe);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      if (js[u] >= 0) fn(js[u], tags[u]);
+  }
+}
+
+// Collect the vertices of this wavefront's 64-vertex chunks that satisfy pred(v, d) into
+// batches of up to 64, one candidate per lane, and hand each batch to process(cand, count)
+// (lanes < count hold a candidate). Whole wavefront, uniform control flow.
+template <typename Pred, typename Proc>
+__device__ __forceinline__ void for_each_batch(const int32_t* st, int n, Pred pred, Proc process) {
+  const int lane = lane_id();
+  int held = -1;
+  int count = 0;
+  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
+    const int v = base + lane;
+    const int32_t d = v < n ? st[v] : kSent;
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(v < n && pred(v, d));
+    if (!mask) continue;
+    const int cnt = __popcll(mask);
+    if (count + cnt > 64) {
+      process(held, count);
+      held = -1;
+      count = 0;
+    }
+    const int k = lane - count;
+    const bool take = k >= 0 && k < cnt;
+    const int got = shfl(v, take ? kth_set_bit(mask, k) : lane);
+    if (take) held = got;
+    count += cnt;
+  }
+  if (count) process(held, count);
+}
+
 // Remove every marked vertex (paper §IV-B): each live unmarked neighbour of a marked vertex
 // loses one degree per marked neighbour, then marked vertices become kSent and s grows by
 // their number. Called right after a barrier that ends a decide step.
 __device__ void apply_marks(const Node& nd) {
-  const int lane = lane_id();
   const int n = nd.n;
   int32_t* st = nd.st;
-  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
-    const int v = base + lane;
-    const int32_t d = v < n ? st[v] : kSent;
-    uint64_t m = __builtin_amdgcn_ballot_w64(d >= 0 && (d & kFlag));
-    while (m) {
-      const int f = base + first_lane(m);
-      m &= m - 1;
-      const int beg = nd.rp[f], end = nd.rp[f + 1];
-      for (int j = beg + lane; j < end; j += 64) {
-        const int x = nd.ci[j];
-        const int32_t dx = st[x];
-        if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
-      }
-    }
-  }
+  for_each_batch(st, n, [](int, int32_t d) { return d >= 0 && (d & kFlag); },
+                 [&](int f, int count) {
+                   const bool mine = lane_id() < count;
+                   wave_expand_rows(mine ? nd.rp[f] : 0, mine ? nd.rp[f + 1] : 0, f,
+                                    [&](int j, int) {
+                                      const int x = nd.ci[j];
+                                      const int32_t dx = st[x];
+                                      if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
+                                    });
+                 });
   __syncthreads();
   int cnt = 0;
   for (int v = threadIdx.x; v < n; v += blockDim.x) {
@@ -188,91 +292,120 @@ __device__ void apply_marks(const Node& nd) {
     }
   }
   cnt = wave_sum(cnt);
-  if (lane == 0 && cnt) atomicAdd(&st[n], cnt);
+  if (lane_id() == 0 && cnt) atomicAdd(&st[n], cnt);
   __syncthreads();
 }
 
 // Degree-one rule (§II-B): v with one live neighbour u puts u in the cover; of two adjacent
 // degree-one vertices only the smaller id is removed, and a shared neighbour once (§IV-D).
+// The rows of all degree-one vertices are walked together; the one live entry of a row names
+// u, and the lane that reads it makes the decision for that row's owner.
 __device__ void decide_degree_one(const Node& nd, Ctrl& c, int epoch) {
-  const int lane = lane_id();
-  const int n = nd.n;
   int32_t* st = nd.st;
-  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
-    const int v = base + lane;
-    const int32_t d = v < n ? st[v] : kSent;
-    uint64_t m = __builtin_amdgcn_ballot_w64(d >= 0 && (d & kDegMask) == 1);
-    while (m) {
-      const int cv = base + first_lane(m);
-      m &= m - 1;
-      const int beg = nd.rp[cv], end = nd.rp[cv + 1];
-      int u = -1;
-      for (int j = beg; j < end; j += 64) {
-        const int x = j + lane < end ? nd.ci[j + lane] : -1;
-        const uint64_t live = __builtin_amdgcn_ballot_w64(x >= 0 && st[x] >= 0);
-        if (live) {
-          u = bcast(x, first_lane(live));
-          break;
-        }
-      }
-      if (u >= 0) {
-        const int32_t du = st[u] & kDegMask;
-        if ((du != 1 || u < cv) && lane == 0) {
-          atomicOr(&st[u], kFlag);
-          c.flag_epoch = epoch;
-        }
-      }
+  for_each_batch(st, nd.n, [](int, int32_t d) { return d >= 0 && (d & kDegMask) == 1; },
+                 [&](int cv, int count) {
+                   const bool mine = lane_id() < count;
+                   wave_expand_rows(mine ? nd.rp[cv] : 0, mine ? nd.rp[cv + 1] : 0, cv,
+                                    [&](int j, int v) {
+                                      const int u = nd.ci[j];
+                                      const int32_t du = st[u];
+                                      if (du < 0) return;  // not the live neighbour of v
+                                      if ((du & kDegMask) != 1 || u < v) {
+                                        atomicOr(&st[u], kFlag);
+                                        c.flag_epoch = epoch;
+                                      }
+                                    });
+                 });
+}
+
+// Is `key` in the sorted CSR segment ci[lo, hi)? An 8-ary search: each round reads seven
+// evenly spaced entries at once and keeps the part that can hold the key, so a row of 125
+// entries takes three rounds of independent loads instead of seven dependent ones.
+__device__ __forceinline__ bool row_contains(const int32_t* __restrict__ ci, int lo, int hi,
+                                             int key) {
+  while (hi - lo > 8) {
+    const int step = (hi - lo + 7) >> 3;
+    int probe[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      const int at = lo + (i + 1) * step;
+      probe[i] = at < hi ? ci[at] : 0x7FFFFFFF;
     }
+    int below = 0;  // probes that are <= key
+#pragma unroll
+    for (int i = 0; i < 7; ++i) below += probe[i] <= key;
+    const int nlo = lo + below * step;
+    const int nhi = nlo + step < hi ? nlo + step : hi;
+    lo = nlo;
+    hi = nhi;
   }
+  bool hit = false;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) hit |= lo + i < hi && ci[lo + i] == key;
+  return hit;
 }
 
 // Degree-two-triangle rule (§II-B): v with live neighbours u, w and uw an edge puts u and w in
 // the cover; among degree-two vertices of one triangle only the smallest id fires (§IV-D).
+// Each lane takes one degree-two vertex: it finds the two live neighbours in its own row (rows
+// longer than kLaneRow are searched by the whole wavefront), then searches the shorter of the
+// two neighbours' rows for the other.
 __device__ void decide_triangle(const Node& nd, Ctrl& c, int epoch) {
-  const int lane = lane_id();
-  const int n = nd.n;
+  constexpr int kLaneRow = 32;
   int32_t* st = nd.st;
-  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
-    const int v = base + lane;
-    const int32_t d = v < n ? st[v] : kSent;
-    uint64_t m = __builtin_amdgcn_ballot_w64(d >= 0 && (d & kDegMask) == 2);
-    while (m) {
-      const int cv = base + first_lane(m);
-      m &= m - 1;
-      const int beg = nd.rp[cv], end = nd.rp[cv + 1];
-      int a = -1, b = -1;
-      for (int j = beg; j < end && b < 0; j += 64) {
-        const int x = j + lane < end ? nd.ci[j + lane] : -1;
-        uint64_t live = __builtin_amdgcn_ballot_w64(x >= 0 && st[x] >= 0);
-        while (live && b < 0) {
-          const int y = bcast(x, first_lane(live));
-          live &= live - 1;
-          if (a < 0) a = y; else b = y;
-        }
-      }
-      if (b < 0) continue;  // cannot happen for a consistent degree array
-      // is b in row a? rows are sorted ascending; scan a's row 64 entries at a time
-      const int abeg = nd.rp[a], aend = nd.rp[a + 1];
-      bool adjacent = false;
-      for (int j = abeg; j < aend; j += 64) {
-        const int x = j + lane < aend ? nd.ci[j + lane] : 0x7FFFFFFF;
-        if (__builtin_amdgcn_ballot_w64(x == b)) {
-          adjacent = true;
-          break;
-        }
-        const int last = nd.ci[(j + 63 < aend ? j + 63 : aend - 1)];
-        if (last > b) break;
-      }
-      if (!adjacent) continue;
-      const int32_t da = st[a] & kDegMask, db = st[b] & kDegMask;
-      const bool blocked = (da == 2 && a < cv) || (db == 2 && b < cv);
-      if (!blocked && lane == 0) {
-        atomicOr(&st[a], kFlag);
-        atomicOr(&st[b], kFlag);
-        c.flag_epoch = epoch;
-      }
-    }
-  }
+  const int lane = lane_id();
+  for_each_batch(st, nd.n, [](int, int32_t d) { return d >= 0 && (d & kDegMask) == 2; },
+                 [&](int cv, int count) {
+                   const bool mine = lane < count;
+                   const int beg = mine ? nd.rp[cv] : 0, end = mine ? nd.rp[cv + 1] : 0;
+                   int a = -1, b = -1;
+                   if (mine && end - beg <= kLaneRow) {
+                     for (int j = beg; j < end && b < 0; j += 8) {
+                       int x[8];
+#pragma unroll
+                       for (int u = 0; u < 8; ++u) x[u] = j + u < end ? nd.ci[j + u] : -1;
+#pragma unroll
+                       for (int u = 0; u < 8; ++u) {
+                         if (x[u] >= 0 && b < 0 && st[x[u]] >= 0) {
+                           if (a < 0) a = x[u]; else b = x[u];
+                         }
+                       }
+                     }
+                   }
+                   // long rows: the whole wavefront scans one row at a time
+                   uint64_t longs = __builtin_amdgcn_ballot_w64(mine && end - beg > kLaneRow);
+                   while (longs) {
+                     const int owner = first_lane(longs);
+                     longs &= longs - 1;
+                     const int rb = __builtin_amdgcn_readlane(beg, owner);
+                     const int re = __builtin_amdgcn_readlane(end, owner);
+                     int fa = -1, fb = -1;
+                     for (int j = rb; j < re && fb < 0; j += 64) {
+                       const int x = j + lane < re ? nd.ci[j + lane] : -1;
+                       uint64_t live = __builtin_amdgcn_ballot_w64(x >= 0 && st[x] >= 0);
+                       while (live && fb < 0) {
+                         const int y = bcast(x, first_lane(live));
+                         live &= live - 1;
+                         if (fa < 0) fa = y; else fb = y;
+                       }
+                     }
+                     if (lane == owner) {
+                       a = fa;
+                       b = fb;
+                     }
+                   }
+                   if (b < 0) return;  // no candidate in this lane
+                   // is b in row a? search the shorter of the two sorted rows
+                   const int ab = nd.rp[a], ae = nd.rp[a + 1];
+                   const int bb = nd.rp[b], be = nd.rp[b + 1];
+                   const bool in_a = ae - ab <= be - bb;
+                   if (!row_contains(nd.ci, in_a ? ab : bb, in_a ? ae : be, in_a ? b : a)) return;
+                   const int32_t da = st[a] & kDegMask, db = st[b] & kDegMask;
+                   if ((da == 2 && a < cv) || (db == 2 && b < cv)) return;
+                   atomicOr(&st[a], kFlag);
+                   atomicOr(&st[b], kFlag);
+                   c.flag_epoch = epoch;
+                 });
 }
 
 // High-degree rule (§II-B): a vertex whose degree exceeds r = bound - s is in every cover of
@@ -458,14 +591,17 @@ __device__ bool try_enqueue(const Params& p, const Node& nd, Ctrl& c, int pendin
 }
 
 // Whole workgroup: take a node from the worklist into LDS. Returns 1 on success, 0 when the
-// whole search is finished, -1 when it is being stopped.
+// whole search is finished, -1 when it is being stopped. An idle workgroup polls the entry
+// count (and, while the list is empty, the outstanding-work counter) with exponential
+// back-off, and looks at the stop flags every fourth poll.
 __device__ int dequeue(const Params& p, const Node& nd, Ctrl& c) {
-  int spins = 0;
+  int polls = 0;
   for (;;) {
     if (threadIdx.x == 0) {
       int status = 2;  // nothing available yet: retry
       int32_t* count = ctr_i32(p, kQCount);
-      if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) {
+      if ((polls & 3) == 0 &&
+          (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound)))) {
         status = -1;
       } else if (load_relaxed(count) > 0) {
         if (fetch_add(count, -1) > 0) {
@@ -486,9 +622,14 @@ __device__ int dequeue(const Params& p, const Node& nd, Ctrl& c) {
         } else {
           fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
         }
+      } else if (load_relaxed(ctr_i32(p, kWork)) == 0) {
+        status = 0;  // nothing queued and nothing held: the search is over
       }
-      if (status == 2 && load_relaxed(ctr_i32(p, kWork)) == 0) status = 0;  // all done
-      if (status == 2) backoff(spins);
+      if (status == 2) {
+        const int units = 1 << (polls < 5 ? polls : 5);
+        for (int i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(16);
+        ++polls;
+      }
       c.status = status;
     }
     __syncthreads();
@@ -522,52 +663,67 @@ __global__ void init_kernel(Params p, DevResult* res) {
     *ctr_i32(p, kErrRow) = 0x7FFFFFFF;
     char* r = reinterpret_cast<char*>(res);
     for (size_t i = 0; i < sizeof(DevResult); ++i) r[i] = 0;
+    res->wg_nodes_min = INT64_MAX;
   }
 }
 
+// The CSR row holding entry i: the largest v in [0, n) with rp[v] <= i. Every probe stays in
+// rp[0..n), whatever rp holds, so a malformed row_ptr cannot send the search out of bounds.
+__device__ __forceinline__ int owner_row(const int32_t* __restrict__ rp, int n, int i) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo + 1) >> 1);
+    if (rp[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Check the CSR (simple undirected graph, §II-A) and write the root node -- the input's
-// degree array, s = 0, no pending vertex -- into worklist slot 0. Every read is bounds-checked
-// before it is made, so a malformed input cannot send a thread out of its arrays.
+// degree array, s = 0, no pending vertex -- into worklist slot 0. Index i < stride checks row
+// i's bounds and writes its degree; index i < nnz checks entry i: in range, not a self-loop,
+// larger than the entry before it in its row, and present in reverse. Every read is
+// bounds-checked before it is made, so a malformed input cannot send a thread out of its
+// arrays. The smallest offending row is recorded.
 __global__ void prepare_kernel(Params p) {
-  const int n = p.n;
+  const int n = p.n, nnz = p.nnz;
   int32_t* root = p.payload;
   int32_t local_sum = 0;
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < p.stride;
-       v += gridDim.x * blockDim.x) {
-    if (v >= n) {
-      root[v] = (v == n + 1) ? -1 : 0;
-      continue;
-    }
-    const int beg = p.rp[v], end = p.rp[v + 1];
-    bool bad = (v == 0 && beg != 0) || (v == n - 1 && end != p.nnz) || beg < 0 || end < beg ||
-               end > p.nnz;
-    if (!bad) {
-      int prev = -1;
-      for (int j = beg; j < end && !bad; ++j) {
-        const int u = p.ci[j];
-        if (u < 0 || u >= n || u == v || u <= prev) {
-          bad = true;
-          break;
-        }
-        prev = u;
-        // the reverse entry v must be in row u
-        const int ub = p.rp[u], ue = p.rp[u + 1];
-        if (ub < 0 || ue < ub || ue > p.nnz) {
-          bad = true;
-          break;
-        }
-        int lo = ub, hi = ue;
-        while (lo < hi) {
-          const int mid = lo + ((hi - lo) >> 1);
-          if (p.ci[mid] < v) lo = mid + 1; else hi = mid;
-        }
-        if (lo >= ue || p.ci[lo] != v) bad = true;
+  const int total = p.stride > nnz ? p.stride : nnz;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+    if (i < p.stride) {
+      if (i >= n) {
+        root[i] = (i == n + 1) ? -1 : 0;
+      } else {
+        const int beg = p.rp[i], end = p.rp[i + 1];
+        const bool bad = (i == 0 && beg != 0) || (i == n - 1 && end != nnz) || beg < 0 ||
+                         end < beg || end > nnz;
+        if (bad) atomicMin(ctr_i32(p, kErrRow), i);
+        const int32_t d = bad ? 0 : end - beg;
+        root[i] = d;
+        local_sum += d;
       }
     }
-    if (bad) atomicMin(ctr_i32(p, kErrRow), v);
-    const int32_t d = bad ? 0 : end - beg;
-    root[v] = d;
-    local_sum += d;
+    if (i < nnz) {
+      const int v = owner_row(p.rp, n, i);
+      const int beg = p.rp[v], end = p.rp[v + 1];
+      if (beg <= i && i < end && beg >= 0 && end <= nnz) {  // otherwise row bounds are bad
+        const int u = p.ci[i];
+        bool bad = u < 0 || u >= n || u == v || (i > beg && p.ci[i - 1] >= u);
+        if (!bad) {
+          const int ub = p.rp[u], ue = p.rp[u + 1];
+          bad = ub < 0 || ue < ub || ue > nnz;
+          if (!bad) {
+            int lo = ub, hi = ue;
+            while (lo < hi) {
+              const int mid = lo + ((hi - lo) >> 1);
+              if (p.ci[mid] < v) lo = mid + 1; else hi = mid;
+            }
+            bad = lo >= ue || p.ci[lo] != v;
+          }
+        }
+        if (bad) atomicMin(ctr_i32(p, kErrRow), v);
+      }
+    }
   }
   local_sum = wave_sum(local_sum);
   if (lane_id() == 0 && local_sum) atomicAdd(ctr_i32(p, kEdges0), local_sum);
@@ -613,8 +769,29 @@ __global__ void __launch_bounds__(1024) greedy_kernel(Params p, DevResult* res) 
   }
 }
 
+// Per-workgroup activity clock of the instrumented kernel (paper §V-D, Fig. 6): shader-clock
+// cycles are charged to the activity that just ended. Compiled out when PROF is false.
+template <bool PROF>
+struct ActivityClock {
+  uint64_t cycles[kNumActivities] = {};
+  uint64_t mark = 0, start = 0;
+  __device__ void begin() {
+    if (PROF) start = mark = clock64();
+  }
+  __device__ void charge(int activity) {
+    if (PROF) {
+      const uint64_t now = clock64();
+      cycles[activity] += now - mark;
+      mark = now;
+    }
+  }
+  __device__ void end() {
+    if (PROF) cycles[kActTotal] = clock64() - start;
+  }
+};
+
 // The hybrid traversal (§IV-A, Fig. 4; PVC differences in §IV-A, termination §IV-C).
-template <bool PVC>
+template <bool PVC, bool PROF>
 __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
@@ -631,9 +808,11 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   }
   __syncthreads();
   if (c.err) {
-    if (tid == 0) p.wg_stats[wg] = WgStats{0, 0, 0, 0, 0, 0, 0};
+    if (tid == 0) p.wg_stats[wg] = WgStats{};
     return;
   }
+  ActivityClock<PROF> clk;
+  clk.begin();
 
   int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * p.stride;
   int sp = 0;             // entries on this workgroup's stack
@@ -651,6 +830,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       c.best = PVC ? 0 : static_cast<int32_t>(load_relaxed(ctr_u64(p, kBestKey)) >> 32);
     }
     __syncthreads();
+    clk.charge(kActOther);
     if (c.stop) break;
 
     if (!have) {
@@ -665,16 +845,19 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
           holding = false;
         }
         const int got = dequeue(p, nd, c);
+        clk.charge(kActAcquire);
         if (got != 1) break;
         holding = true;
         ++dequeues;
       }
+      clk.charge(kActAcquire);
       const int pending = st[n + 1];
       if (pending >= 0) {
         __syncthreads();  // every thread has read the pending vertex
         if (tid == 0) st[n + 1] = -1;
         remove_neighbourhood(nd, pending);
       }
+      clk.charge(kActBranch);
       have = true;
     }
 
@@ -690,7 +873,9 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     }
 
     const int64_t bound = PVC ? p.k : static_cast<int64_t>(c.best) - 1;
+    clk.charge(kActOther);
     reduce_node(nd, c, bound, p.rules, epoch);
+    clk.charge(kActReduce);
 
     // stopping condition (§II-B): no cover of size <= bound below this node if r < 0 or
     // |E| > r^2 (every remaining degree is <= r once the high-degree rule has run)
@@ -703,6 +888,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     int vmax, dmax;
     int32_t degsum;
     max_degree_and_sum(nd, c, vmax, dmax, degsum);
+    clk.charge(kActBranch);
     const int64_t edges = degsum / 2;
     if ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > r * r) {
       have = false;
@@ -723,6 +909,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         uint8_t* cov = p.covers + static_cast<size_t>(wg) * p.cover_stride;
         for (int v = tid; v < n; v += blockDim.x) cov[v] = st[v] == kSent;
       }
+      clk.charge(kActOther);
       have = false;
       continue;
     }
@@ -745,13 +932,24 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       if (sp > max_depth) max_depth = sp;
       __syncthreads();  // the copy has read the node before it changes below
     }
+    clk.charge(kActDonate);
     remove_vertex(nd, vmax);
+    clk.charge(kActBranch);
   }
+  clk.end();
 
   if (tid == 0) {
     if (p.node_budget > 0 && nodes > budget_mark)
       fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
-    p.wg_stats[wg] = WgStats{nodes, pushes, pops, enqueues, dequeues, max_depth, 0};
+    WgStats w{};
+    w.nodes = nodes;
+    w.pushes = pushes;
+    w.pops = pops;
+    w.enqueues = enqueues;
+    w.dequeues = dequeues;
+    w.max_depth = max_depth;
+    for (int a = 0; a < kNumActivities; ++a) w.cycles[a] = static_cast<int64_t>(clk.cycles[a]);
+    p.wg_stats[wg] = w;
   }
 }
 
@@ -769,50 +967,62 @@ __device__ int64_t block_reduce_256(int64_t v, int64_t* buf, Op op) {
   return r;
 }
 
-// Pick the answer, copy its cover out, gather the statistics. One workgroup of 256.
+// Index of the cover buffer holding the answer: >= 0, or -2 for "no cover" (rejected input,
+// edgeless graph, PVC no).
+__device__ __forceinline__ int32_t answer_buffer(const Params& p, int pvc) {
+  if (*ctr_i32(p, kErrRow) != 0x7FFFFFFF || *ctr_i32(p, kEdges0) == 0) return -2;
+  if (pvc) {
+    const int32_t f = *ctr_i32(p, kFound);
+    return f ? f - 1 : -2;
+  }
+  return static_cast<int32_t>(*ctr_u64(p, kBestKey) & 0xFFFFFFFFull);
+}
+
+// After the traversal (256-thread blocks, any grid): pick the answer, copy its cover out, check
+// the cover edge by edge (one thread per CSR entry) and count its vertices, and gather the
+// per-workgroup statistics.
 __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_t* cover_out,
                                                        DevResult* res) {
-  __shared__ int32_t src_sh;
   __shared__ int64_t buf[256];
-  if (threadIdx.x == 0) {
-    const int32_t err_row = *ctr_i32(p, kErrRow);
+  const int32_t src = answer_buffer(p, pvc);
+  const bool valid = *ctr_i32(p, kErrRow) == 0x7FFFFFFF;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int32_t edges0 = *ctr_i32(p, kEdges0) / 2;
-    res->err_row = err_row;
+    res->err_row = *ctr_i32(p, kErrRow);
     res->edges0 = edges0;
     res->aborted = *ctr_i32(p, kAbort);
     res->error = *ctr_i32(p, kError);
     res->q_max_count = *ctr_i32(p, kQMaxCount);
-    res->uncovered = 0;
-    res->cover_count = 0;
-    int32_t src = -2;  // -2: no cover (all zero), else index of the cover buffer
-    if (err_row == 0x7FFFFFFF) {
-      if (edges0 == 0) {
-        res->size = 0;
-        res->yes = 1;
-      } else if (pvc) {
-        const int32_t f = *ctr_i32(p, kFound);
-        res->yes = f != 0;
-        res->size = -1;
-        if (f) src = f - 1;
-      } else {
-        const unsigned long long key = *ctr_u64(p, kBestKey);
-        res->size = static_cast<int32_t>(key >> 32);
-        res->yes = 1;
-        src = static_cast<int32_t>(key & 0xFFFFFFFFull);
+    if (valid && edges0 == 0) {
+      res->size = 0;
+      res->yes = 1;
+    } else if (valid && pvc) {
+      res->size = -1;
+      res->yes = src >= 0;
+    } else if (valid) {
+      res->size = static_cast<int32_t>(*ctr_u64(p, kBestKey) >> 32);
+      res->yes = 1;
+    }
+  }
+  const uint8_t* from = src >= 0 ? p.covers + static_cast<size_t>(src) * p.cover_stride : nullptr;
+  int32_t bad = 0, ones = 0;
+  if (valid) {
+    const int total = p.n > p.nnz ? p.n : p.nnz;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
+      if (i < p.n) {
+        const uint8_t c = from ? from[i] : 0;
+        if (cover_out) cover_out[i] = c;
+        ones += c != 0;
+      }
+      if (i < p.nnz && from) {
+        const int v = owner_row(p.rp, p.n, i);
+        bad += from[v] == 0 && from[p.ci[i]] == 0;
       }
     }
-    src_sh = src;
-  }
-  __syncthreads();
-  const int32_t src = src_sh;
-  if (cover_out) {
-    const uint8_t* from =
-        src >= 0 ? p.covers + static_cast<size_t>(src) * p.cover_stride : nullptr;
-    for (int v = threadIdx.x; v < p.n; v += blockDim.x) cover_out[v] = from ? from[v] : 0;
   }
   int64_t nodes = 0, pushes = 0, pops = 0, enq = 0, deq = 0, mx = 0, mn = INT64_MAX, depth = 0;
-  const int nwg = p.num_wg;  // every traversal workgroup writes its slot, also on early exit
-  for (int w = threadIdx.x; w < nwg; w += blockDim.x) {
+  int64_t cyc[kNumActivities] = {};
+  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < p.num_wg; w += gridDim.x * blockDim.x) {
     const WgStats s = p.wg_stats[w];
     nodes += s.nodes;
     pushes += s.pushes;
@@ -822,10 +1032,13 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
     mx = s.nodes > mx ? s.nodes : mx;
     mn = s.nodes < mn ? s.nodes : mn;
     depth = s.max_depth > depth ? s.max_depth : depth;
+    for (int a = 0; a < kNumActivities; ++a) cyc[a] += s.cycles[a];
   }
-  auto add = [](int64_t a, int64_t b) { return a + b; };
-  auto hi = [](int64_t a, int64_t b) { return a > b ? a : b; };
-  auto lo = [](int64_t a, int64_t b) { return a < b ? a : b; };
+  auto add = [](int64_t x, int64_t y) { return x + y; };
+  auto hi = [](int64_t x, int64_t y) { return x > y ? x : y; };
+  auto lo = [](int64_t x, int64_t y) { return x < y ? x : y; };
+  bad = static_cast<int32_t>(block_reduce_256(bad, buf, add));
+  ones = static_cast<int32_t>(block_reduce_256(ones, buf, add));
   nodes = block_reduce_256(nodes, buf, add);
   pushes = block_reduce_256(pushes, buf, add);
   pops = block_reduce_256(pops, buf, add);
@@ -834,34 +1047,21 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
   mx = block_reduce_256(mx, buf, hi);
   mn = block_reduce_256(mn, buf, lo);
   depth = block_reduce_256(depth, buf, hi);
+  for (int a = 0; a < kNumActivities; ++a) cyc[a] = block_reduce_256(cyc[a], buf, add);
   if (threadIdx.x == 0) {
-    res->nodes = nodes;
-    res->pushes = pushes;
-    res->pops = pops;
-    res->enqueues = enq;
-    res->dequeues = deq;
-    res->wg_nodes_max = mx;
-    res->wg_nodes_min = nwg ? mn : 0;
-    res->max_depth = static_cast<int32_t>(depth);
-  }
-}
-
-// Check a cover edge by edge and count its vertices.
-__global__ void verify_kernel(Params p, const uint8_t* cover, DevResult* res) {
-  if (*ctr_i32(p, kErrRow) != 0x7FFFFFFF) return;  // rejected input: nothing to check
-  int32_t bad = 0, ones = 0;
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < p.n; v += gridDim.x * blockDim.x) {
-    if (cover[v]) {
-      ++ones;
-      continue;
-    }
-    for (int j = p.rp[v]; j < p.rp[v + 1]; ++j) bad += cover[p.ci[j]] == 0;
-  }
-  bad = wave_sum(bad);
-  ones = wave_sum(ones);
-  if (lane_id() == 0) {
+    using ull = unsigned long long;
     if (bad) atomicAdd(&res->uncovered, bad);
     if (ones) atomicAdd(&res->cover_count, ones);
+    if (nodes) atomicAdd(reinterpret_cast<ull*>(&res->nodes), static_cast<ull>(nodes));
+    if (pushes) atomicAdd(reinterpret_cast<ull*>(&res->pushes), static_cast<ull>(pushes));
+    if (pops) atomicAdd(reinterpret_cast<ull*>(&res->pops), static_cast<ull>(pops));
+    if (enq) atomicAdd(reinterpret_cast<ull*>(&res->enqueues), static_cast<ull>(enq));
+    if (deq) atomicAdd(reinterpret_cast<ull*>(&res->dequeues), static_cast<ull>(deq));
+    atomicMax(reinterpret_cast<ull*>(&res->wg_nodes_max), static_cast<ull>(mx));
+    atomicMin(reinterpret_cast<ull*>(&res->wg_nodes_min), static_cast<ull>(mn));
+    atomicMax(&res->max_depth, static_cast<int32_t>(depth));
+    for (int a = 0; a < kNumActivities; ++a)
+      if (cyc[a]) atomicAdd(reinterpret_cast<ull*>(&res->cycles[a]), static_cast<ull>(cyc[a]));
   }
 }
 
@@ -898,7 +1098,8 @@ hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream) {
 
 hipError_t launch_prepare(const Params& p, hipStream_t stream) {
   const int threads = 256;
-  int blocks = (p.stride + threads - 1) / threads;
+  const int items = p.stride > p.nnz ? p.stride : p.nnz;
+  int blocks = (items + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(prepare_kernel, dim3(blocks), dim3(threads), 0, stream, p);
   return hipGetLastError();
@@ -910,30 +1111,33 @@ hipError_t launch_greedy(const Params& p, int32_t wg_size, DevResult* res, hipSt
   return hipGetLastError();
 }
 
-hipError_t launch_traverse(bool pvc, const Params& p, int32_t wg_size, hipStream_t stream) {
+static const void* traverse_fn(bool pvc, bool prof) {
+  if (pvc) return prof ? reinterpret_cast<const void*>(&traverse_kernel<true, true>)
+                       : reinterpret_cast<const void*>(&traverse_kernel<true, false>);
+  return prof ? reinterpret_cast<const void*>(&traverse_kernel<false, true>)
+              : reinterpret_cast<const void*>(&traverse_kernel<false, false>);
+}
+
+hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size,
+                           hipStream_t stream) {
   const size_t lds = static_cast<size_t>(p.stride) * sizeof(int32_t);
   Params args = p;
   void* kargs[] = {&args};
-  const void* fn = pvc ? reinterpret_cast<const void*>(&traverse_kernel<true>)
-                       : reinterpret_cast<const void*>(&traverse_kernel<false>);
+  const void* fn = traverse_fn(pvc, prof);
   return hipLaunchCooperativeKernel(fn, dim3(p.num_wg), dim3(wg_size), kargs,
                                     static_cast<unsigned int>(lds), stream);
 }
 
 hipError_t launch_finalize(bool pvc, const Params& p, uint8_t* cover_out, DevResult* res,
                            hipStream_t stream) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(256), 0, stream, p, pvc ? 1 : 0, cover_out,
-                     res);
-  return hipGetLastError();
-}
-
-hipError_t launch_verify(const Params& p, const uint8_t* cover, DevResult* res,
-                         hipStream_t stream) {
   const int threads = 256;
-  int blocks = (p.n + threads - 1) / threads;
+  int items = p.n > p.nnz ? p.n : p.nnz;
+  if (p.num_wg > items) items = p.num_wg;
+  int blocks = (items + threads - 1) / threads;
   if (blocks < 1) blocks = 1;
-  if (blocks > 2048) blocks = 2048;
-  hipLaunchKernelGGL(verify_kernel, dim3(blocks), dim3(threads), 0, stream, p, cover, res);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks), dim3(threads), 0, stream, p, pvc ? 1 : 0,
+                     cover_out, res);
   return hipGetLastError();
 }
 
@@ -944,15 +1148,15 @@ hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t
   return hipGetLastError();
 }
 
-hipError_t traverse_occupancy(bool pvc, int32_t wg_size, size_t lds_bytes, int* blocks_per_cu) {
-  const void* fn = pvc ? reinterpret_cast<const void*>(&traverse_kernel<true>)
-                       : reinterpret_cast<const void*>(&traverse_kernel<false>);
+hipError_t traverse_occupancy(bool pvc, bool prof, int32_t wg_size, size_t lds_bytes,
+                              int* blocks_per_cu) {
+  const void* fn = traverse_fn(pvc, prof);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, wg_size, lds_bytes);
 }
 
 hipError_t set_lds_limit(size_t lds_bytes) {
-  const void* fns[] = {reinterpret_cast<const void*>(&traverse_kernel<true>),
-                       reinterpret_cast<const void*>(&traverse_kernel<false>),
+  const void* fns[] = {traverse_fn(true, false), traverse_fn(false, false),
+                       traverse_fn(true, true), traverse_fn(false, true),
                        reinterpret_cast<const void*>(&greedy_kernel),
                        reinterpret_cast<const void*>(&reduce_kernel)};
   for (const void* fn : fns) {

@@ -104,7 +104,7 @@ int check_options(vc_ctx* ctx, const vc_options* o) {
   if (o->num_wg < 0 || o->wl_capacity < 0 || o->wl_threshold < -1 || o->node_budget < 0)
     return fail(ctx, VC_ERR_INVALID_ARG, "negative option value");
   const int32_t known = VC_OPT_NO_DEGREE_ONE | VC_OPT_NO_TRIANGLE | VC_OPT_NO_HIGH_DEGREE |
-                        VC_OPT_NO_EDGE_PRUNE;
+                        VC_OPT_NO_EDGE_PRUNE | VC_OPT_PROFILE;
   if (o->flags & ~known) return fail(ctx, VC_ERR_INVALID_ARG, "unknown option flag");
   return VC_OK;
 }
@@ -129,10 +129,11 @@ struct Plan {
   size_t lds = 0;
 };
 
-// Workgroup size and count (paper §IV-E, adapted): the smallest power-of-two workgroup that
-// reaches the highest number of resident threads per CU, given the LDS the node needs; as
-// many workgroups as can be resident at once (all must be, since they wait on each other).
+// Workgroup size and count (paper §IV-E, adapted): a power-of-two workgroup of about n/4
+// threads; as many workgroups as can be resident at once (all must be, since they wait on
+// each other), fewer if their stacks do not fit in device memory.
 int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl) {
+  const bool prof = o && (o->flags & VC_OPT_PROFILE);
   pl.stride = static_cast<int32_t>(round_up(static_cast<int64_t>(n) + 2, 64));
   pl.cover_stride = static_cast<int32_t>(round_up(std::max<int64_t>(n, 1), 256));
   pl.lds = static_cast<size_t>(pl.stride) * sizeof(int32_t);
@@ -146,22 +147,18 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl)
   }
   const int cus = ctx->prop.multiProcessorCount;
   int best_ws = 0, best_occ = 0;
-  long best_threads = -1;
   if (o && o->wg_size) {
     best_ws = o->wg_size;
-    VC_HIP(ctx, vc::traverse_occupancy(pvc, best_ws, pl.lds, &best_occ));
+    VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, best_ws, pl.lds, &best_occ));
   } else {
-    const int upper = static_cast<int>(std::min<int64_t>(1024, round_up(std::max(n, 1), 64)));
-    for (int ws = 64; ws <= upper; ws *= 2) {
-      int occ = 0;
-      VC_HIP(ctx, vc::traverse_occupancy(pvc, ws, pl.lds, &occ));
-      const long threads = static_cast<long>(occ) * ws;
-      if (threads > best_threads) {
-        best_threads = threads;
-        best_ws = ws;
-        best_occ = occ;
-      }
-    }
+    // The paper's rule (§IV-E) admits any power of two between the size that fills the CU and
+    // min(1024, n). A node's passes are chains of dependent LDS and L2 accesses, so the time
+    // per node falls with more wavefronts per node: take about n/4 threads (four vertices per
+    // thread per pass), as a power of two in [64, 1024].
+    int ws = 64;
+    while (ws < 1024 && ws * 2 <= std::max(n, 1) / 4) ws *= 2;
+    best_ws = ws;
+    VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, best_ws, pl.lds, &best_occ));
   }
   if (best_occ < 1)
     return fail(ctx, VC_ERR_INVALID_ARG, "traversal kernel cannot be resident at this size");
@@ -290,11 +287,10 @@ int run_search(vc_ctx* ctx, const vc_graph* g, bool pvc, int64_t k, const vc_opt
   p.num_wg = pl.num_wg;
 
   VC_HIP(ctx, hipEventRecord(ctx->ev[0], s));
-  VC_HIP(ctx, vc::launch_traverse(pvc, p, pl.wg_size, s));
+  VC_HIP(ctx, vc::launch_traverse(pvc, o && (o->flags & VC_OPT_PROFILE), p, pl.wg_size, s));
   VC_HIP(ctx, hipEventRecord(ctx->ev[1], s));
   uint8_t* cover_dst = cover_dev ? cover_dev : static_cast<uint8_t*>(ctx->cover_tmp.ptr);
   VC_HIP(ctx, vc::launch_finalize(pvc, p, cover_dst, dres, s));
-  VC_HIP(ctx, vc::launch_verify(p, cover_dst, dres, s));
   VC_HIP(ctx, hipMemcpyAsync(&res, dres, sizeof res, hipMemcpyDeviceToHost, s));
   if (cover_host && n > 0)
     VC_HIP(ctx, hipMemcpyAsync(cover_host, cover_dst, static_cast<size_t>(n),
@@ -341,6 +337,7 @@ int run_search(vc_ctx* ctx, const vc_graph* g, bool pvc, int64_t k, const vc_opt
     stats->depth_cap = depth_cap;
     stats->n = n;
     stats->kernel_ms = kernel_ms;
+    for (int a = 0; a < vc::kNumActivities; ++a) stats->cycles[a] = res.cycles[a];
     stats->greedy_ms = greedy_ms;
     stats->total_ms = ms_since(t0);
   }

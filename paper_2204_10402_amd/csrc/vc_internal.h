@@ -35,6 +35,17 @@ enum CounterSlot : int {
 };
 constexpr int kCounterStride = 32;  // int32 words per control line (128 bytes)
 
+// Activities of the instrumented traversal (paper §V-D, Fig. 6).
+enum Activity : int {
+  kActAcquire = 0,  // taking a node: stack pops, worklist dequeues and the wait for work
+  kActReduce = 1,   // the reduction rules
+  kActBranch = 2,   // max-degree pass and stopping test, removing v_max or N(v_max)
+  kActDonate = 3,   // deferring a child: stack pushes and worklist enqueues
+  kActOther = 4,    // flags, bound, budget, recording solutions
+  kActTotal = 5,    // the whole kernel, per workgroup
+  kNumActivities = 6,
+};
+
 struct WgStats {
   int64_t nodes;
   int64_t pushes;
@@ -43,6 +54,7 @@ struct WgStats {
   int64_t dequeues;
   int32_t max_depth;
   int32_t pad;
+  int64_t cycles[kNumActivities];
 };
 
 // Everything a search kernel needs; passed by value.
@@ -70,7 +82,7 @@ struct Params {
   int32_t greedy_slot;  // cover buffer index of the greedy's cover
 };
 
-// Result block written by the finalize/verify kernels and copied to the host once.
+// Result block written by the finalize kernel and copied to the host once.
 struct DevResult {
   int32_t err_row;
   int32_t edges0;
@@ -91,6 +103,7 @@ struct DevResult {
   int64_t pops;
   int64_t enqueues;
   int64_t dequeues;
+  int64_t cycles[kNumActivities];
 };
 
 // Kernel launchers (vc_device.hip). All run on `stream`; they return the HIP status of the
@@ -98,16 +111,16 @@ struct DevResult {
 hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream);
 hipError_t launch_prepare(const Params& p, hipStream_t stream);
 hipError_t launch_greedy(const Params& p, int32_t wg_size, DevResult* res, hipStream_t stream);
-hipError_t launch_traverse(bool pvc, const Params& p, int32_t wg_size, hipStream_t stream);
+hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size,
+                           hipStream_t stream);
 hipError_t launch_finalize(bool pvc, const Params& p, uint8_t* cover_out, DevResult* res,
                            hipStream_t stream);
-hipError_t launch_verify(const Params& p, const uint8_t* cover, DevResult* res,
-                         hipStream_t stream);
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
                          int64_t bound, DevResult* res, hipStream_t stream);
 
 // Resident workgroups per CU for the traversal kernel at this size (occupancy API).
-hipError_t traverse_occupancy(bool pvc, int32_t wg_size, size_t lds_bytes, int* blocks_per_cu);
+hipError_t traverse_occupancy(bool pvc, bool prof, int32_t wg_size, size_t lds_bytes,
+                              int* blocks_per_cu);
 hipError_t set_lds_limit(size_t lds_bytes);
 
 }  // namespace vc

@@ -375,3 +375,19 @@ def test_context_reuse_across_sizes(solver, oracle_lib):
         r = solver.mvc(g)
         assert r.size == o.size
         check_cover(g, r.cover, o.size)
+
+
+def test_profiled_kernel_same_answers(solver, oracle_lib):
+    import paper_2204_10402_amd as vc
+    g = G.erdos_renyi(80, 0.1, 21)
+    o = oracle.mvc(g)
+    r = solver.mvc(g, vc.Options(flags=vc.OPT_PROFILE))
+    assert r.size == o.size
+    check_cover(g, r.cover, o.size)
+    cyc = r.stats["cycles"]
+    assert cyc["total"] > 0 and cyc["reduce"] > 0
+    assert sum(v for k, v in cyc.items() if k != "total") <= cyc["total"]
+    one = solver.mvc(g, vc.Options(num_wg=1, wl_threshold=-1, flags=vc.OPT_PROFILE))
+    assert one.stats["nodes"] == o.nodes
+    plain = solver.mvc(g)
+    assert all(v == 0 for v in plain.stats["cycles"].values())
