@@ -55,6 +55,11 @@ extern "C" {
 #define VC_OPT_NO_EDGE_PRUNE 0x8  /* ablation: switch off the |E| > r^2 prune */
 #define VC_OPT_PROFILE 0x10       /* run the instrumented traversal kernel, which charges shader
                                      clock cycles to activities (vc_stats.cycles) */
+#define VC_OPT_DEGREE_ARRAYS 0x20 /* use the degree-array kernels (the default above 256
+                                     vertices): a node is an int32 degree array in LDS */
+#define VC_OPT_BITSETS 0x40       /* use the bitset kernels (the default up to 256 vertices;
+                                     VC_ERR_INVALID_ARG above): a node is the set of live
+                                     vertices, held in registers */
 
 typedef struct vc_ctx vc_ctx;
 
@@ -98,6 +103,8 @@ typedef struct {
   int32_t wl_threshold;
   int32_t depth_cap;      /* stack entries provisioned per workgroup */
   int32_t n;
+  int32_t bitset_words;   /* 64-bit words per node with the bitset kernels; 0 = degree arrays */
+  int32_t node_bytes;     /* bytes of one stored search node */
   double kernel_ms;       /* traversal kernel time (HIP events on the context stream) */
   double greedy_ms;       /* greedy kernel time (MVC) */
   double total_ms;        /* wall clock of the whole call */

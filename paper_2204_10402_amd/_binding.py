@@ -26,6 +26,8 @@ OPT_NO_TRIANGLE = 0x2
 OPT_NO_HIGH_DEGREE = 0x4
 OPT_NO_EDGE_PRUNE = 0x8
 OPT_PROFILE = 0x10
+OPT_DEGREE_ARRAYS = 0x20
+OPT_BITSETS = 0x40
 ACTIVITIES = ("acquire", "reduce", "branch", "donate", "other", "total")
 
 # Every function include/vc.h declares.
@@ -56,7 +58,8 @@ class _Stats(ctypes.Structure):
                 ("greedy_size", ctypes.c_int32), ("wg_size", ctypes.c_int32),
                 ("num_wg", ctypes.c_int32), ("wl_capacity", ctypes.c_int32),
                 ("wl_threshold", ctypes.c_int32), ("depth_cap", ctypes.c_int32),
-                ("n", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
+                ("n", ctypes.c_int32), ("bitset_words", ctypes.c_int32),
+                ("node_bytes", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
                 ("greedy_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
                 ("cycles", ctypes.c_int64 * 6)]
 

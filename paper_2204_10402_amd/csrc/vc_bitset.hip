@@ -1,0 +1,706 @@
+// vc_bitset.hip -- the vertex-cover search for graphs of at most 256 vertices, with a search
+// node held as a bitset of live vertices (gfx950).
+//
+// Same method and same rules as the degree-array kernels in vc_device.hip (paper §II-B, §IV):
+// the same passes in the same order with the same tie-breaks, the same branching vertex, the
+// same child order, the same stack / worklist protocol. Only the representation of an
+// intermediate graph differs: instead of a degree array (§IV-B) a node is the set L of live
+// vertices (W = ceil(n/64) 64-bit words, held in scalar registers) plus |S|. It is just as
+// self-contained, given the read-only adjacency, and W*8 + 8 bytes instead of 4(n+2). A degree
+// is recomputed as popcount(adj[v] & L).
+//
+// One wavefront per workgroup. Lane l holds vertices l, 64+l, ..., (W-1)*64+l and their W
+// adjacency words each in vector registers; the whole adjacency matrix also sits in LDS for
+// random access (the triangle test). A rule pass is a handful of ballots and bit operations;
+// the main loop has no barriers except inside the worklist protocol.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "vc_device_common.h"
+#include "vc_internal.h"
+
+namespace vc {
+
+template <int W>
+struct Rows {  // this lane's vertices (w*64 + lane) and their adjacency words
+  uint64_t adj[W][W];
+};
+
+template <int W>
+struct Live {  // a search node, uniform across the wavefront
+  uint64_t bits[W];
+  int32_t s;
+};
+
+__device__ __forceinline__ uint64_t ballot(bool b) { return __builtin_amdgcn_ballot_w64(b); }
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(x >> 32));
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Is this lane's vertex of word wv live?
+template <int W>
+__device__ __forceinline__ bool held_live(const Live<W>& L, int wv) {
+  return (L.bits[wv] >> lane_id()) & 1ull;
+}
+
+// Bit x of a W-word mask (x < 64 W), without indexing the register array at run time.
+template <int W>
+__device__ __forceinline__ bool bit_of(const uint64_t (&M)[W], int x) {
+  uint64_t word = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) word = (x >> 6) == w ? M[w] : word;
+  return (word >> (x & 63)) & 1ull;
+}
+
+template <int W>
+__device__ __forceinline__ void held_degrees(const Rows<W>& r, const Live<W>& L, int (&deg)[W]) {
+#pragma unroll
+  for (int wv = 0; wv < W; ++wv) {
+    int d = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) d += __popcll(r.adj[wv][w] & L.bits[w]);
+    deg[wv] = d;
+  }
+}
+
+// Remove the marked set F: |S| grows by its size (§IV-B, with the |S| counter).
+template <int W>
+__device__ __forceinline__ int remove_set(Live<W>& L, const uint64_t (&F)[W]) {
+  int removed = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    removed += __popcll(F[w] & L.bits[w]);
+    L.bits[w] &= ~F[w];
+  }
+  L.s += removed;
+  return removed;
+}
+
+// Degree-one rule (§II-B, tie-breaks §IV-D). A live u is removed if it has a degree-one live
+// neighbour c and either deg(u) != 1 or u < c (for deg(u) = 1, c is its only neighbour).
+template <int W>
+__device__ __forceinline__ int pass_degree_one(const Rows<W>& r, Live<W>& L) {
+  int deg[W];
+  held_degrees(r, L, deg);
+  uint64_t D1[W];
+  uint64_t any = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    D1[w] = ballot(held_live(L, w) && deg[w] == 1);
+    any |= D1[w];
+  }
+  if (!any) return 0;
+  const int lane = lane_id();
+  uint64_t F[W];
+#pragma unroll
+  for (int wv = 0; wv < W; ++wv) {
+    bool has = false, bigger = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t m = r.adj[wv][w] & L.bits[w] & D1[w];
+      has |= m != 0;
+      if (w > wv) bigger |= m != 0;
+      if (w == wv) bigger |= ((m >> lane) >> 1) != 0;  // a neighbour with a larger id
+    }
+    F[wv] = ballot(held_live(L, wv) && has && (deg[wv] != 1 || bigger));
+  }
+  return remove_set(L, F);
+}
+
+// Degree-two-triangle rule (§II-B, tie-break §IV-D). A live v of degree two whose neighbours
+// a < b are adjacent fires unless a or b is a degree-two vertex with a smaller id; the live
+// neighbours of firing vertices (exactly their a and b) are removed.
+template <int W>
+__device__ __forceinline__ int pass_triangle(const Rows<W>& r, Live<W>& L,
+                                             const uint64_t* __restrict__ adj_lds) {
+  int deg[W];
+  held_degrees(r, L, deg);
+  uint64_t D2[W];
+  uint64_t any = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    D2[w] = ballot(held_live(L, w) && deg[w] == 2);
+    any |= D2[w];
+  }
+  if (!any) return 0;
+  const int lane = lane_id();
+  uint64_t Fire[W];
+  uint64_t anyfire = 0;
+#pragma unroll
+  for (int wv = 0; wv < W; ++wv) {
+    bool fires = false;
+    if ((D2[wv] >> lane) & 1ull) {
+      const int v = wv * 64 + lane;
+      int a = -1, b = -1;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        uint64_t m = r.adj[wv][w] & L.bits[w];
+        while (m && b < 0) {
+          const int x = w * 64 + (__ffsll(static_cast<long long>(m)) - 1);
+          m &= m - 1;
+          if (a < 0) a = x; else b = x;
+        }
+      }
+      const bool adjacent = (adj_lds[a * W + (b >> 6)] >> (b & 63)) & 1ull;
+      const bool a2 = bit_of<W>(D2, a);
+      const bool b2 = bit_of<W>(D2, b);
+      fires = adjacent && !((a2 && a < v) || (b2 && b < v));
+    }
+    Fire[wv] = ballot(fires);
+    anyfire |= Fire[wv];
+  }
+  if (!anyfire) return 0;
+  uint64_t F[W];
+#pragma unroll
+  for (int wu = 0; wu < W; ++wu) {
+    bool near = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) near |= (r.adj[wu][w] & L.bits[w] & Fire[w]) != 0;
+    F[wu] = ballot(held_live(L, wu) && near);
+  }
+  return remove_set(L, F);
+}
+
+// High-degree rule (§II-B): degree above r = bound - |S|.
+template <int W>
+__device__ __forceinline__ int pass_high_degree(const Rows<W>& r, Live<W>& L, int64_t rr) {
+  int deg[W];
+  held_degrees(r, L, deg);
+  uint64_t F[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) F[w] = ballot(held_live(L, w) && static_cast<int64_t>(deg[w]) > rr);
+  return remove_set(L, F);
+}
+
+// The rules until the graph stops changing or |S| exceeds bound (same order as the
+// degree-array kernels).
+template <int W>
+__device__ __forceinline__ void reduce_bits(const Rows<W>& r, Live<W>& L, const uint64_t* adj_lds,
+                            int64_t bound, int rules) {
+  for (;;) {
+    const int32_t s0 = L.s;
+    if (s0 > bound) return;
+    if (rules & kRuleDeg1) {
+      pass_degree_one(r, L);
+      if (L.s > bound) return;
+    }
+    if (rules & kRuleTri) {
+      pass_triangle(r, L, adj_lds);
+      if (L.s > bound) return;
+    }
+    if (rules & kRuleHigh) pass_high_degree(r, L, bound - L.s);
+    if (L.s == s0) return;
+  }
+}
+
+// Live vertex of maximum degree (smallest id on ties) and the sum of live degrees.
+template <int W>
+__device__ __forceinline__ void bits_max_degree(const Rows<W>& r, const Live<W>& L, int& vmax,
+                                                int32_t& degsum) {
+  int deg[W];
+  held_degrees(r, L, deg);
+  uint64_t key = 0;
+  int32_t sum = 0;
+  const int lane = lane_id();
+#pragma unroll
+  for (int wv = 0; wv < W; ++wv) {
+    if (held_live(L, wv)) {
+      sum += deg[wv];
+      const uint64_t k = (static_cast<uint64_t>(deg[wv]) << 32) |
+                         static_cast<uint32_t>(~static_cast<uint32_t>(wv * 64 + lane));
+      key = key > k ? key : k;
+    }
+  }
+  key = wave_max(key);
+  degsum = wave_sum(sum);
+  vmax = static_cast<int>(~static_cast<uint32_t>(key));
+}
+
+template <int W>
+__device__ __forceinline__ void remove_vertex_bits(Live<W>& L, int v) {
+  const uint64_t bit = 1ull << (v & 63);
+  const int wv = v >> 6;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint64_t keep = ~(bit & (0ull - static_cast<uint64_t>(wv == w)));  // all ones but v
+    L.bits[w] &= keep;
+  }
+  L.s += 1;
+}
+
+template <int W>
+__device__ __forceinline__ void remove_neighbourhood_bits(Live<W>& L, int v,
+                                                          const uint64_t* adj_lds) {
+  uint64_t F[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) F[w] = uniform64(adj_lds[v * W + w]);
+  remove_set(L, F);
+}
+
+// A stored node: W words of live bits (lo/hi 32-bit halves), |S|, pending vertex, padding.
+// Lane 0 writes and reads every stored node, so a node pushed on the workgroup's stack is read
+// back in program order, and the worklist publishes it with one release store.
+template <int W>
+constexpr int bits_stride() {
+  return ((2 * W + 2) + 3) & ~3;
+}
+
+template <int W>
+__device__ __forceinline__ void bits_store(int32_t* dst, const Live<W>& L, int pending) {
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      dst[2 * w] = static_cast<int32_t>(static_cast<uint32_t>(L.bits[w]));
+      dst[2 * w + 1] = static_cast<int32_t>(static_cast<uint32_t>(L.bits[w] >> 32));
+    }
+    dst[2 * W] = L.s;
+    dst[2 * W + 1] = pending;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ int bits_load(const int32_t* src, Live<W>& L) {
+  uint32_t x[2 * W + 2];
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int i = 0; i < 2 * W + 2; ++i) x[i] = static_cast<uint32_t>(src[i]);
+  }
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(x[2 * w]);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(x[2 * w + 1]);
+    L.bits[w] = (static_cast<uint64_t>(hi) << 32) | lo;
+  }
+  L.s = __builtin_amdgcn_readfirstlane(x[2 * W]);
+  return __builtin_amdgcn_readfirstlane(x[2 * W + 1]);  // pending vertex
+}
+
+// Adjacency into LDS (all rows) and this lane's rows into registers.
+template <int W>
+__device__ __forceinline__ void load_adjacency(const Params& p, uint64_t* adj_lds, Rows<W>& r) {
+  for (int i = threadIdx.x; i < p.n * W; i += blockDim.x) adj_lds[i] = p.bits[i];
+#pragma unroll
+  for (int wv = 0; wv < W; ++wv) {
+    const int v = wv * 64 + lane_id();
+#pragma unroll
+    for (int w = 0; w < W; ++w) r.adj[wv][w] = v < p.n ? p.bits[v * W + w] : 0ull;
+  }
+  __syncthreads();
+}
+
+template <int W>
+__device__ __forceinline__ void write_cover(uint8_t* cov, const Live<W>& L, int n) {
+#pragma unroll
+  for (int wv = 0; wv < W; ++wv) {
+    const int v = wv * 64 + lane_id();
+    if (v < n) cov[v] = !held_live(L, wv);
+  }
+}
+
+// ---- worklist protocol for a one-wavefront workgroup ----------------------------------------
+// Lane 0 runs the whole protocol (reservation, the node copy, the release / acquire of the slot
+// ticket), so one agent-scope release store orders the node's words before the ticket and one
+// acquire load orders them after it; the result reaches the other lanes by readfirstlane.
+
+// Donate a deferred child to the worklist; true if the worklist took it. The child is the
+// stored node at `oldest` (the bottom of this workgroup's stack) when that is not null, else
+// node L with `pending` as its branch vertex.
+template <int W>
+__device__ __forceinline__ bool bits_enqueue(const Params& p, Ctrl& c, const Live<W>& L,
+                                             int pending, const int32_t* oldest) {
+  int ok = 0;
+  if (lane_id() == 0) {
+    ok = enqueue_reserve(p, c) == 1;
+    if (ok) {
+      int32_t* dst = p.payload + static_cast<size_t>(c.slot) * p.stride;
+      if (oldest) {
+#pragma unroll
+        for (int i = 0; i < 2 * W + 2; ++i) dst[i] = oldest[i];
+      } else {
+        bits_store<W>(dst, L, pending);
+      }
+      store_release(p.seq + c.slot, 2u * c.lap + 1u);
+    }
+  }
+  return __builtin_amdgcn_readfirstlane(ok);
+}
+
+// Take a node from the worklist. Returns 1 with L / pending set, 0 when the search is over,
+// -1 when it is being stopped. Idle polling as in dequeue_begin.
+template <int W>
+__device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pending) {
+  int status = 2;
+  uint32_t words[2 * W + 2];
+  if (lane_id() == 0) {
+    int polls = 0;
+    while (status == 2) {
+      int32_t* count = ctr_i32(p, kQCount);
+      if ((polls & 3) == 0 &&
+          (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound)))) {
+        status = -1;
+      } else if (load_relaxed(count) > 0) {
+        if (fetch_add(count, -1) > 0) {
+          const unsigned long long h = fetch_add(ctr_u64(p, kQHead), 1ull);
+          const uint32_t slot = static_cast<uint32_t>(h) & (p.q_cap - 1);
+          const uint32_t lap = static_cast<uint32_t>(h / p.q_cap);
+          int wait = 0;
+          status = 1;
+          while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
+            if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) {
+              status = -1;
+              break;
+            }
+            backoff(wait);
+          }
+          if (status == 1) {
+            const int32_t* src = p.payload + static_cast<size_t>(slot) * p.stride;
+#pragma unroll
+            for (int i = 0; i < 2 * W + 2; ++i) words[i] = static_cast<uint32_t>(src[i]);
+            store_release(p.seq + slot, 2u * (lap + 1u));
+          }
+        } else {
+          fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
+        }
+      } else if (load_relaxed(ctr_i32(p, kWork)) == 0) {
+        status = 0;  // nothing queued and nothing held: the search is over
+      }
+      if (status == 2) {
+        const int units = 1 << (polls < 5 ? polls : 5);
+        for (int i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(16);
+        ++polls;
+      }
+    }
+  }
+  status = __builtin_amdgcn_readfirstlane(status);
+  if (status == 1) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint32_t lo = __builtin_amdgcn_readfirstlane(words[2 * w]);
+      const uint32_t hi = __builtin_amdgcn_readfirstlane(words[2 * w + 1]);
+      L.bits[w] = (static_cast<uint64_t>(hi) << 32) | lo;
+    }
+    L.s = __builtin_amdgcn_readfirstlane(words[2 * W]);
+    pending = __builtin_amdgcn_readfirstlane(words[2 * W + 1]);
+  }
+  return status;
+}
+
+// ---- kernels -----------------------------------------------------------------------------------
+
+// Adjacency bit matrix (n rows of W words) from the validated CSR, and the root node in
+// worklist slot 0: every vertex live, |S| = 0, nothing pending.
+__global__ void bitset_pack_kernel(Params p) {
+  if (*ctr_i32(p, kErrRow) != 0x7FFFFFFF) return;
+  const int W = p.words;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < p.n; v += gridDim.x * blockDim.x) {
+    uint64_t row[4] = {0, 0, 0, 0};
+    for (int j = p.rp[v]; j < p.rp[v + 1]; ++j) {
+      const int u = p.ci[j];
+      row[u >> 6] |= 1ull << (u & 63);
+    }
+    for (int w = 0; w < W; ++w) p.bits[v * W + w] = row[w];
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 4 * ((2 * W + 2 + 3) / 4)) {
+    const int i = threadIdx.x;
+    int32_t x = 0;
+    if (i < 2 * W) {
+      const int w = i >> 1;
+      const int lo = w * 64, hi = lo + 64 < p.n ? lo + 64 : p.n;  // vertices of word w
+      uint64_t m = 0;
+      if (hi > lo) m = hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1ull);
+      x = static_cast<int32_t>(static_cast<uint32_t>((i & 1) ? (m >> 32) : m));
+    } else if (i == 2 * W + 1) {
+      x = -1;
+    }
+    p.payload[i] = x;
+  }
+}
+
+// Greedy approximation (§II-B), as greedy_kernel, on the bitset node.
+template <int W>
+__global__ void __launch_bounds__(64) bitset_greedy_kernel(Params p, DevResult* res) {
+  extern __shared__ uint64_t adj_lds[];
+  if (threadIdx.x == 0) {
+    res->err_row = load_relaxed(ctr_i32(p, kErrRow));
+    res->edges0 = load_relaxed(ctr_i32(p, kEdges0)) / 2;
+    res->greedy = 0;
+  }
+  if (load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF) return;
+  Rows<W> r;
+  load_adjacency<W>(p, adj_lds, r);
+  Live<W> L;
+  bits_load<W>(p.payload, L);
+  const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
+  for (;;) {
+    reduce_bits<W>(r, L, adj_lds, unbounded, kRuleDeg1 | kRuleTri);
+    int vmax;
+    int32_t degsum;
+    bits_max_degree<W>(r, L, vmax, degsum);
+    if (degsum == 0) break;
+    remove_vertex_bits<W>(L, vmax);
+  }
+  write_cover<W>(p.covers + static_cast<size_t>(p.greedy_slot) * p.cover_stride, L, p.n);
+  if (threadIdx.x == 0) {
+    *ctr_u64(p, kBestKey) =
+        (static_cast<unsigned long long>(L.s) << 32) | static_cast<uint32_t>(p.greedy_slot);
+    res->greedy = L.s;
+  }
+}
+
+// The hybrid traversal (§IV-A, Fig. 4; termination §IV-C) on bitset nodes.
+template <int W, bool PVC, bool PROF>
+__global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
+  extern __shared__ uint64_t adj_lds[];
+  __shared__ Ctrl c;
+  const int wg = blockIdx.x;
+  const int tid = threadIdx.x;
+  const bool skip = load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF ||
+                    load_relaxed(ctr_i32(p, kEdges0)) == 0;
+  if (__builtin_amdgcn_readfirstlane(skip)) {
+    if (tid == 0) p.wg_stats[wg] = WgStats{};
+    return;
+  }
+  Rows<W> r;
+  load_adjacency<W>(p, adj_lds, r);
+  ActivityClock<PROF> clk;
+  clk.begin();
+
+  constexpr int kStride = bits_stride<W>();
+  int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * kStride;
+  // The stack is a ring of depth_cap entries holding [bot, top): pops take the top, donations
+  // take the bottom (the oldest deferred child, nearest its sub-tree root).
+  int top = 0, bot = 0;
+  bool have = false, holding = false;
+  int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0;
+  int max_depth = 0;
+  int64_t budget_mark = 0;
+  Live<W> L;
+
+  for (;;) {
+    const int stop = __builtin_amdgcn_readfirstlane(
+        load_relaxed(ctr_i32(p, kAbort)) | (PVC ? load_relaxed(ctr_i32(p, kFound)) : 0));
+    const int32_t best =
+        PVC ? 0 : __builtin_amdgcn_readfirstlane(
+                      static_cast<int32_t>(load_relaxed(ctr_u64(p, kBestKey)) >> 32));
+    clk.charge(kActOther);
+    if (stop) break;
+
+    if (!have) {
+      int pending;
+      if (top > bot) {
+        --top;
+        pending = bits_load<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L);
+        ++pops;
+      } else {
+        if (holding) {
+          if (tid == 0) fetch_add(ctr_i32(p, kWork), -1);
+          holding = false;
+        }
+        const int got = bits_dequeue<W>(p, L, pending);
+        if (got != 1) {
+          clk.charge(kActAcquire);
+          break;
+        }
+        holding = true;
+        ++dequeues;
+      }
+      clk.charge(kActAcquire);
+      if (pending >= 0) remove_neighbourhood_bits<W>(L, pending, adj_lds);
+      clk.charge(kActBranch);
+      have = true;
+    }
+
+    ++nodes;
+    if (p.node_budget > 0 && nodes - budget_mark >= p.budget_chunk) {
+      if (tid == 0) {
+        const unsigned long long total =
+            fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
+        if (static_cast<int64_t>(total) + (nodes - budget_mark) >= p.node_budget)
+          store_relaxed(ctr_i32(p, kAbort), 1);
+      }
+      budget_mark = nodes;
+    }
+
+    const int64_t bound = PVC ? p.k : static_cast<int64_t>(best) - 1;
+    clk.charge(kActOther);
+    reduce_bits<W>(r, L, adj_lds, bound, p.rules);
+    clk.charge(kActReduce);
+
+    const int64_t rr = bound - L.s;
+    if (rr < 0) {
+      have = false;
+      continue;
+    }
+    int vmax;
+    int32_t degsum;
+    bits_max_degree<W>(r, L, vmax, degsum);
+    clk.charge(kActBranch);
+    const int64_t edges = degsum / 2;
+    if ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > rr * rr) {
+      have = false;
+      continue;
+    }
+    if (edges == 0) {  // a vertex cover of size |S|
+      int won = 0;
+      if (tid == 0) {
+        if (PVC) {
+          won = atomicCAS(ctr_i32(p, kFound), 0, wg + 1) == 0;
+        } else {
+          const unsigned long long key =
+              (static_cast<unsigned long long>(L.s) << 32) | static_cast<uint32_t>(wg);
+          won = atomicMin(ctr_u64(p, kBestKey), key) > key;
+        }
+      }
+      if (__builtin_amdgcn_readfirstlane(won))
+        write_cover<W>(p.covers + static_cast<size_t>(wg) * p.cover_stride, L, p.n);
+      clk.charge(kActOther);
+      have = false;
+      continue;
+    }
+
+    // branch on v_max: defer the N(v_max) child, continue with the v_max child. While the
+    // worklist is below its threshold a deferred child is donated: the oldest one on this
+    // workgroup's stack if there is one (the largest sub-tree it holds), else this one.
+    bool kept_local = true;
+    if (p.q_threshold > 0) {
+      const bool from_stack = top > bot;
+      const int32_t* oldest =
+          from_stack ? stack + static_cast<size_t>(bot % p.depth_cap) * kStride : nullptr;
+      if (bits_enqueue<W>(p, c, L, vmax, oldest)) {
+        ++enqueues;
+        if (from_stack) ++bot;
+        else kept_local = false;
+      }
+    }
+    if (kept_local) {
+      if (top - bot >= p.depth_cap) {  // cannot happen: the depth bound of §IV-E holds
+        if (tid == 0) {
+          atomicMax(ctr_i32(p, kError), 1);
+          store_relaxed(ctr_i32(p, kAbort), 1);
+        }
+        break;
+      }
+      bits_store<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, vmax);
+      ++top;
+      ++pushes;
+      if (top - bot > max_depth) max_depth = top - bot;
+    }
+    clk.charge(kActDonate);
+    remove_vertex_bits<W>(L, vmax);
+    clk.charge(kActBranch);
+  }
+  clk.end();
+
+  if (tid == 0) {
+    if (p.node_budget > 0 && nodes > budget_mark)
+      fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
+    WgStats w{};
+    w.nodes = nodes;
+    w.pushes = pushes;
+    w.pops = pops;
+    w.enqueues = enqueues;
+    w.dequeues = dequeues;
+    w.max_depth = max_depth;
+    for (int a = 0; a < kNumActivities; ++a) w.cycles[a] = static_cast<int64_t>(clk.cycles[a]);
+    p.wg_stats[wg] = w;
+  }
+}
+
+// The reduction rules of one node on a degree array in device memory (-1 = in the cover).
+template <int W>
+__global__ void __launch_bounds__(64) bitset_reduce_kernel(Params p, int32_t* deg, int32_t* s,
+                                                           int64_t bound, DevResult* res) {
+  extern __shared__ uint64_t adj_lds[];
+  if (threadIdx.x == 0) res->err_row = load_relaxed(ctr_i32(p, kErrRow));
+  if (load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF) return;
+  Rows<W> r;
+  load_adjacency<W>(p, adj_lds, r);
+  Live<W> L;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int v = w * 64 + lane_id();
+    L.bits[w] = ballot(v < p.n && deg[v] >= 0);
+  }
+  L.s = __builtin_amdgcn_readfirstlane(*s);
+  reduce_bits<W>(r, L, adj_lds, bound, p.rules);
+  int d[W];
+  held_degrees(r, L, d);
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int v = w * 64 + lane_id();
+    if (v < p.n) deg[v] = held_live(L, w) ? d[w] : -1;
+  }
+  if (threadIdx.x == 0) *s = L.s;
+}
+
+// ---- launchers ---------------------------------------------------------------------------------
+
+hipError_t launch_bitset_pack(const Params& p, hipStream_t stream) {
+  int blocks = (p.n + 255) / 256;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(bitset_pack_kernel, dim3(blocks), dim3(256), 0, stream, p);
+  return hipGetLastError();
+}
+
+template <int W>
+static const void* bitset_traverse_fn(bool pvc, bool prof) {
+  if (pvc) return prof ? reinterpret_cast<const void*>(&bitset_traverse_kernel<W, true, true>)
+                       : reinterpret_cast<const void*>(&bitset_traverse_kernel<W, true, false>);
+  return prof ? reinterpret_cast<const void*>(&bitset_traverse_kernel<W, false, true>)
+              : reinterpret_cast<const void*>(&bitset_traverse_kernel<W, false, false>);
+}
+
+static const void* bitset_fn(int words, bool pvc, bool prof) {
+  switch (words) {
+    case 1: return bitset_traverse_fn<1>(pvc, prof);
+    case 2: return bitset_traverse_fn<2>(pvc, prof);
+    case 3: return bitset_traverse_fn<3>(pvc, prof);
+    default: return bitset_traverse_fn<4>(pvc, prof);
+  }
+}
+
+size_t bitset_lds_bytes(int n, int words) { return static_cast<size_t>(n) * words * 8; }
+
+int bitset_stride(int words) { return ((2 * words + 2) + 3) & ~3; }
+
+hipError_t launch_bitset_greedy(const Params& p, DevResult* res, hipStream_t stream) {
+  const size_t lds = bitset_lds_bytes(p.n, p.words);
+  switch (p.words) {
+    case 1: hipLaunchKernelGGL(bitset_greedy_kernel<1>, dim3(1), dim3(64), lds, stream, p, res); break;
+    case 2: hipLaunchKernelGGL(bitset_greedy_kernel<2>, dim3(1), dim3(64), lds, stream, p, res); break;
+    case 3: hipLaunchKernelGGL(bitset_greedy_kernel<3>, dim3(1), dim3(64), lds, stream, p, res); break;
+    default: hipLaunchKernelGGL(bitset_greedy_kernel<4>, dim3(1), dim3(64), lds, stream, p, res); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStream_t stream) {
+  Params args = p;
+  void* kargs[] = {&args};
+  return hipLaunchCooperativeKernel(bitset_fn(p.words, pvc, prof), dim3(p.num_wg), dim3(64),
+                                    kargs, static_cast<unsigned int>(bitset_lds_bytes(p.n, p.words)),
+                                    stream);
+}
+
+hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,
+                                DevResult* res, hipStream_t stream) {
+  const size_t lds = bitset_lds_bytes(p.n, p.words);
+  switch (p.words) {
+    case 1: hipLaunchKernelGGL(bitset_reduce_kernel<1>, dim3(1), dim3(64), lds, stream, p, deg, s, bound, res); break;
+    case 2: hipLaunchKernelGGL(bitset_reduce_kernel<2>, dim3(1), dim3(64), lds, stream, p, deg, s, bound, res); break;
+    case 3: hipLaunchKernelGGL(bitset_reduce_kernel<3>, dim3(1), dim3(64), lds, stream, p, deg, s, bound, res); break;
+    default: hipLaunchKernelGGL(bitset_reduce_kernel<4>, dim3(1), dim3(64), lds, stream, p, deg, s, bound, res); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t bitset_occupancy(int words, bool pvc, bool prof, int n, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bitset_fn(words, pvc, prof),
+                                                      64, bitset_lds_bytes(n, words));
+}
+
+}  // namespace vc

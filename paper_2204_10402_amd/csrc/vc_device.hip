@@ -35,116 +35,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vc_device_common.h"
 #include "vc_internal.h"
 
 namespace vc {
 
-constexpr int32_t kSent = -1;
 constexpr int32_t kFlag = 0x40000000;     // "decided this pass" mark on a live entry
 constexpr int32_t kDegMask = 0x3FFFFFFF;  // degree bits of a live entry
-constexpr int kMaxWaves = 16;             // 1024 threads
-
-// ---- scoped atomics ------------------------------------------------------------------------
-
-__device__ __forceinline__ int32_t* ctr_i32(const Params& p, int slot) {
-  return p.ctr + slot * kCounterStride;
-}
-__device__ __forceinline__ unsigned long long* ctr_u64(const Params& p, int slot) {
-  return reinterpret_cast<unsigned long long*>(p.ctr + slot * kCounterStride);
-}
-__device__ __forceinline__ int32_t load_relaxed(int32_t* a) {
-  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long load_relaxed(unsigned long long* a) {
-  return __hip_atomic_load(a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ uint32_t load_acquire(uint32_t* a) {
-  return __hip_atomic_load(a, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_release(uint32_t* a, uint32_t v) {
-  __hip_atomic_store(a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void store_relaxed(int32_t* a, int32_t v) {
-  __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int32_t fetch_add(int32_t* a, int32_t v) {
-  return __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ unsigned long long fetch_add(unsigned long long* a,
-                                                        unsigned long long v) {
-  return __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// ---- wavefront-64 reductions (DPP row operations + lane reads) -----------------------------
-
-template <int CTRL>
-__device__ __forceinline__ uint32_t dpp(uint32_t x) {
-  return static_cast<uint32_t>(
-      __builtin_amdgcn_update_dpp(static_cast<int>(x), static_cast<int>(x), CTRL, 0xF, 0xF, false));
-}
-template <int CTRL>
-__device__ __forceinline__ uint64_t dpp64(uint64_t x) {
-  const uint32_t lo = dpp<CTRL>(static_cast<uint32_t>(x));
-  const uint32_t hi = dpp<CTRL>(static_cast<uint32_t>(x >> 32));
-  return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-// DPP controls: quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror, row_mirror. After
-// the four steps every lane of a 16-lane row holds the row's result.
-constexpr int kDppQuadSwap1 = 0xB1;
-constexpr int kDppQuadSwap2 = 0x4E;
-constexpr int kDppHalfMirror = 0x141;
-constexpr int kDppMirror = 0x140;
-
-__device__ __forceinline__ int32_t wave_sum(int32_t x) {
-  uint32_t u = static_cast<uint32_t>(x);
-  u += dpp<kDppQuadSwap1>(u);
-  u += dpp<kDppQuadSwap2>(u);
-  u += dpp<kDppHalfMirror>(u);
-  u += dpp<kDppMirror>(u);
-  const uint32_t r = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), 0)) +
-                     static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), 16)) +
-                     static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), 32)) +
-                     static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(u), 48));
-  return static_cast<int32_t>(r);
-}
-
-__device__ __forceinline__ uint64_t umax64(uint64_t a, uint64_t b) { return a > b ? a : b; }
-
-__device__ __forceinline__ uint64_t readlane64(uint64_t x, int lane) {
-  const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), lane));
-  const uint32_t hi =
-      static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x >> 32), lane));
-  return (static_cast<uint64_t>(hi) << 32) | lo;
-}
-
-__device__ __forceinline__ uint64_t wave_max(uint64_t x) {
-  x = umax64(x, dpp64<kDppQuadSwap1>(x));
-  x = umax64(x, dpp64<kDppQuadSwap2>(x));
-  x = umax64(x, dpp64<kDppHalfMirror>(x));
-  x = umax64(x, dpp64<kDppMirror>(x));
-  return umax64(umax64(readlane64(x, 0), readlane64(x, 16)),
-                umax64(readlane64(x, 32), readlane64(x, 48)));
-}
-
-__device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x) & 63; }
-__device__ __forceinline__ int wave_id() { return static_cast<int>(threadIdx.x) >> 6; }
-__device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll(static_cast<long long>(m)) - 1; }
-__device__ __forceinline__ int bcast(int x, int lane) { return __builtin_amdgcn_readlane(x, lane); }
-
-// ---- per-workgroup LDS control block ------------------------------------------------------
-
-struct Ctrl {
-  int32_t flag_epoch;  // epoch of the last decide step that marked a vertex
-  int32_t status;      // broadcast of a result computed by thread 0
-  uint32_t slot;
-  uint32_t lap;
-  int32_t best;        // broadcast of the global best size (MVC)
-  int32_t stop;        // broadcast of the found / abort flags
-  int32_t err;         // broadcast: the input graph was rejected
-  int32_t pad;
-  uint64_t red_key[kMaxWaves];
-  int32_t red_sum[kMaxWaves];
-};
 
 // ---- node operations on the LDS degree array -------------------------------------------------
 // st[0..n) degrees (kSent = in cover), st[n] = s, st[n+1] = pending vertex (-1 = none).
@@ -155,50 +52,6 @@ struct Node {
   const int32_t* __restrict__ rp;
   const int32_t* __restrict__ ci;
 };
-
-// ---- wavefront building blocks ---------------------------------------------------------------
-
-// Inclusive prefix sum over the 64 lanes: DPP row shifts inside each 16-lane row, then row
-// broadcasts (row_bcast:15 to rows 1 and 3, row_bcast:31 to rows 2 and 3).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int32_t dpp_or_zero(int32_t x) {
-  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xF, false);
-}
-__device__ __forceinline__ int32_t wave_incl_scan(int32_t x) {
-  x += dpp_or_zero<0x111, 0xF>(x);  // row_shr:1
-  x += dpp_or_zero<0x112, 0xF>(x);  // row_shr:2
-  x += dpp_or_zero<0x114, 0xF>(x);  // row_shr:4
-  x += dpp_or_zero<0x118, 0xF>(x);  // row_shr:8
-  x += dpp_or_zero<0x142, 0xA>(x);  // row_bcast:15
-  x += dpp_or_zero<0x143, 0xC>(x);  // row_bcast:31
-  return x;
-}
-
-__device__ __forceinline__ int shfl(int x, int src_lane) {
-  return __builtin_amdgcn_ds_bpermute(src_lane << 2, x);
-}
-
-// Index of the k-th (from 0) set bit of m; m must have more than k set bits.
-__device__ __forceinline__ int kth_set_bit(uint64_t m, int k) {
-  int pos = 0;
-  uint32_t w = static_cast<uint32_t>(m);
-  int c = __popc(w);
-  if (k >= c) {
-    k -= c;
-    pos = 32;
-    w = static_cast<uint32_t>(m >> 32);
-  }
-#pragma unroll
-  for (int half = 16; half > 0; half >>= 1) {
-    c = __popc(w & ((1u << half) - 1u));
-    if (k >= c) {
-      k -= c;
-      pos += half;
-      w >>= half;
-    }
-  }
-  return pos;
-}
 
 // Walk the CSR rows [beg, end) held by the lanes of a wavefront (empty where beg >= end) as one
 // list, 64 consecutive entries per step, so rows of any length keep every lane busy and
@@ -534,116 +387,41 @@ __device__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int str
   }
 }
 
+// Copy a stored node between two device-memory slots with the same thread-to-word mapping as
+// node_store / node_load, so each thread reads back words it wrote itself.
+__device__ void node_copy(int32_t* __restrict__ dst, const int32_t* __restrict__ src, int stride) {
+  const int4* s4 = reinterpret_cast<const int4*>(src);
+  int4* d4 = reinterpret_cast<int4*>(dst);
+  for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
+}
+
 __device__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stride) {
   const int4* s4 = reinterpret_cast<const int4*>(src);
   int4* d4 = reinterpret_cast<int4*>(st);
   for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
 }
 
-__device__ __forceinline__ void backoff(int& spins) {
-  if (spins < 8) ++spins;
-  for (int i = 0; i < spins; ++i) __builtin_amdgcn_s_sleep(8);
-}
-
-// ---- global worklist -----------------------------------------------------------------------
-// A bounded ring of q_cap node slots (a power of two). Ticket t uses slot t % cap in lap
-// t / cap; seq[slot] = 2*lap means free for lap `lap`, 2*lap + 1 means filled in lap `lap`.
-// `count` is the number of entries producers have reserved and consumers have not: a
-// consumer only takes a ticket after lowering a positive count, so it never waits for a
-// node that will not come. A producer raises the outstanding-work counter before it
-// reserves, so that counter can read zero only when nothing is queued or held.
-
-// Thread 0 tries to reserve a slot for a donated node; returns 1 with c.slot/c.lap set, 0 if
-// the worklist is at its threshold, -1 if the search is being stopped.
-__device__ int enqueue_reserve(const Params& p, Ctrl& c) {
-  int32_t* count = ctr_i32(p, kQCount);
-  const int32_t seen = load_relaxed(count);
-  if (seen >= static_cast<int32_t>(p.q_threshold)) return 0;
-  fetch_add(ctr_i32(p, kWork), 1);
-  const int32_t before = fetch_add(count, 1);  // cannot exceed cap: threshold + num_wg <= cap
-  if (before + 1 > load_relaxed(ctr_i32(p, kQMaxCount))) atomicMax(ctr_i32(p, kQMaxCount), before + 1);
-  const unsigned long long t = fetch_add(ctr_u64(p, kQTail), 1ull);
-  const uint32_t slot = static_cast<uint32_t>(t) & (p.q_cap - 1);
-  const uint32_t lap = static_cast<uint32_t>(t / p.q_cap);
-  int spins = 0;
-  while (load_acquire(p.seq + slot) != 2u * lap) {
-    if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) return -1;
-    backoff(spins);
-  }
-  c.slot = slot;
-  c.lap = lap;
-  return 1;
-}
-
-// Whole workgroup: donate the node in LDS (with `pending` as its branch vertex). Returns true
-// if the worklist took it.
-__device__ bool try_enqueue(const Params& p, const Node& nd, Ctrl& c, int pending) {
-  if (threadIdx.x == 0) c.status = enqueue_reserve(p, c);
-  __syncthreads();
-  const int status = c.status;
-  if (status != 1) return false;  // at threshold, or stopping: keep the node locally
-  const uint32_t slot = c.slot, lap = c.lap;
-  node_store(p.payload + static_cast<size_t>(slot) * p.stride, nd.st, p.stride, nd.n, pending);
-  __threadfence();  // make this thread's part of the node visible at agent scope
-  __syncthreads();
-  if (threadIdx.x == 0) store_release(p.seq + slot, 2u * lap + 1u);
+// Whole workgroup: donate a deferred child to the worklist; true if the worklist took it. The
+// child is the stored node at `oldest` (the bottom of this workgroup's stack) when that is not
+// null, else the node in LDS with `pending` as its branch vertex.
+__device__ bool try_enqueue(const Params& p, const Node& nd, Ctrl& c, int pending,
+                            const int32_t* oldest) {
+  if (!enqueue_begin(p, c)) return false;
+  int32_t* dst = p.payload + static_cast<size_t>(c.slot) * p.stride;
+  if (oldest) node_copy(dst, oldest, p.stride);
+  else node_store(dst, nd.st, p.stride, nd.n, pending);
+  enqueue_publish(p, c);
   return true;
 }
 
 // Whole workgroup: take a node from the worklist into LDS. Returns 1 on success, 0 when the
-// whole search is finished, -1 when it is being stopped. An idle workgroup polls the entry
-// count (and, while the list is empty, the outstanding-work counter) with exponential
-// back-off, and looks at the stop flags every fourth poll.
+// whole search is finished, -1 when it is being stopped.
 __device__ int dequeue(const Params& p, const Node& nd, Ctrl& c) {
-  int polls = 0;
-  for (;;) {
-    if (threadIdx.x == 0) {
-      int status = 2;  // nothing available yet: retry
-      int32_t* count = ctr_i32(p, kQCount);
-      if ((polls & 3) == 0 &&
-          (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound)))) {
-        status = -1;
-      } else if (load_relaxed(count) > 0) {
-        if (fetch_add(count, -1) > 0) {
-          const unsigned long long h = fetch_add(ctr_u64(p, kQHead), 1ull);
-          const uint32_t slot = static_cast<uint32_t>(h) & (p.q_cap - 1);
-          const uint32_t lap = static_cast<uint32_t>(h / p.q_cap);
-          int wait = 0;
-          status = 1;
-          while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
-            if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) {
-              status = -1;
-              break;
-            }
-            backoff(wait);
-          }
-          c.slot = slot;
-          c.lap = lap;
-        } else {
-          fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
-        }
-      } else if (load_relaxed(ctr_i32(p, kWork)) == 0) {
-        status = 0;  // nothing queued and nothing held: the search is over
-      }
-      if (status == 2) {
-        const int units = 1 << (polls < 5 ? polls : 5);
-        for (int i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(16);
-        ++polls;
-      }
-      c.status = status;
-    }
-    __syncthreads();
-    const int status = c.status;
-    if (status == 1) {
-      const uint32_t slot = c.slot, lap = c.lap;
-      node_load(nd.st, p.payload + static_cast<size_t>(slot) * p.stride, p.stride);
-      __syncthreads();
-      if (threadIdx.x == 0) store_release(p.seq + slot, 2u * (lap + 1u));
-      return 1;
-    }
-    if (status != 2) return status;
-    __syncthreads();  // every thread has read c.status before thread 0 writes it again
-  }
+  const int status = dequeue_begin(p, c);
+  if (status != 1) return status;
+  node_load(nd.st, p.payload + static_cast<size_t>(c.slot) * p.stride, p.stride);
+  dequeue_finish(p, c);
+  return 1;
 }
 
 // ---- kernels ---------------------------------------------------------------------------------
@@ -667,17 +445,6 @@ __global__ void init_kernel(Params p, DevResult* res) {
   }
 }
 
-// The CSR row holding entry i: the largest v in [0, n) with rp[v] <= i. Every probe stays in
-// rp[0..n), whatever rp holds, so a malformed row_ptr cannot send the search out of bounds.
-__device__ __forceinline__ int owner_row(const int32_t* __restrict__ rp, int n, int i) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = lo + ((hi - lo + 1) >> 1);
-    if (rp[mid] <= i) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Check the CSR (simple undirected graph, §II-A) and write the root node -- the input's
 // degree array, s = 0, no pending vertex -- into worklist slot 0. Index i < stride checks row
 // i's bounds and writes its degree; index i < nnz checks entry i: in range, not a self-loop,
@@ -688,9 +455,11 @@ __global__ void prepare_kernel(Params p) {
   const int n = p.n, nnz = p.nnz;
   int32_t* root = p.payload;
   int32_t local_sum = 0;
-  const int total = p.stride > nnz ? p.stride : nnz;
+  // the bitset kernels build their own root node (bitset_pack_kernel)
+  const int vertex_items = p.words ? n : p.stride;
+  const int total = vertex_items > nnz ? vertex_items : nnz;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-    if (i < p.stride) {
+    if (i < vertex_items) {
       if (i >= n) {
         root[i] = (i == n + 1) ? -1 : 0;
       } else {
@@ -699,7 +468,7 @@ __global__ void prepare_kernel(Params p) {
                          end < beg || end > nnz;
         if (bad) atomicMin(ctr_i32(p, kErrRow), i);
         const int32_t d = bad ? 0 : end - beg;
-        root[i] = d;
+        if (!p.words) root[i] = d;
         local_sum += d;
       }
     }
@@ -769,27 +538,6 @@ __global__ void __launch_bounds__(1024) greedy_kernel(Params p, DevResult* res) 
   }
 }
 
-// Per-workgroup activity clock of the instrumented kernel (paper §V-D, Fig. 6): shader-clock
-// cycles are charged to the activity that just ended. Compiled out when PROF is false.
-template <bool PROF>
-struct ActivityClock {
-  uint64_t cycles[kNumActivities] = {};
-  uint64_t mark = 0, start = 0;
-  __device__ void begin() {
-    if (PROF) start = mark = clock64();
-  }
-  __device__ void charge(int activity) {
-    if (PROF) {
-      const uint64_t now = clock64();
-      cycles[activity] += now - mark;
-      mark = now;
-    }
-  }
-  __device__ void end() {
-    if (PROF) cycles[kActTotal] = clock64() - start;
-  }
-};
-
 // The hybrid traversal (§IV-A, Fig. 4; PVC differences in §IV-A, termination §IV-C).
 template <bool PVC, bool PROF>
 __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
@@ -815,7 +563,9 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   clk.begin();
 
   int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * p.stride;
-  int sp = 0;             // entries on this workgroup's stack
+  // The stack is a ring of depth_cap entries holding [bot, top): pops take the top, donations
+  // take the bottom (the oldest deferred child, nearest its sub-tree root).
+  int top = 0, bot = 0;
   bool have = false;      // a node is in LDS and still to be visited
   bool holding = false;   // this workgroup holds a sub-tree taken from the worklist
   int epoch = 0;
@@ -834,9 +584,9 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     if (c.stop) break;
 
     if (!have) {
-      if (sp > 0) {
-        --sp;
-        node_load(st, stack + static_cast<size_t>(sp) * p.stride, p.stride);
+      if (top > bot) {
+        --top;
+        node_load(st, stack + static_cast<size_t>(top % p.depth_cap) * p.stride, p.stride);
         ++pops;
         __syncthreads();
       } else {
@@ -914,22 +664,32 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       continue;
     }
 
-    // branch on v_max (§II-B): defer the N(v_max) child, continue with the v_max child
-    const bool donated = p.q_threshold > 0 && try_enqueue(p, nd, c, vmax);
-    if (donated) {
-      ++enqueues;
-    } else {
-      if (sp >= p.depth_cap) {  // cannot happen: the depth bound of §IV-E holds
+    // branch on v_max (§II-B): defer the N(v_max) child, continue with the v_max child. While
+    // the worklist is below its threshold a deferred child is donated (§IV-A): the oldest one on
+    // this workgroup's stack if there is one (the largest sub-tree it holds), else this one.
+    bool kept_local = true;
+    if (p.q_threshold > 0) {
+      const bool from_stack = top > bot;
+      const int32_t* oldest =
+          from_stack ? stack + static_cast<size_t>(bot % p.depth_cap) * p.stride : nullptr;
+      if (try_enqueue(p, nd, c, vmax, oldest)) {
+        ++enqueues;
+        if (from_stack) ++bot;
+        else kept_local = false;
+      }
+    }
+    if (kept_local) {
+      if (top - bot >= p.depth_cap) {  // cannot happen: the depth bound of §IV-E holds
         if (tid == 0) {
           atomicMax(ctr_i32(p, kError), 1);
           store_relaxed(ctr_i32(p, kAbort), 1);
         }
         break;
       }
-      node_store(stack + static_cast<size_t>(sp) * p.stride, st, p.stride, n, vmax);
-      ++sp;
+      node_store(stack + static_cast<size_t>(top % p.depth_cap) * p.stride, st, p.stride, n, vmax);
+      ++top;
       ++pushes;
-      if (sp > max_depth) max_depth = sp;
+      if (top - bot > max_depth) max_depth = top - bot;
       __syncthreads();  // the copy has read the node before it changes below
     }
     clk.charge(kActDonate);
@@ -951,20 +711,6 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     for (int a = 0; a < kNumActivities; ++a) w.cycles[a] = static_cast<int64_t>(clk.cycles[a]);
     p.wg_stats[wg] = w;
   }
-}
-
-// Sum / max / min over a 256-thread workgroup through shared memory.
-template <typename Op>
-__device__ int64_t block_reduce_256(int64_t v, int64_t* buf, Op op) {
-  buf[threadIdx.x] = v;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (static_cast<int>(threadIdx.x) < h) buf[threadIdx.x] = op(buf[threadIdx.x], buf[threadIdx.x + h]);
-    __syncthreads();
-  }
-  const int64_t r = buf[0];
-  __syncthreads();
-  return r;
 }
 
 // Index of the cover buffer holding the answer: >= 0, or -2 for "no cover" (rejected input,
@@ -1098,7 +844,8 @@ hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream) {
 
 hipError_t launch_prepare(const Params& p, hipStream_t stream) {
   const int threads = 256;
-  const int items = p.stride > p.nnz ? p.stride : p.nnz;
+  const int vertex_items = p.words ? p.n : p.stride;
+  const int items = vertex_items > p.nnz ? vertex_items : p.nnz;
   int blocks = (items + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(prepare_kernel, dim3(blocks), dim3(threads), 0, stream, p);

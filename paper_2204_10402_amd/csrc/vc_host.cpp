@@ -32,7 +32,7 @@ struct vc_ctx {
   bool own_stream = false;
   hipDeviceProp_t prop{};
   size_t lds_limit_set = 0;
-  DevBuf rp, ci, payload, seq, ctr, stacks, covers, wg_stats, result, cover_tmp, scratch_s;
+  DevBuf rp, ci, payload, seq, ctr, stacks, covers, wg_stats, result, cover_tmp, scratch_s, bits;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::string last_error;
 };
@@ -104,8 +104,11 @@ int check_options(vc_ctx* ctx, const vc_options* o) {
   if (o->num_wg < 0 || o->wl_capacity < 0 || o->wl_threshold < -1 || o->node_budget < 0)
     return fail(ctx, VC_ERR_INVALID_ARG, "negative option value");
   const int32_t known = VC_OPT_NO_DEGREE_ONE | VC_OPT_NO_TRIANGLE | VC_OPT_NO_HIGH_DEGREE |
-                        VC_OPT_NO_EDGE_PRUNE | VC_OPT_PROFILE;
+                        VC_OPT_NO_EDGE_PRUNE | VC_OPT_PROFILE | VC_OPT_DEGREE_ARRAYS |
+                        VC_OPT_BITSETS;
   if (o->flags & ~known) return fail(ctx, VC_ERR_INVALID_ARG, "unknown option flag");
+  if ((o->flags & VC_OPT_DEGREE_ARRAYS) && (o->flags & VC_OPT_BITSETS))
+    return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_DEGREE_ARRAYS and VC_OPT_BITSETS exclude each other");
   return VC_OK;
 }
 
@@ -127,43 +130,68 @@ struct Plan {
   uint32_t cap = 0;
   uint32_t threshold = 0;
   size_t lds = 0;
+  int32_t words = 0;  // > 0: bitset kernels with this many 64-bit words per node
 };
+
+// Bitset kernels up to 256 vertices unless the caller asks for degree arrays.
+int choose_words(vc_ctx* ctx, int32_t n, int32_t flags, int32_t* words) {
+  const bool force_bits = flags & VC_OPT_BITSETS;
+  const bool force_arrays = flags & VC_OPT_DEGREE_ARRAYS;
+  if (force_bits && n > vc::kMaxBitsetN)
+    return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_BITSETS needs n <= 256");
+  *words = (!force_arrays && n <= vc::kMaxBitsetN) ? (std::max(n, 1) + 63) / 64 : 0;
+  return VC_OK;
+}
 
 // Workgroup size and count (paper §IV-E, adapted): a power-of-two workgroup of about n/4
 // threads; as many workgroups as can be resident at once (all must be, since they wait on
 // each other), fewer if their stacks do not fit in device memory.
 int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl) {
   const bool prof = o && (o->flags & VC_OPT_PROFILE);
-  pl.stride = static_cast<int32_t>(round_up(static_cast<int64_t>(n) + 2, 64));
+  int rc = choose_words(ctx, n, o ? o->flags : 0, &pl.words);
+  if (rc) return rc;
   pl.cover_stride = static_cast<int32_t>(round_up(std::max<int64_t>(n, 1), 256));
-  pl.lds = static_cast<size_t>(pl.stride) * sizeof(int32_t);
-  const size_t lds_cap = static_cast<size_t>(ctx->prop.maxSharedMemoryPerMultiProcessor);
-  if (pl.lds + 1024 > lds_cap)
-    return fail(ctx, VC_ERR_INVALID_ARG,
-                "graph too large for the LDS-resident node (n = " + std::to_string(n) + ")");
-  if (pl.lds > 65536 && ctx->lds_limit_set < pl.lds) {
-    VC_HIP(ctx, vc::set_lds_limit(pl.lds));
-    ctx->lds_limit_set = pl.lds;
-  }
   const int cus = ctx->prop.multiProcessorCount;
   int best_ws = 0, best_occ = 0;
-  if (o && o->wg_size) {
-    best_ws = o->wg_size;
-    VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, best_ws, pl.lds, &best_occ));
+  if (pl.words) {
+    // one wavefront per workgroup; the adjacency matrix (n * words * 8 bytes) in LDS
+    pl.stride = vc::bitset_stride(pl.words);
+    pl.lds = vc::bitset_lds_bytes(n, pl.words);
+    best_ws = 64;
+    if (o && o->wg_size && o->wg_size != 64)
+      return fail(ctx, VC_ERR_INVALID_ARG, "the bitset kernels use 64-thread workgroups");
+    VC_HIP(ctx, vc::bitset_occupancy(pl.words, pvc, prof, n, &best_occ));
   } else {
-    // The paper's rule (§IV-E) admits any power of two between the size that fills the CU and
-    // min(1024, n). A node's passes are chains of dependent LDS and L2 accesses, so the time
-    // per node falls with more wavefronts per node: take about n/4 threads (four vertices per
-    // thread per pass), as a power of two in [64, 1024].
-    int ws = 64;
-    while (ws < 1024 && ws * 2 <= std::max(n, 1) / 4) ws *= 2;
-    best_ws = ws;
+    pl.stride = static_cast<int32_t>(round_up(static_cast<int64_t>(n) + 2, 64));
+    pl.lds = static_cast<size_t>(pl.stride) * sizeof(int32_t);
+    const size_t lds_cap = static_cast<size_t>(ctx->prop.maxSharedMemoryPerMultiProcessor);
+    if (pl.lds + 1024 > lds_cap)
+      return fail(ctx, VC_ERR_INVALID_ARG,
+                  "graph too large for the LDS-resident node (n = " + std::to_string(n) + ")");
+    if (pl.lds > 65536 && ctx->lds_limit_set < pl.lds) {
+      VC_HIP(ctx, vc::set_lds_limit(pl.lds));
+      ctx->lds_limit_set = pl.lds;
+    }
+    if (o && o->wg_size) {
+      best_ws = o->wg_size;
+    } else {
+      // The paper's rule (§IV-E) admits any power of two between the size that fills the CU
+      // and min(1024, n). A node's passes are chains of dependent LDS and L2 accesses, so the
+      // time per node falls with more wavefronts per node: take about n/4 threads (four
+      // vertices per thread per pass), as a power of two in [64, 1024].
+      int ws = 64;
+      while (ws < 1024 && ws * 2 <= std::max(n, 1) / 4) ws *= 2;
+      best_ws = ws;
+    }
     VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, best_ws, pl.lds, &best_occ));
   }
   if (best_occ < 1)
     return fail(ctx, VC_ERR_INVALID_ARG, "traversal kernel cannot be resident at this size");
   pl.wg_size = best_ws;
   pl.num_wg = best_occ * cus;
+  // Bitset nodes take a few microseconds each, so more than eight workgroups per CU only add
+  // contention on the worklist counters (measured on the hard MVC instances).
+  if (pl.words && !(o && o->num_wg > 0)) pl.num_wg = std::min(pl.num_wg, 8 * cus);
   if (o && o->num_wg > 0) pl.num_wg = std::min(pl.num_wg, o->num_wg);
   pl.max_wg = pl.num_wg;
 
@@ -178,7 +206,7 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl)
   uint64_t thr;
   if (o && o->wl_threshold == -1) thr = 0;
   else if (o && o->wl_threshold > 0) thr = static_cast<uint64_t>(o->wl_threshold);
-  else thr = pl.cap / 2;
+  else thr = std::max<uint64_t>(64, static_cast<uint64_t>(pl.num_wg) / 4);
   thr = std::min<uint64_t>(thr, pl.cap - 2ull * static_cast<uint64_t>(pl.num_wg));
   pl.threshold = static_cast<uint32_t>(thr);
   return VC_OK;
@@ -241,11 +269,17 @@ int run_search(vc_ctx* ctx, const vc_graph* g, bool pvc, int64_t k, const vc_opt
   p.num_wg = pl.num_wg;
   p.greedy_slot = pl.max_wg;
   p.cover_stride = pl.cover_stride;
+  p.words = pl.words;
+  if (pl.words) {
+    if ((rc = ensure(ctx, ctx->bits, static_cast<size_t>(n) * pl.words * sizeof(uint64_t)))) return rc;
+    p.bits = static_cast<uint64_t*>(ctx->bits.ptr);
+  }
   DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
   hipStream_t s = ctx->stream;
 
   VC_HIP(ctx, vc::launch_init(p, dres, s));
   VC_HIP(ctx, vc::launch_prepare(p, s));
+  if (pl.words) VC_HIP(ctx, vc::launch_bitset_pack(p, s));
 
   DevResult res{};
   int32_t depth_cap;
@@ -253,7 +287,8 @@ int run_search(vc_ctx* ctx, const vc_graph* g, bool pvc, int64_t k, const vc_opt
   if (!pvc) {
     const int gws = static_cast<int>(std::min<int64_t>(1024, round_up(std::max(n, 1), 64)));
     VC_HIP(ctx, hipEventRecord(ctx->ev[2], s));
-    VC_HIP(ctx, vc::launch_greedy(p, gws, dres, s));
+    if (pl.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, dres, s));
+    else VC_HIP(ctx, vc::launch_greedy(p, gws, dres, s));
     VC_HIP(ctx, hipEventRecord(ctx->ev[3], s));
     VC_HIP(ctx, hipMemcpyAsync(&res, dres, sizeof res, hipMemcpyDeviceToHost, s));
     VC_HIP(ctx, hipStreamSynchronize(s));
@@ -287,7 +322,9 @@ int run_search(vc_ctx* ctx, const vc_graph* g, bool pvc, int64_t k, const vc_opt
   p.num_wg = pl.num_wg;
 
   VC_HIP(ctx, hipEventRecord(ctx->ev[0], s));
-  VC_HIP(ctx, vc::launch_traverse(pvc, o && (o->flags & VC_OPT_PROFILE), p, pl.wg_size, s));
+  const bool prof = o && (o->flags & VC_OPT_PROFILE);
+  if (pl.words) VC_HIP(ctx, vc::launch_bitset_traverse(pvc, prof, p, s));
+  else VC_HIP(ctx, vc::launch_traverse(pvc, prof, p, pl.wg_size, s));
   VC_HIP(ctx, hipEventRecord(ctx->ev[1], s));
   uint8_t* cover_dst = cover_dev ? cover_dev : static_cast<uint8_t*>(ctx->cover_tmp.ptr);
   VC_HIP(ctx, vc::launch_finalize(pvc, p, cover_dst, dres, s));
@@ -336,6 +373,8 @@ int run_search(vc_ctx* ctx, const vc_graph* g, bool pvc, int64_t k, const vc_opt
     stats->wl_threshold = static_cast<int32_t>(pl.threshold);
     stats->depth_cap = depth_cap;
     stats->n = n;
+    stats->bitset_words = pl.words;
+    stats->node_bytes = pl.words ? 8 * pl.words + 8 : 4 * (n + 2);
     stats->kernel_ms = kernel_ms;
     for (int a = 0; a < vc::kNumActivities; ++a) stats->cycles[a] = res.cycles[a];
     stats->greedy_ms = greedy_ms;
@@ -390,9 +429,11 @@ int solve(vc_ctx* ctx, const vc_graph* g, bool device_graph, bool pvc, int64_t k
 }
 
 // Validate a device CSR and stage its root node for a one-workgroup kernel (greedy, reduce).
-int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, Params& p) {
+int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, Params& p) {
   Plan pl;
-  int rc = plan_launch(ctx, false, g->n, nullptr, pl);
+  vc_options o{};
+  o.flags = flags & (VC_OPT_DEGREE_ARRAYS | VC_OPT_BITSETS);
+  int rc = plan_launch(ctx, false, g->n, &o, pl);
   if (rc) return rc;
   if ((rc = ensure(ctx, ctx->payload, static_cast<size_t>(pl.stride) * sizeof(int32_t)))) return rc;
   if ((rc = ensure(ctx, ctx->seq, sizeof(uint32_t)))) return rc;
@@ -412,9 +453,15 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, Params& p) {
   p.covers = static_cast<uint8_t*>(ctx->covers.ptr);
   p.q_cap = 1;
   p.cover_stride = pl.cover_stride;
+  p.words = pl.words;
+  if (pl.words) {
+    if ((rc = ensure(ctx, ctx->bits, static_cast<size_t>(g->n) * pl.words * sizeof(uint64_t)))) return rc;
+    p.bits = static_cast<uint64_t*>(ctx->bits.ptr);
+  }
   DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
   VC_HIP(ctx, vc::launch_init(p, dres, ctx->stream));
   VC_HIP(ctx, vc::launch_prepare(p, ctx->stream));
+  if (pl.words) VC_HIP(ctx, vc::launch_bitset_pack(p, ctx->stream));
   return VC_OK;
 }
 
@@ -473,7 +520,7 @@ int vc_destroy(vc_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,       &ctx->payload, &ctx->seq,
                     &ctx->ctr,    &ctx->stacks,   &ctx->covers,  &ctx->wg_stats,
-                    &ctx->result, &ctx->cover_tmp, &ctx->scratch_s};
+                    &ctx->result, &ctx->cover_tmp, &ctx->scratch_s, &ctx->bits};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   for (hipEvent_t ev : ctx->ev)
@@ -514,11 +561,12 @@ int vc_greedy_device(vc_ctx* ctx, const vc_graph* g, int32_t* size_out, uint8_t*
     return VC_OK;
   }
   Params p{};
-  if ((rc = setup_single(ctx, g, vc::kRulesAll, p))) return rc;
+  if ((rc = setup_single(ctx, g, vc::kRulesAll, 0, p))) return rc;
   DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
   hipStream_t s = ctx->stream;
   const int gws = static_cast<int>(std::min<int64_t>(1024, round_up(n, 64)));
-  VC_HIP(ctx, vc::launch_greedy(p, gws, dres, s));
+  if (p.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, dres, s));
+  else VC_HIP(ctx, vc::launch_greedy(p, gws, dres, s));
   DevResult res{};
   VC_HIP(ctx, hipMemcpyAsync(&res, dres, sizeof res, hipMemcpyDeviceToHost, s));
   VC_HIP(ctx, hipStreamSynchronize(s));
@@ -546,14 +594,15 @@ int vc_reduce_device(vc_ctx* ctx, const vc_graph* g, int32_t* deg_dev, int32_t* 
   const int32_t n = g->n;
   if (n == 0) return VC_OK;
   Params p{};
-  if ((rc = setup_single(ctx, g, rules_from_flags(flags), p))) return rc;
+  if ((rc = setup_single(ctx, g, rules_from_flags(flags), flags, p))) return rc;
   if ((rc = ensure(ctx, ctx->scratch_s, sizeof(int32_t)))) return rc;
   DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
   hipStream_t s = ctx->stream;
   int32_t* sdev = static_cast<int32_t*>(ctx->scratch_s.ptr);
   VC_HIP(ctx, hipMemcpyAsync(sdev, s_inout, sizeof(int32_t), hipMemcpyHostToDevice, s));
   const int ws = static_cast<int>(std::min<int64_t>(1024, round_up(n, 64)));
-  VC_HIP(ctx, vc::launch_reduce(p, ws, deg_dev, sdev, bound, dres, s));
+  if (p.words) VC_HIP(ctx, vc::launch_bitset_reduce(p, deg_dev, sdev, bound, dres, s));
+  else VC_HIP(ctx, vc::launch_reduce(p, ws, deg_dev, sdev, bound, dres, s));
   DevResult res{};
   int32_t s_new = 0;
   VC_HIP(ctx, hipMemcpyAsync(&res, dres, sizeof res, hipMemcpyDeviceToHost, s));

@@ -80,6 +80,9 @@ struct Params {
   int32_t num_wg;
   int32_t cover_stride;
   int32_t greedy_slot;  // cover buffer index of the greedy's cover
+  uint64_t* bits;       // bitset kernels: adjacency rows, n * words 64-bit words
+  int32_t words;        // bitset kernels: 64-bit words per row; 0 selects the degree-array kernels
+  int32_t pad;
 };
 
 // Result block written by the finalize kernel and copied to the host once.
@@ -117,6 +120,17 @@ hipError_t launch_finalize(bool pvc, const Params& p, uint8_t* cover_out, DevRes
                            hipStream_t stream);
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
                          int64_t bound, DevResult* res, hipStream_t stream);
+
+// Bitset kernels (vc_bitset.hip), graphs of at most kMaxBitsetN vertices.
+constexpr int kMaxBitsetN = 256;
+hipError_t launch_bitset_pack(const Params& p, hipStream_t stream);
+hipError_t launch_bitset_greedy(const Params& p, DevResult* res, hipStream_t stream);
+hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStream_t stream);
+hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,
+                                DevResult* res, hipStream_t stream);
+hipError_t bitset_occupancy(int words, bool pvc, bool prof, int n, int* blocks_per_cu);
+size_t bitset_lds_bytes(int n, int words);
+int bitset_stride(int words);
 
 // Resident workgroups per CU for the traversal kernel at this size (occupancy API).
 hipError_t traverse_occupancy(bool pvc, bool prof, int32_t wg_size, size_t lds_bytes,

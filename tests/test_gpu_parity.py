@@ -36,9 +36,17 @@ def solver(torch_cuda):
     s.close()
 
 
-def single_wg():
+KERNELS = {"bitsets": 0x40, "degree_arrays": 0x20}
+
+
+def single_wg(flags=0):
     import paper_2204_10402_amd as vc
-    return vc.Options(num_wg=1, wl_threshold=-1)
+    return vc.Options(num_wg=1, wl_threshold=-1, flags=flags)
+
+
+def opts(**kw):
+    import paper_2204_10402_amd as vc
+    return vc.Options(**kw)
 
 
 def check_cover(g, cover, size):
@@ -56,18 +64,21 @@ def golden():
 
 # ---- small graphs: answers, covers and node counts ----------------------------------------
 
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
 @pytest.mark.parametrize("seed", range(40))
-def test_small_mvc_and_pvc(solver, oracle_lib, seed):
+def test_small_mvc_and_pvc(solver, oracle_lib, seed, kernel):
     n = 5 + seed % 14
     g = G.random_small(n, 20000 + seed) if seed % 2 else G.erdos_renyi(n, 0.3, 20000 + seed)
     tau, _ = oracle.tau_by_definition(g)
-    r = solver.mvc(g)
+    o = opts(flags=KERNELS[kernel])
+    r = solver.mvc(g, o)
     assert r.size == tau
+    assert (r.stats["bitset_words"] > 0) == (kernel == "bitsets")
     check_cover(g, r.cover, tau)
     for k in (max(tau - 2, 0), tau - 1, tau, tau + 1):
         if k < 0:
             continue
-        p = solver.pvc(g, k)
+        p = solver.pvc(g, k, o)
         assert p.yes == (k >= tau)
         if p.yes:
             check_cover(g, p.cover, p.size)
@@ -76,17 +87,18 @@ def test_small_mvc_and_pvc(solver, oracle_lib, seed):
             assert p.size == -1 and int(p.cover.sum()) == 0
 
 
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
 @pytest.mark.parametrize("seed", range(12))
-def test_single_workgroup_node_parity(solver, oracle_lib, seed):
+def test_single_workgroup_node_parity(solver, oracle_lib, seed, kernel):
     """One workgroup that never donates visits the oracle's tree in the oracle's order."""
     g = G.erdos_renyi(30 + 7 * seed, 0.12 + 0.01 * (seed % 5), 300 + seed)
     o = oracle.mvc(g)
-    r = solver.mvc(g, single_wg())
+    r = solver.mvc(g, single_wg(KERNELS[kernel]))
     assert (r.size, r.stats["nodes"], r.stats["greedy_size"]) == (o.size, o.nodes, o.greedy)
     check_cover(g, r.cover, o.size)
     for k in (o.size - 1, o.size):
         op = oracle.pvc(g, k)
-        gp = solver.pvc(g, k, single_wg())
+        gp = solver.pvc(g, k, single_wg(KERNELS[kernel]))
         assert (gp.yes, gp.stats["nodes"]) == (op.yes, op.nodes)
 
 
@@ -100,10 +112,13 @@ def test_c1_er60(solver, oracle_lib):
     assert r.stats["greedy_size"] == o.greedy
     one = solver.mvc(g, single_wg())
     assert one.stats["nodes"] == o.nodes
+    arr = solver.mvc(g, opts(flags=KERNELS["degree_arrays"]))
+    assert arr.size == o.size
 
 
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
 @pytest.mark.parametrize("rules", [0x1, 0x2, 0x4, 0x8, 0x3])
-def test_ablation_flags(solver, oracle_lib, rules):
+def test_ablation_flags(solver, oracle_lib, rules, kernel):
     """Switching rules off leaves tau unchanged; single-workgroup node counts follow the
     oracle with the same rules switched off."""
     import paper_2204_10402_amd as vc
@@ -119,9 +134,9 @@ def test_ablation_flags(solver, oracle_lib, rules):
     for seed in range(4):
         g = G.erdos_renyi(40, 0.12, 700 + seed)
         o = oracle.mvc(g, rules=mask)
-        r = solver.mvc(g, vc.Options(num_wg=1, wl_threshold=-1, flags=rules))
+        r = solver.mvc(g, vc.Options(num_wg=1, wl_threshold=-1, flags=rules | KERNELS[kernel]))
         assert (r.size, r.stats["nodes"]) == (o.size, o.nodes)
-        assert solver.mvc(g, vc.Options(flags=rules)).size == o.size
+        assert solver.mvc(g, vc.Options(flags=rules | KERNELS[kernel])).size == o.size
 
 
 # ---- reduction rules and greedy: vertex-by-vertex parity --------------------------------
@@ -139,11 +154,14 @@ def random_consistent_state(g, rng, frac):
     return deg, int(removed.sum())
 
 
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
 @pytest.mark.parametrize("seed", range(30))
-def test_reduce_fixpoint_parity(solver, oracle_lib, torch_cuda, seed):
+def test_reduce_fixpoint_parity(solver, oracle_lib, torch_cuda, seed, kernel):
     torch = torch_cuda
     rng = np.random.default_rng(900 + seed)
-    n = [12, 40, 63, 64, 65, 130, 200, 700][seed % 8]
+    n = [12, 40, 63, 64, 65, 130, 200, 256, 700][seed % 9]
+    if kernel == "bitsets" and n > 256:
+        n = 193
     g = G.random_small(n, 900 + seed) if n <= 40 else G.erdos_renyi(n, float(rng.uniform(0.02, 0.1)), seed)
     deg, s = random_consistent_state(g, rng, float(rng.uniform(0.0, 0.4)))
     rp = torch.from_numpy(g.row_ptr).cuda()
@@ -159,7 +177,7 @@ def test_reduce_fixpoint_parity(solver, oracle_lib, torch_cuda, seed):
             mask &= ~(oracle.RULE_HIGH | oracle.PRUNE_EDGES)
         od, os_ = oracle.reduce(g, deg, s, bound, mask)
         dd = torch.from_numpy(deg.copy()).cuda()
-        gs = solver.reduce_device(rp, ci, dd, s, bound, flags)
+        gs = solver.reduce_device(rp, ci, dd, s, bound, flags | KERNELS[kernel])
         assert gs == os_, (bound, flags)
         assert np.array_equal(dd.cpu().numpy(), od), (bound, flags)
 
@@ -229,6 +247,17 @@ def test_hard_mvc_full_size(solver, oracle_lib, workload, seed):
     assert r.stats["nodes"] > 0
 
 
+@pytest.mark.parametrize("workload,seed", [("mvc_reg120", 1), ("mvc_er150", 7)])
+def test_hard_mvc_degree_arrays(solver, oracle_lib, workload, seed):
+    """The degree-array kernels on two of the hard instances (the bitset kernels run them by
+    default)."""
+    want = {(r["workload"], r["seed"]): r for r in golden()}[(workload, seed)]
+    g = G.random_regular(120, 5, seed) if workload == "mvc_reg120" else G.erdos_renyi(150, 0.08, seed)
+    r = solver.mvc(g, opts(flags=KERNELS["degree_arrays"]))
+    assert r.size == want["size"] and r.stats["bitset_words"] == 0
+    check_cover(g, r.cover, want["size"])
+
+
 def test_hard_pvc_no_node_parity(solver, oracle_lib):
     """PVC k = tau - 1 (no instance): every workgroup schedule visits the same tree."""
     want = {(r["workload"], r["seed"]): r for r in golden()}[("mvc_reg120", 3)]
@@ -237,6 +266,8 @@ def test_hard_pvc_no_node_parity(solver, oracle_lib):
     r = solver.pvc(g, want["size"] - 1)
     assert not o.yes and not r.yes
     assert r.stats["nodes"] == o.nodes
+    r2 = solver.pvc(g, want["size"] - 1, opts(flags=KERNELS["degree_arrays"]))
+    assert not r2.yes and r2.stats["nodes"] == o.nodes
     y = solver.pvc(g, want["size"])
     assert y.yes and y.size <= want["size"]
     check_cover(g, y.cover, y.size)
@@ -334,24 +365,28 @@ def test_node_budget(solver, oracle_lib):
 def test_bad_options(solver):
     import paper_2204_10402_amd as vc
     for o in (vc.Options(wg_size=100), vc.Options(num_wg=-1), vc.Options(flags=0x100),
-              vc.Options(wl_threshold=-2)):
+              vc.Options(wl_threshold=-2), vc.Options(flags=0x60), vc.Options(wg_size=128)):
         with pytest.raises(vc.VCError) as ei:
             solver.mvc(G.path(4), o)
         assert ei.value.code == vc.ERR_INVALID_ARG
+    with pytest.raises(vc.VCError) as ei:
+        solver.mvc(G.path(300), vc.Options(flags=vc.OPT_BITSETS))
+    assert ei.value.code == vc.ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("opts", [dict(wl_capacity=1), dict(wl_capacity=1, wl_threshold=1),
-                                  dict(num_wg=3), dict(num_wg=7, wl_threshold=1),
-                                  dict(wg_size=128), dict(wg_size=256, num_wg=64),
-                                  dict(wg_size=1024)])
-def test_launch_knobs_keep_answers(solver, oracle_lib, opts):
+@pytest.mark.parametrize("knobs", [dict(wl_capacity=1), dict(wl_capacity=1, wl_threshold=1),
+                                   dict(num_wg=3), dict(num_wg=7, wl_threshold=1),
+                                   dict(wg_size=128, flags=0x20), dict(wg_size=256, num_wg=64, flags=0x20),
+                                   dict(wg_size=1024, flags=0x20), dict(num_wg=5, flags=0x20),
+                                   dict(wl_capacity=1, flags=0x20)])
+def test_launch_knobs_keep_answers(solver, oracle_lib, knobs):
     import paper_2204_10402_amd as vc
     g = G.erdos_renyi(90, 0.1, 5)
     o = oracle.mvc(g)
-    r = solver.mvc(g, vc.Options(**opts))
+    r = solver.mvc(g, vc.Options(**knobs))
     assert r.size == o.size
     check_cover(g, r.cover, o.size)
-    pn = solver.pvc(g, o.size - 1, vc.Options(**opts))
+    pn = solver.pvc(g, o.size - 1, vc.Options(**knobs))
     assert not pn.yes and pn.stats["nodes"] == oracle.pvc(g, o.size - 1).nodes
 
 
@@ -389,5 +424,7 @@ def test_profiled_kernel_same_answers(solver, oracle_lib):
     assert sum(v for k, v in cyc.items() if k != "total") <= cyc["total"]
     one = solver.mvc(g, vc.Options(num_wg=1, wl_threshold=-1, flags=vc.OPT_PROFILE))
     assert one.stats["nodes"] == o.nodes
+    arr = solver.mvc(g, vc.Options(num_wg=1, wl_threshold=-1, flags=vc.OPT_PROFILE | 0x20))
+    assert arr.stats["nodes"] == o.nodes and arr.stats["cycles"]["reduce"] > 0
     plain = solver.mvc(g)
     assert all(v == 0 for v in plain.stats["cycles"].values())
