@@ -112,8 +112,10 @@ typedef struct {
    * [0] taking nodes (stack pops, worklist dequeues, waiting for work), [1] reduction rules,
    * [2] branching (max-degree pass, stopping test, removing v_max or N(v_max)),
    * [3] deferring children (stack pushes, worklist enqueues), [4] other (flags, bound,
-   * recording covers), [5] the whole kernel. Zero without VC_OPT_PROFILE. */
-  int64_t cycles[6];
+   * recording covers), [5] the whole kernel; with the degree-array kernels [1] is split into
+   * [6] degree-one decisions, [7] degree-two-triangle decisions, [8] high-degree decisions,
+   * [9] removing the decided vertices. Zero without VC_OPT_PROFILE. */
+  int64_t cycles[10];
 } vc_stats;
 
 /* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to run on, or NULL

@@ -28,7 +28,8 @@ OPT_NO_EDGE_PRUNE = 0x8
 OPT_PROFILE = 0x10
 OPT_DEGREE_ARRAYS = 0x20
 OPT_BITSETS = 0x40
-ACTIVITIES = ("acquire", "reduce", "branch", "donate", "other", "total")
+ACTIVITIES = ("acquire", "reduce", "branch", "donate", "other", "total",
+              "reduce_deg1", "reduce_tri", "reduce_high", "reduce_apply")
 
 # Every function include/vc.h declares.
 EXPORTS = (
@@ -61,7 +62,7 @@ class _Stats(ctypes.Structure):
                 ("n", ctypes.c_int32), ("bitset_words", ctypes.c_int32),
                 ("node_bytes", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
                 ("greedy_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("cycles", ctypes.c_int64 * 6)]
+                ("cycles", ctypes.c_int64 * 10)]
 
 
 @dataclass

@@ -681,9 +681,9 @@ hipError_t launch_bitset_greedy(const Params& p, DevResult* res, hipStream_t str
 hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStream_t stream) {
   Params args = p;
   void* kargs[] = {&args};
-  return hipLaunchCooperativeKernel(bitset_fn(p.words, pvc, prof), dim3(p.num_wg), dim3(64),
-                                    kargs, static_cast<unsigned int>(bitset_lds_bytes(p.n, p.words)),
-                                    stream);
+  // plain launch; see launch_traverse for why co-residency is not required
+  return hipLaunchKernel(bitset_fn(p.words, pvc, prof), dim3(p.num_wg), dim3(64), kargs,
+                         bitset_lds_bytes(p.n, p.words), stream);
 }
 
 hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,

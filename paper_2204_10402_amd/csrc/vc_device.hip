@@ -51,15 +51,35 @@ struct Node {
   int n;
   const int32_t* __restrict__ rp;
   const int32_t* __restrict__ ci;
+  int32_t* heads;  // 64 LDS words per wavefront for wave_expand_rows
 };
+
+// Inclusive max-scan over the 64 lanes (DPP, as wave_incl_scan), identity -1.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t dpp_or_minus1(int32_t x) {
+  return __builtin_amdgcn_update_dpp(-1, x, CTRL, ROW_MASK, 0xF, false);
+}
+__device__ __forceinline__ int32_t wave_incl_max(int32_t x) {
+  x = max(x, dpp_or_minus1<0x111, 0xF>(x));
+  x = max(x, dpp_or_minus1<0x112, 0xF>(x));
+  x = max(x, dpp_or_minus1<0x114, 0xF>(x));
+  x = max(x, dpp_or_minus1<0x118, 0xF>(x));
+  x = max(x, dpp_or_minus1<0x142, 0xA>(x));
+  x = max(x, dpp_or_minus1<0x143, 0xC>(x));
+  return x;
+}
 
 // Walk the CSR rows [beg, end) held by the lanes of a wavefront (empty where beg >= end) as one
 // list, 64 consecutive entries per step, so rows of any length keep every lane busy and
-// neighbouring lanes read neighbouring entries. fn(j, tag) runs for entry j, with `tag` the
-// value the row's owner lane passed in. Eight steps are issued together to keep several loads
-// in flight. All cross-lane moves happen in uniform control flow.
+// neighbouring lanes read neighbouring entries. fn(x, tag) runs for every entry x = ci[j], with
+// `tag` the value the row's owner lane passed in. The owner of each entry of a step comes from
+// head flags: every row writes its lane into `heads` (this wavefront's 64 LDS words) at its
+// first position in the step, and a max-scan over the lanes carries it forward. Eight steps
+// are issued together, with unconditional loads (an index past the list reads entry 0, whose
+// value is discarded), so eight loads are in flight before the first is used.
 template <typename Fn>
-__device__ __forceinline__ void wave_expand_rows(int beg, int end, int tag, Fn fn) {
+__device__ __forceinline__ void wave_expand_rows(const int32_t* __restrict__ ci, int32_t* heads,
+                                                 int beg, int end, int tag, Fn fn) {
   const int lane = lane_id();
   const int len = end > beg ? end - beg : 0;
   const int incl = wave_incl_scan(len);
@@ -67,27 +87,31 @@ __device__ __forceinline__ void wave_expand_rows(int beg, int end, int tag, Fn f
   const int total = __builtin_amdgcn_readlane(incl, 63);
   constexpr int kUnroll = 8;
   for (int t0 = 0; t0 < total; t0 += 64 * kUnroll) {
-    int js[kUnroll], tags[kUnroll];
+    int xs[kUnroll], tags[kUnroll];
+    bool ok[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      js[u] = -1;
-      if (t0 + u * 64 < total) {  // uniform: only as many steps as the rows need
-        const int t = t0 + u * 64 + lane;
-        int i = 0;  // largest lane with excl <= t: the owner, whose row is not empty
-#pragma unroll
-        for (int step = 32; step > 0; step >>= 1) {
-          const int probe = shfl(excl, i + step);
-          i += probe <= t ? step : 0;
-        }
-        const int ob = shfl(beg, i);
-        const int oe = shfl(excl, i);
-        tags[u] = shfl(tag, i);
-        if (t < total) js[u] = ob + (t - oe);
+      ok[u] = false;
+      const int s0 = t0 + u * 64;
+      if (s0 < total) {  // uniform: only as many steps as the rows need
+        heads[lane] = -1;
+        __builtin_amdgcn_wave_barrier();
+        if (len > 0 && excl < s0 + 64 && incl > s0) heads[excl > s0 ? excl - s0 : 0] = lane;
+        __builtin_amdgcn_wave_barrier();
+        const int i = wave_incl_max(heads[lane]);  // owner of entry s0 + lane
+        __builtin_amdgcn_wave_barrier();
+        const int t = s0 + lane;
+        const int src = i < 0 ? 0 : i;  // i < 0 only past the end of the list
+        const int ob = shfl(beg, src);
+        const int oe = shfl(excl, src);
+        tags[u] = shfl(tag, src);
+        ok[u] = t < total;
+        xs[u] = ci[ok[u] ? ob + (t - oe) : 0];  // not read until every step has issued
       }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
-      if (js[u] >= 0) fn(js[u], tags[u]);
+      if (ok[u]) fn(xs[u], tags[u]);
   }
 }
 
@@ -122,15 +146,15 @@ __device__ __forceinline__ void for_each_batch(const int32_t* st, int n, Pred pr
 // Remove every marked vertex (paper §IV-B): each live unmarked neighbour of a marked vertex
 // loses one degree per marked neighbour, then marked vertices become kSent and s grows by
 // their number. Called right after a barrier that ends a decide step.
-__device__ void apply_marks(const Node& nd) {
+__device__ void apply_marks(const Node nd) {
   const int n = nd.n;
   int32_t* st = nd.st;
   for_each_batch(st, n, [](int, int32_t d) { return d >= 0 && (d & kFlag); },
                  [&](int f, int count) {
                    const bool mine = lane_id() < count;
-                   wave_expand_rows(mine ? nd.rp[f] : 0, mine ? nd.rp[f + 1] : 0, f,
-                                    [&](int j, int) {
-                                      const int x = nd.ci[j];
+                   wave_expand_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[f] : 0,
+                                    mine ? nd.rp[f + 1] : 0, f,
+                                    [&](int x, int) {
                                       const int32_t dx = st[x];
                                       if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
                                     });
@@ -153,14 +177,14 @@ __device__ void apply_marks(const Node& nd) {
 // degree-one vertices only the smaller id is removed, and a shared neighbour once (§IV-D).
 // The rows of all degree-one vertices are walked together; the one live entry of a row names
 // u, and the lane that reads it makes the decision for that row's owner.
-__device__ void decide_degree_one(const Node& nd, Ctrl& c, int epoch) {
+__device__ void decide_degree_one(const Node nd, Ctrl& c, int epoch) {
   int32_t* st = nd.st;
   for_each_batch(st, nd.n, [](int, int32_t d) { return d >= 0 && (d & kDegMask) == 1; },
                  [&](int cv, int count) {
                    const bool mine = lane_id() < count;
-                   wave_expand_rows(mine ? nd.rp[cv] : 0, mine ? nd.rp[cv + 1] : 0, cv,
-                                    [&](int j, int v) {
-                                      const int u = nd.ci[j];
+                   wave_expand_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[cv] : 0,
+                                    mine ? nd.rp[cv + 1] : 0, cv,
+                                    [&](int u, int v) {
                                       const int32_t du = st[u];
                                       if (du < 0) return;  // not the live neighbour of v
                                       if ((du & kDegMask) != 1 || u < v) {
@@ -203,7 +227,7 @@ __device__ __forceinline__ bool row_contains(const int32_t* __restrict__ ci, int
 // Each lane takes one degree-two vertex: it finds the two live neighbours in its own row (rows
 // longer than kLaneRow are searched by the whole wavefront), then searches the shorter of the
 // two neighbours' rows for the other.
-__device__ void decide_triangle(const Node& nd, Ctrl& c, int epoch) {
+__device__ void decide_triangle(const Node nd, Ctrl& c, int epoch) {
   constexpr int kLaneRow = 32;
   int32_t* st = nd.st;
   const int lane = lane_id();
@@ -263,7 +287,7 @@ __device__ void decide_triangle(const Node& nd, Ctrl& c, int epoch) {
 
 // High-degree rule (§II-B): a vertex whose degree exceeds r = bound - s is in every cover of
 // size <= bound (bound = best - 1 for MVC, k for PVC).
-__device__ void decide_high_degree(const Node& nd, Ctrl& c, int epoch, int64_t r) {
+__device__ void decide_high_degree(const Node nd, Ctrl& c, int epoch, int64_t r) {
   int32_t* st = nd.st;
   for (int v = threadIdx.x; v < nd.n; v += blockDim.x) {
     const int32_t d = st[v];
@@ -274,9 +298,16 @@ __device__ void decide_high_degree(const Node& nd, Ctrl& c, int epoch, int64_t r
   }
 }
 
+// No-op activity clock for the uninstrumented callers.
+struct NoClock {
+  __device__ void charge(int) {}
+};
+
 // The reduction rules until the graph stops changing (§II-B, §IV-D), or until s > bound.
 // Precondition: the node in LDS is consistent and visible to the whole workgroup.
-__device__ void reduce_node(const Node& nd, Ctrl& c, int64_t bound, int rules, int& epoch) {
+template <typename Clock>
+__device__ void reduce_node(const Node nd, Ctrl& c, int64_t bound, int rules, int& epoch,
+                            Clock& clk) {
   const int n = nd.n;
   int32_t* st = nd.st;
   for (;;) {
@@ -286,8 +317,10 @@ __device__ void reduce_node(const Node& nd, Ctrl& c, int64_t bound, int rules, i
       ++epoch;
       decide_degree_one(nd, c, epoch);
       __syncthreads();
+      clk.charge(kActDeg1);
       if (c.flag_epoch == epoch) {
         apply_marks(nd);
+        clk.charge(kActApply);
         if (st[n] > bound) return;
       }
     }
@@ -295,8 +328,10 @@ __device__ void reduce_node(const Node& nd, Ctrl& c, int64_t bound, int rules, i
       ++epoch;
       decide_triangle(nd, c, epoch);
       __syncthreads();
+      clk.charge(kActTri);
       if (c.flag_epoch == epoch) {
         apply_marks(nd);
+        clk.charge(kActApply);
         if (st[n] > bound) return;
       }
     }
@@ -304,15 +339,24 @@ __device__ void reduce_node(const Node& nd, Ctrl& c, int64_t bound, int rules, i
       ++epoch;
       decide_high_degree(nd, c, epoch, bound - st[n]);
       __syncthreads();
-      if (c.flag_epoch == epoch) apply_marks(nd);
+      clk.charge(kActHigh);
+      if (c.flag_epoch == epoch) {
+        apply_marks(nd);
+        clk.charge(kActApply);
+      }
     }
     if (st[n] == s0) return;
   }
 }
 
+__device__ void reduce_node(const Node nd, Ctrl& c, int64_t bound, int rules, int& epoch) {
+  NoClock none;
+  reduce_node(nd, c, bound, rules, epoch, none);
+}
+
 // One pass over the degree array: the sum of live degrees (= 2|E|) and the live vertex of
 // maximum degree, smallest id on ties (§IV-B). Results are the same in every thread.
-__device__ void max_degree_and_sum(const Node& nd, Ctrl& c, int& vmax, int& dmax,
+__device__ void max_degree_and_sum(const Node nd, Ctrl& c, int& vmax, int& dmax,
                                    int32_t& degsum) {
   const int n = nd.n;
   const int32_t* st = nd.st;
@@ -346,7 +390,7 @@ __device__ void max_degree_and_sum(const Node& nd, Ctrl& c, int& vmax, int& dmax
 }
 
 // Mark every live neighbour of v (the "N(v) in the cover" child, §II-B) and remove them.
-__device__ void remove_neighbourhood(const Node& nd, int v) {
+__device__ void remove_neighbourhood(const Node nd, int v) {
   int32_t* st = nd.st;
   const int lane = lane_id();
   if (wave_id() == 0) {
@@ -361,7 +405,7 @@ __device__ void remove_neighbourhood(const Node& nd, int v) {
 }
 
 // Mark v alone (the "v in the cover" child, §II-B) and remove it.
-__device__ void remove_vertex(const Node& nd, int v) {
+__device__ void remove_vertex(const Node nd, int v) {
   if (threadIdx.x == 0) nd.st[v] |= kFlag;
   __syncthreads();
   apply_marks(nd);
@@ -387,6 +431,17 @@ __device__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int str
   }
 }
 
+// The row pointers a kernel reads: a copy in LDS right after the node when the host found room
+// for it (one LDS access instead of an L2 round trip at the head of every row walk), else the
+// input array itself. Whole workgroup; ends with a barrier.
+__device__ const int32_t* stage_row_ptr(const Params& p, int32_t* st) {
+  if (!p.rp_lds) return p.rp;
+  int32_t* dst = st + p.stride;
+  for (int i = threadIdx.x; i <= p.n; i += blockDim.x) dst[i] = p.rp[i];
+  __syncthreads();
+  return dst;
+}
+
 // Copy a stored node between two device-memory slots with the same thread-to-word mapping as
 // node_store / node_load, so each thread reads back words it wrote itself.
 __device__ void node_copy(int32_t* __restrict__ dst, const int32_t* __restrict__ src, int stride) {
@@ -404,7 +459,7 @@ __device__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stri
 // Whole workgroup: donate a deferred child to the worklist; true if the worklist took it. The
 // child is the stored node at `oldest` (the bottom of this workgroup's stack) when that is not
 // null, else the node in LDS with `pending` as its branch vertex.
-__device__ bool try_enqueue(const Params& p, const Node& nd, Ctrl& c, int pending,
+__device__ bool try_enqueue(const Params& p, const Node nd, Ctrl& c, int pending,
                             const int32_t* oldest) {
   if (!enqueue_begin(p, c)) return false;
   int32_t* dst = p.payload + static_cast<size_t>(c.slot) * p.stride;
@@ -416,7 +471,7 @@ __device__ bool try_enqueue(const Params& p, const Node& nd, Ctrl& c, int pendin
 
 // Whole workgroup: take a node from the worklist into LDS. Returns 1 on success, 0 when the
 // whole search is finished, -1 when it is being stopped.
-__device__ int dequeue(const Params& p, const Node& nd, Ctrl& c) {
+__device__ int dequeue(const Params& p, const Node nd, Ctrl& c) {
   const int status = dequeue_begin(p, c);
   if (status != 1) return status;
   node_load(nd.st, p.payload + static_cast<size_t>(c.slot) * p.stride, p.stride);
@@ -504,6 +559,7 @@ __global__ void prepare_kernel(Params p) {
 __global__ void __launch_bounds__(1024) greedy_kernel(Params p, DevResult* res) {
   extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
+  __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = reinterpret_cast<int32_t*>(lds4);
   if (threadIdx.x == 0) {
     const int32_t err_row = load_relaxed(ctr_i32(p, kErrRow));
@@ -515,7 +571,7 @@ __global__ void __launch_bounds__(1024) greedy_kernel(Params p, DevResult* res) 
   }
   __syncthreads();
   if (c.err) return;
-  const Node nd{st, p.n, p.rp, p.ci};
+  const Node nd{st, p.n, stage_row_ptr(p, st), p.ci, heads};
   node_load(st, p.payload, p.stride);  // the root written by prepare_kernel
   __syncthreads();
   int epoch = 0;
@@ -543,12 +599,11 @@ template <bool PVC, bool PROF>
 __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
+  __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = reinterpret_cast<int32_t*>(lds4);
   const int n = p.n;
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
-  const Node nd{st, n, p.rp, p.ci};
-
   if (tid == 0) {
     c.err = load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF ||
             load_relaxed(ctr_i32(p, kEdges0)) == 0;
@@ -559,6 +614,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     if (tid == 0) p.wg_stats[wg] = WgStats{};
     return;
   }
+  const Node nd{st, n, stage_row_ptr(p, st), p.ci, heads};
   ActivityClock<PROF> clk;
   clk.begin();
 
@@ -624,7 +680,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
 
     const int64_t bound = PVC ? p.k : static_cast<int64_t>(c.best) - 1;
     clk.charge(kActOther);
-    reduce_node(nd, c, bound, p.rules, epoch);
+    reduce_node(nd, c, bound, p.rules, epoch, clk);
     clk.charge(kActReduce);
 
     // stopping condition (§II-B): no cover of size <= bound below this node if r < 0 or
@@ -766,6 +822,14 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
       }
     }
   }
+  bad = wave_sum(bad);
+  ones = wave_sum(ones);
+  if (lane_id() == 0) {
+    if (bad) atomicAdd(&res->uncovered, bad);
+    if (ones) atomicAdd(&res->cover_count, ones);
+  }
+  // per-workgroup statistics: only the blocks that cover workgroup slots
+  if (static_cast<int>(blockIdx.x) * static_cast<int>(blockDim.x) >= p.num_wg) return;
   int64_t nodes = 0, pushes = 0, pops = 0, enq = 0, deq = 0, mx = 0, mn = INT64_MAX, depth = 0;
   int64_t cyc[kNumActivities] = {};
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < p.num_wg; w += gridDim.x * blockDim.x) {
@@ -783,8 +847,6 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
   auto add = [](int64_t x, int64_t y) { return x + y; };
   auto hi = [](int64_t x, int64_t y) { return x > y ? x : y; };
   auto lo = [](int64_t x, int64_t y) { return x < y ? x : y; };
-  bad = static_cast<int32_t>(block_reduce_256(bad, buf, add));
-  ones = static_cast<int32_t>(block_reduce_256(ones, buf, add));
   nodes = block_reduce_256(nodes, buf, add);
   pushes = block_reduce_256(pushes, buf, add);
   pops = block_reduce_256(pops, buf, add);
@@ -796,8 +858,6 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
   for (int a = 0; a < kNumActivities; ++a) cyc[a] = block_reduce_256(cyc[a], buf, add);
   if (threadIdx.x == 0) {
     using ull = unsigned long long;
-    if (bad) atomicAdd(&res->uncovered, bad);
-    if (ones) atomicAdd(&res->cover_count, ones);
     if (nodes) atomicAdd(reinterpret_cast<ull*>(&res->nodes), static_cast<ull>(nodes));
     if (pushes) atomicAdd(reinterpret_cast<ull*>(&res->pushes), static_cast<ull>(pushes));
     if (pops) atomicAdd(reinterpret_cast<ull*>(&res->pops), static_cast<ull>(pops));
@@ -816,6 +876,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, in
                                                       int64_t bound, DevResult* res) {
   extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
+  __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = reinterpret_cast<int32_t*>(lds4);
   if (threadIdx.x == 0) {
     const int32_t err_row = load_relaxed(ctr_i32(p, kErrRow));
@@ -828,7 +889,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, in
     st[v] = v < p.n ? deg[v] : (v == p.n ? *s : (v == p.n + 1 ? -1 : 0));
   if (threadIdx.x == 0) c.flag_epoch = -1;
   __syncthreads();
-  const Node nd{st, p.n, p.rp, p.ci};
+  const Node nd{st, p.n, stage_row_ptr(p, st), p.ci, heads};
   int epoch = 0;
   reduce_node(nd, c, bound, p.rules, epoch);
   for (int v = threadIdx.x; v < p.n; v += blockDim.x) deg[v] = st[v];
@@ -853,7 +914,7 @@ hipError_t launch_prepare(const Params& p, hipStream_t stream) {
 }
 
 hipError_t launch_greedy(const Params& p, int32_t wg_size, DevResult* res, hipStream_t stream) {
-  const size_t lds = static_cast<size_t>(p.stride) * sizeof(int32_t);
+  const size_t lds = node_lds_bytes(p.stride, p.n, p.rp_lds);
   hipLaunchKernelGGL(greedy_kernel, dim3(1), dim3(wg_size), lds, stream, p, res);
   return hipGetLastError();
 }
@@ -865,14 +926,16 @@ static const void* traverse_fn(bool pvc, bool prof) {
               : reinterpret_cast<const void*>(&traverse_kernel<false, false>);
 }
 
+// A plain launch: the grid is sized by the occupancy API so that all workgroups are normally
+// resident together, but the search does not depend on it. A workgroup only ever waits for
+// workgroups that have already taken a worklist ticket (and are therefore running); one that
+// starts late finds either work or a zero outstanding-work counter.
 hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size,
                            hipStream_t stream) {
-  const size_t lds = static_cast<size_t>(p.stride) * sizeof(int32_t);
+  const size_t lds = node_lds_bytes(p.stride, p.n, p.rp_lds);
   Params args = p;
   void* kargs[] = {&args};
-  const void* fn = traverse_fn(pvc, prof);
-  return hipLaunchCooperativeKernel(fn, dim3(p.num_wg), dim3(wg_size), kargs,
-                                    static_cast<unsigned int>(lds), stream);
+  return hipLaunchKernel(traverse_fn(pvc, prof), dim3(p.num_wg), dim3(wg_size), kargs, lds, stream);
 }
 
 hipError_t launch_finalize(bool pvc, const Params& p, uint8_t* cover_out, DevResult* res,
@@ -890,7 +953,7 @@ hipError_t launch_finalize(bool pvc, const Params& p, uint8_t* cover_out, DevRes
 
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
                          int64_t bound, DevResult* res, hipStream_t stream) {
-  const size_t lds = static_cast<size_t>(p.stride) * sizeof(int32_t);
+  const size_t lds = node_lds_bytes(p.stride, p.n, p.rp_lds);
   hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(wg_size), lds, stream, p, deg, s, bound, res);
   return hipGetLastError();
 }

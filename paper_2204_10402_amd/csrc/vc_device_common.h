@@ -297,7 +297,11 @@ struct ActivityClock {
     }
   }
   __device__ void end() {
-    if (PROF) cycles[kActTotal] = clock64() - start;
+    if (PROF) {
+      cycles[kActTotal] = clock64() - start;
+      // the reduction total includes its parts
+      cycles[kActReduce] += cycles[kActDeg1] + cycles[kActTri] + cycles[kActHigh] + cycles[kActApply];
+    }
   }
 };
 

@@ -10,7 +10,9 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 
 #include "vc.h"
 #include "vc_internal.h"
@@ -35,6 +37,8 @@ struct vc_ctx {
   DevBuf rp, ci, payload, seq, ctr, stacks, covers, wg_stats, result, cover_tmp, scratch_s, bits;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   std::string last_error;
+  // occupancy-API answers: (kernel family, pvc, profiled, workgroup size, words, LDS bytes)
+  std::map<std::tuple<int, int, int, int, int, size_t>, int> occupancy;
 };
 
 namespace {
@@ -131,7 +135,22 @@ struct Plan {
   uint32_t threshold = 0;
   size_t lds = 0;
   int32_t words = 0;  // > 0: bitset kernels with this many 64-bit words per node
+  int32_t rp_lds = 0;  // degree-array kernels: row_ptr staged in LDS
 };
+
+// Resident workgroups per CU, from the occupancy API, remembered per context.
+int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, int n, int* out) {
+  const auto key = std::make_tuple(words ? 1 : 0, pvc ? 1 : 0, prof ? 1 : 0, ws, words, lds);
+  const auto it = ctx->occupancy.find(key);
+  if (it != ctx->occupancy.end()) {
+    *out = it->second;
+    return VC_OK;
+  }
+  if (words) VC_HIP(ctx, vc::bitset_occupancy(words, pvc, prof, n, out));
+  else VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, ws, lds, out));
+  ctx->occupancy[key] = *out;
+  return VC_OK;
+}
 
 // Bitset kernels up to 256 vertices unless the caller asks for degree arrays.
 int choose_words(vc_ctx* ctx, int32_t n, int32_t flags, int32_t* words) {
@@ -160,17 +179,19 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl)
     best_ws = 64;
     if (o && o->wg_size && o->wg_size != 64)
       return fail(ctx, VC_ERR_INVALID_ARG, "the bitset kernels use 64-thread workgroups");
-    VC_HIP(ctx, vc::bitset_occupancy(pl.words, pvc, prof, n, &best_occ));
+    if ((rc = occupancy(ctx, pl.words, pvc, prof, 64, pl.lds, n, &best_occ))) return rc;
   } else {
     pl.stride = static_cast<int32_t>(round_up(static_cast<int64_t>(n) + 2, 64));
-    pl.lds = static_cast<size_t>(pl.stride) * sizeof(int32_t);
+    pl.lds = vc::node_lds_bytes(pl.stride, n, false);
     const size_t lds_cap = static_cast<size_t>(ctx->prop.maxSharedMemoryPerMultiProcessor);
     if (pl.lds + 1024 > lds_cap)
       return fail(ctx, VC_ERR_INVALID_ARG,
                   "graph too large for the LDS-resident node (n = " + std::to_string(n) + ")");
-    if (pl.lds > 65536 && ctx->lds_limit_set < pl.lds) {
-      VC_HIP(ctx, vc::set_lds_limit(pl.lds));
-      ctx->lds_limit_set = pl.lds;
+    const size_t lds_rp = vc::node_lds_bytes(pl.stride, n, true);
+    const size_t lds_max = lds_rp + 1024 <= lds_cap ? lds_rp : pl.lds;
+    if (lds_max > 65536 && ctx->lds_limit_set < lds_max) {
+      VC_HIP(ctx, vc::set_lds_limit(lds_max));
+      ctx->lds_limit_set = lds_max;
     }
     if (o && o->wg_size) {
       best_ws = o->wg_size;
@@ -183,7 +204,16 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl)
       while (ws < 1024 && ws * 2 <= std::max(n, 1) / 4) ws *= 2;
       best_ws = ws;
     }
-    VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, best_ws, pl.lds, &best_occ));
+    if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, pl.lds, n, &best_occ))) return rc;
+    // Keep row_ptr in LDS too when that costs no resident workgroup.
+    if (lds_rp + 1024 <= lds_cap) {
+      int occ_rp = 0;
+      if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_rp, n, &occ_rp))) return rc;
+      if (occ_rp == best_occ) {
+        pl.rp_lds = 1;
+        pl.lds = lds_rp;
+      }
+    }
   }
   if (best_occ < 1)
     return fail(ctx, VC_ERR_INVALID_ARG, "traversal kernel cannot be resident at this size");
@@ -216,6 +246,7 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl)
 // (§IV-E: the stacks bound the number of workgroups), then make sure they are allocated.
 int size_stacks(vc_ctx* ctx, Plan& pl, int32_t depth_cap) {
   const size_t per_wg = static_cast<size_t>(depth_cap) * pl.stride * sizeof(int32_t);
+  if (per_wg * static_cast<size_t>(pl.num_wg) <= ctx->stacks.bytes) return VC_OK;
   size_t free_b = 0, total_b = 0;
   VC_HIP(ctx, hipMemGetInfo(&free_b, &total_b));
   const size_t avail = ctx->stacks.bytes + (free_b > (size_t(1) << 30) ? free_b - (size_t(1) << 30) : 0);
@@ -270,6 +301,7 @@ int run_search(vc_ctx* ctx, const vc_graph* g, bool pvc, int64_t k, const vc_opt
   p.greedy_slot = pl.max_wg;
   p.cover_stride = pl.cover_stride;
   p.words = pl.words;
+  p.rp_lds = pl.rp_lds;
   if (pl.words) {
     if ((rc = ensure(ctx, ctx->bits, static_cast<size_t>(n) * pl.words * sizeof(uint64_t)))) return rc;
     p.bits = static_cast<uint64_t*>(ctx->bits.ptr);
@@ -454,6 +486,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, Param
   p.q_cap = 1;
   p.cover_stride = pl.cover_stride;
   p.words = pl.words;
+  p.rp_lds = pl.rp_lds;
   if (pl.words) {
     if ((rc = ensure(ctx, ctx->bits, static_cast<size_t>(g->n) * pl.words * sizeof(uint64_t)))) return rc;
     p.bits = static_cast<uint64_t*>(ctx->bits.ptr);
@@ -496,7 +529,6 @@ int vc_create(vc_ctx** ctx_out, int device, void* hip_stream) {
   ctx->device = device;
   hipError_t e = hipSetDevice(device);
   if (e == hipSuccess) e = hipGetDeviceProperties(&ctx->prop, device);
-  if (e == hipSuccess && !ctx->prop.cooperativeLaunch) e = hipErrorNotSupported;
   if (e == hipSuccess) {
     if (hip_stream) {
       ctx->stream = static_cast<hipStream_t>(hip_stream);

@@ -43,7 +43,12 @@ enum Activity : int {
   kActDonate = 3,   // deferring a child: stack pushes and worklist enqueues
   kActOther = 4,    // flags, bound, budget, recording solutions
   kActTotal = 5,    // the whole kernel, per workgroup
-  kNumActivities = 6,
+  // parts of kActReduce (degree-array kernels only)
+  kActDeg1 = 6,     // degree-one decisions
+  kActTri = 7,      // degree-two-triangle decisions
+  kActHigh = 8,     // high-degree decisions
+  kActApply = 9,    // removing the decided vertices
+  kNumActivities = 10,
 };
 
 struct WgStats {
@@ -82,8 +87,14 @@ struct Params {
   int32_t greedy_slot;  // cover buffer index of the greedy's cover
   uint64_t* bits;       // bitset kernels: adjacency rows, n * words 64-bit words
   int32_t words;        // bitset kernels: 64-bit words per row; 0 selects the degree-array kernels
-  int32_t pad;
+  int32_t rp_lds;       // degree-array kernels: copy row_ptr into LDS after the node
 };
+
+// Dynamic LDS of a degree-array kernel: the node (stride words), then row_ptr if staged.
+inline size_t node_lds_bytes(int32_t stride, int32_t n, bool rp_lds) {
+  const size_t node = static_cast<size_t>(stride) * 4;
+  return rp_lds ? node + ((static_cast<size_t>(n) + 1) * 4 + 15) / 16 * 16 : node;
+}
 
 // Result block written by the finalize kernel and copied to the host once.
 struct DevResult {

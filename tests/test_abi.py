@@ -52,7 +52,7 @@ def test_struct_layouts_match_header():
     from paper_2204_10402_amd import _binding as b
     assert ctypes.sizeof(b._Graph) == 24
     assert ctypes.sizeof(b._Options) == 48
-    assert ctypes.sizeof(b._Stats) == 7 * 8 + 10 * 4 + 3 * 8 + 6 * 8
+    assert ctypes.sizeof(b._Stats) == 7 * 8 + 10 * 4 + 3 * 8 + 10 * 8
 
 
 def test_no_gpu_means_device_error(lib):
