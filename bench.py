@@ -3,12 +3,17 @@ one MI355X, inputs resident in device memory.
 
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
-A step solves every instance of the workload once through the device-resident C-ABI entry
-points (vc_pvc_device / vc_mvc_device). Workloads (seeded, synthetic):
+A step solves every instance of the workload once, inputs resident in device memory:
+  --mode single  one device-form call per instance (vc_pvc_device / vc_mvc_device)
+  --mode batch   one batched call for all of them (vc_pvc_batch_device / vc_mvc_batch_device)
+Workloads (seeded, synthetic):
   planted-pvc    PVC on planted-cover graphs n=5000, |C|=400, 40,000 edges (75% C-rest),
                  k in {400, 399}, seeds 0-3: 8 solves per step (default)
   er60-mvc       MVC on G(60, 0.10), seed 0
   hard-mvc       MVC on random 5-regular n=120 and G(150, 0.08), seeds 0-7: 16 solves
+  planted-batch  4,096 planted-cover PVC instances, n uniform in [40, 400], average degree in
+                 [3, 12], |C| = 0.3n, k = |C| (even i) or |C| - 1 (odd i), master seed 0;
+                 also timed once with one launch per instance for comparison
 Prints one JSON line on stdout; progress goes to stderr.
 """
 
@@ -47,20 +52,29 @@ def instances(workload):
         out = [("mvc", G.random_regular(120, 5, s), None, f"5-regular n=120 seed {s}") for s in range(8)]
         out += [("mvc", G.erdos_renyi(150, 0.08, s), None, f"G(150,0.08) seed {s}") for s in range(8)]
         return out, {"families": ["5-regular n=120", "G(150, 0.08)"], "seeds": list(range(8))}
+    if workload == "planted-batch":
+        out = [("pvc", g, k, f"planted batch instance {i}")
+               for i, (g, k) in enumerate(G.planted_batch(4096, 0))]
+        return out, {"n": [40, 400], "avg_degree": [3, 12], "cover_frac": 0.3,
+                     "k": "|C| for even i, |C|-1 for odd i", "master_seed": 0}
     raise SystemExit(f"unknown workload {workload}")
 
 
-def algorithmic_bytes(g, st):
-    """HBM bytes the method itself must move in one traversal launch: every node copy between
-    a workgroup and its stack or the worklist (4(n+2) bytes: the degree array, s and the
-    pending vertex), plus one read of the CSR."""
+WORKLOADS = ["planted-pvc", "er60-mvc", "hard-mvc", "planted-batch"]
+
+
+def algorithmic_bytes(gs, st):
+    """HBM bytes the method itself must move in one call: every node copy between a
+    workgroup and its stack or the worklist (st["node_bytes"]: the node's state -- degree
+    array or live-vertex bitset, s, the pending vertex and the instance), plus one read of
+    each graph's CSR."""
     copies = st["stack_pushes"] + st["stack_pops"] + st["wl_enqueues"] + st["wl_dequeues"]
-    return 4 * (g.n + 2) * copies + 4 * (g.n + 1 + g.nnz)
+    return st["node_bytes"] * copies + sum(4 * (g.n + 1 + g.nnz) for g in gs)
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("vc_device.hip", "vc_internal.h"):
+    for f in ("vc_device.hip", "vc_bitset.hip", "vc_device_common.h", "vc_internal.h"):
         with open(os.path.join(ROOT, "paper_2204_10402_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -86,6 +100,15 @@ def cpu_baseline(workload, insts):
     t0 = time.perf_counter()
     nodes = 0
     reps = 0
+    if workload == "planted-batch":
+        # the whole batch once (about 3-5 s of oracle time on one core)
+        for kind, g, k, name in insts:
+            nodes += oracle.pvc(g, k).nodes
+        dt = time.perf_counter() - t0
+        return {"value": nodes / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
+                "sample": f"all {len(insts)} instances once", "seconds": round(dt, 3),
+                "instances_per_s": len(insts) / dt,
+                "time_to_solve_ms": round(1000 * dt / len(insts), 4)}
     if workload == "hard-mvc":
         # bounded sample: the first instance (about 10-15 s of oracle time)
         kind, g, k, name = insts[0]
@@ -113,31 +136,43 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="planted-pvc",
-                    choices=["planted-pvc", "er60-mvc", "hard-mvc"])
+    ap.add_argument("--workload", default="planted-pvc", choices=WORKLOADS)
+    ap.add_argument("--mode", default=None, choices=["single", "batch"],
+                    help="default: batch for planted-batch, single otherwise")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args()
     if a.gpus != 1:
         log("bench.py measures one GPU: the traversal runs on a single MI355X and no multi-GPU "
             "path is built; run with --gpus 1")
         sys.exit(2)
+    mode = a.mode or ("batch" if a.workload == "planted-batch" else "single")
 
+    import numpy as np
     import torch
     import paper_2204_10402_amd as vc
 
     insts, cfg = instances(a.workload)
+    kinds = {kind for kind, _, _, _ in insts}
+    assert len(kinds) == 1, "a workload is all MVC or all PVC"
+    kind = kinds.pop()
+    gs = [g for _, g, _, _ in insts]
+    ks = [k for _, _, k, _ in insts]
     dev = torch.device("cuda:0")
     resident = []
-    for kind, g, k, name in insts:
+    for _, g, k, name in insts:
         rp = torch.from_numpy(g.row_ptr).to(dev)
         ci = torch.from_numpy(g.col_idx).to(dev)
-        cover = torch.zeros(g.n, dtype=torch.uint8, device=dev)
-        resident.append((kind, g, k, name, rp, ci, cover))
+        cover = torch.zeros(max(g.n, 1), dtype=torch.uint8, device=dev)
+        resident.append((g, k, rp, ci, cover))
+    n_arr, nnz_arr, rp_all, ci_all = vc.pack_batch(gs)
+    rp_all_d = torch.from_numpy(rp_all).to(dev)
+    ci_all_d = torch.from_numpy(ci_all).to(dev)
+    cover_all_d = torch.zeros(max(int(n_arr.sum()), 1), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
     solver = vc.Solver(0, stream=torch.cuda.current_stream(dev))
 
-    def step(record):
-        for kind, g, k, name, rp, ci, cover in resident:
+    def run_single(record):
+        for g, k, rp, ci, cover in resident:
             t = time.perf_counter()
             if kind == "pvc":
                 r = solver.pvc_device(rp, ci, k, cover)
@@ -145,8 +180,21 @@ def main():
                 r = solver.mvc_device(rp, ci, cover)
             dt = time.perf_counter() - t
             if record is not None:
-                record.append((g, r, dt))
+                record.append(([g], r.stats, dt, 1))
 
+    def run_batch(record):
+        t = time.perf_counter()
+        if kind == "pvc":
+            r = solver.pvc_batch_device(n_arr, nnz_arr, rp_all_d, ci_all_d, ks, cover_all_d)
+        else:
+            r = solver.mvc_batch_device(n_arr, nnz_arr, rp_all_d, ci_all_d, cover_all_d)
+        dt = time.perf_counter() - t
+        if not (r.status == 0).all():
+            raise SystemExit("a batched instance failed: status " + str(np.unique(r.status)))
+        if record is not None:
+            record.append((gs, r.stats, dt, len(gs)))
+
+    step = run_batch if mode == "batch" else run_single
     for i in range(a.warmup):
         step(None)
         log(f"warmup {i + 1}/{a.warmup} done")
@@ -160,14 +208,15 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    nodes = sum(r.stats["nodes"] for _, r, _ in rec)
-    kernel_s = sum(r.stats["kernel_ms"] for _, r, _ in rec) / 1000.0
-    alg_bytes = sum(algorithmic_bytes(g, r.stats) for g, r, _ in rec)
-    launches = len(rec)
-    avg_kernel_s = kernel_s / launches
-    achieved = alg_bytes / launches / avg_kernel_s / 1e9
+    nodes = sum(st["nodes"] for _, st, _, _ in rec)
+    kernel_s = sum(st["kernel_ms"] for _, st, _, _ in rec) / 1000.0
+    alg_bytes = sum(algorithmic_bytes(g_list, st) for g_list, st, _, _ in rec)
+    calls = len(rec)
+    solved = sum(c for _, _, _, c in rec)
+    avg_kernel_s = kernel_s / calls
+    achieved = alg_bytes / calls / avg_kernel_s / 1e9
     traffic = measured_traffic(a.workload)
-    last = rec[-1][1].stats
+    last = rec[-1][1]
     out = {
         "metric": METRIC,
         "value": nodes / wall,
@@ -181,18 +230,33 @@ def main():
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": a.workload, "instances": len(insts), **cfg,
+        "config": {"workload": a.workload, "mode": mode, "instances": len(insts), **cfg,
                    "wg_size": last["wg_size"], "num_wg": last["num_wg"],
                    "wl_capacity": last["wl_capacity"], "wl_threshold": last["wl_threshold"]},
         "nodes_per_step": nodes // a.steps,
-        "time_to_solve_ms": {"median": 1000 * statistics.median(dt for _, _, dt in rec),
-                             "max": 1000 * max(dt for _, _, dt in rec)},
-        "instances_per_s": launches / wall,
+        "instances_per_s": solved / wall,
+        "time_to_solve_ms": {"median": 1000 * statistics.median(dt for _, _, dt, _ in rec),
+                             "max": 1000 * max(dt for _, _, dt, _ in rec),
+                             "per": "call" if mode == "batch" else "instance"},
         "kernel_ms_avg": 1000 * avg_kernel_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "traverse_kernel", "algorithmic_bytes_per_launch": alg_bytes / launches},
+                     "kernel": ("traverse_kernel" if last["n"] > 256 or not last["bitset_words"]
+                                else "bitset_traverse_kernel")
+                     + (" (all launches of a call)" if mode == "batch" else ""),
+                     "algorithmic_bytes_per_launch": alg_bytes / calls},
     }
+    if a.workload == "planted-batch":
+        # the plain form: one device-form call (one persistent launch) per instance, once
+        log("timing one launch per instance for comparison")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        run_single(None)
+        torch.cuda.synchronize()
+        plain = time.perf_counter() - t
+        out["per_instance_launches"] = {"instances_per_s": len(insts) / plain,
+                                        "seconds": round(plain, 3)}
+        out["batched_over_per_instance"] = out["instances_per_s"] / (len(insts) / plain)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(a.workload, insts)

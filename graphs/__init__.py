@@ -12,6 +12,7 @@ from .csr import CSRGraph, from_edges, edges_of, disjoint_union
 from .generators import (
     erdos_renyi,
     planted_cover,
+    planted_batch,
     random_regular,
     complete,
     cycle,
@@ -29,7 +30,8 @@ from .generators import (
 
 __all__ = [
     "CSRGraph", "from_edges", "edges_of", "disjoint_union",
-    "erdos_renyi", "planted_cover", "random_regular", "complete", "cycle", "path",
+    "erdos_renyi", "planted_cover",
+    "planted_batch", "random_regular", "complete", "cycle", "path",
     "complete_bipartite", "star", "empty", "complete_multipartite", "hypercube", "grid",
     "petersen", "random_bipartite", "random_small",
 ]

@@ -30,9 +30,14 @@ def planted_cover(n: int, c: int, m: int, cross_frac: float, seed: int) -> CSRGr
     remaining edges distinct pairs inside C. Duplicates and loops are rejected and redrawn, so
     every edge has at least one endpoint in C and C is a vertex cover of size c.
     """
+    return _planted(np.random.default_rng(seed), n, c, m, cross_frac,
+                    {"family": "planted", "n": n, "c": c, "m": m, "cross_frac": cross_frac,
+                     "seed": seed})
+
+
+def _planted(rng, n, c, m, cross_frac, meta):
     if not (0 < c <= n):
         raise ValueError("need 0 < c <= n")
-    rng = np.random.default_rng(seed)
     cover = np.sort(rng.choice(n, size=c, replace=False))
     in_c = np.zeros(n, dtype=bool)
     in_c[cover] = True
@@ -69,9 +74,32 @@ def planted_cover(n: int, c: int, m: int, cross_frac: float, seed: int) -> CSRGr
         draw(m_cross, lambda k: cover[rng.integers(0, c, k)],
              lambda k: rest[rng.integers(0, rest.size, k)])
     draw(m_in, lambda k: cover[rng.integers(0, c, k)], lambda k: cover[rng.integers(0, c, k)])
-    return from_edges(n, us, vs, meta={"family": "planted", "n": n, "c": c, "m": m,
-                                       "cross_frac": cross_frac, "seed": seed,
-                                       "cover": cover.astype(np.int32)})
+    return from_edges(n, us, vs, meta={**meta, "cover": cover.astype(np.int32)})
+
+
+def planted_batch(count: int, seed: int, n_lo: int = 40, n_hi: int = 400,
+                  deg_lo: float = 3.0, deg_hi: float = 12.0, cover_frac: float = 0.3,
+                  cross_frac: float = 0.75) -> list[tuple[CSRGraph, int]]:
+    """A batch of independent planted-cover PVC instances.
+
+    Instance ``i`` draws everything from ``default_rng([seed, i])``: n uniform in
+    [n_lo, n_hi], average degree d uniform in [deg_lo, deg_hi), |C| = floor(cover_frac*n),
+    m = round(d*n/2) edges split ``cross_frac`` C-rest and the rest inside C, as in
+    ``planted_cover``. Its parameter is k = |C| for even i (a yes-instance) and |C|-1 for
+    odd i. Returns ``[(graph, k), ...]``; ``graph.meta["cover"]`` holds C.
+    """
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng([seed, i])
+        n = int(rng.integers(n_lo, n_hi + 1))
+        d = float(rng.uniform(deg_lo, deg_hi))
+        c = int(np.floor(cover_frac * n))
+        m = int(round(d * n / 2))
+        g = _planted(rng, n, c, m, cross_frac,
+                     {"family": "planted_batch", "n": n, "c": c, "m": m, "avg_degree": d,
+                      "cross_frac": cross_frac, "seed": seed, "index": i})
+        out.append((g, c if i % 2 == 0 else c - 1))
+    return out
 
 
 def random_regular(n: int, d: int, seed: int, max_tries: int = 100000) -> CSRGraph:

@@ -25,7 +25,13 @@
  * reference after a call returns. The context owns its device workspace (kept and grown
  * across calls) and, if it created one, its HIP stream.
  * Errors: every entry point returns VC_OK (0) or a negative VC_ERR_* code. On error the
- * output arguments are left untouched and vc_last_error() describes the failure.
+ * host output arguments are left untouched (device cover buffers may have been written) and
+ * vc_last_error() describes the failure.
+ *
+ * Batches: vc_mvc_batch / vc_pvc_batch solve many independent graphs in one persistent
+ * launch per kernel family (bitset kernels by words per row, degree-array kernels): every
+ * graph's root is handed out to the workgroups in turn, and the sub-trees of all graphs share
+ * one worklist. A single-graph call is a batch of one.
  */
 #ifndef VC_H
 #define VC_H
@@ -80,10 +86,22 @@ typedef struct {
   int32_t wl_threshold; /* a branch is donated to the worklist only while it holds fewer than
                            this many entries (§IV-A); 0 = auto; -1 = never donate (every
                            workgroup keeps its whole sub-tree on its own stack) */
-  int64_t node_budget;  /* stop with VC_ERR_BUDGET after about this many nodes; 0 = none */
+  int64_t node_budget;  /* stop with VC_ERR_BUDGET after about this many nodes (per graph
+                           of a batch); 0 = none */
   int32_t flags;        /* VC_OPT_* */
   int32_t reserved[5];  /* must be zero */
 } vc_options;
+
+/* A batch of independent graphs, each in the format above, packed one after the other. */
+typedef struct {
+  int32_t count;           /* number of graphs, >= 0 */
+  const int32_t *n;        /* HOST, count entries: vertices of graph i */
+  const int32_t *nnz;      /* HOST, count entries: stored CSR entries of graph i */
+  const int32_t *row_ptr;  /* sum(n[i] + 1) entries: graph i's row_ptr (starting at 0), then
+                              graph i+1's */
+  const int32_t *col_idx;  /* sum(nnz[i]) entries: graph i's neighbour ids (0..n[i]-1), then
+                              graph i+1's */
+} vc_batch;
 
 /* Per-call statistics. A search-tree node is one visit: a node is taken from the stack or
  * the worklist (or continued in place) and the reduction rules run on it. */
@@ -94,7 +112,7 @@ typedef struct {
   int64_t stack_pushes;   /* deferred children kept on a workgroup's own stack */
   int64_t stack_pops;
   int64_t wl_enqueues;    /* deferred children donated to the worklist */
-  int64_t wl_dequeues;    /* worklist entries taken (the root included) */
+  int64_t wl_dequeues;    /* worklist entries taken (roots are handed out separately) */
   int32_t max_stack_depth;
   int32_t greedy_size;    /* MVC: size of the greedy cover that seeds the bound; PVC: -1 */
   int32_t wg_size;
@@ -102,10 +120,12 @@ typedef struct {
   int32_t wl_capacity;
   int32_t wl_threshold;
   int32_t depth_cap;      /* stack entries provisioned per workgroup */
-  int32_t n;
-  int32_t bitset_words;   /* 64-bit words per node with the bitset kernels; 0 = degree arrays */
-  int32_t node_bytes;     /* bytes of one stored search node */
-  double kernel_ms;       /* traversal kernel time (HIP events on the context stream) */
+  int32_t n;              /* vertices (batches: of the largest graph) */
+  int32_t bitset_words;   /* 64-bit words per node with the bitset kernels; 0 = degree arrays
+                             (batches: the largest used) */
+  int32_t node_bytes;     /* bytes of one search node's state (batches: the largest) */
+  double kernel_ms;       /* traversal kernel time (HIP events on the context stream; batches:
+                             summed over the launches) */
   double greedy_ms;       /* greedy kernel time (MVC) */
   double total_ms;        /* wall clock of the whole call */
   /* With VC_OPT_PROFILE, shader-clock cycles summed over the workgroups (paper §V-D):
@@ -154,6 +174,34 @@ int vc_mvc_device(vc_ctx *ctx, const vc_graph *g, const vc_options *opts, int32_
                   uint8_t *cover_dev, vc_stats *stats);
 int vc_pvc_device(vc_ctx *ctx, const vc_graph *g, int32_t k, const vc_options *opts,
                   int32_t *yes_out, int32_t *size_out, uint8_t *cover_dev, vc_stats *stats);
+
+/* Batched MVC / PVC (paper §II-A, §IV-A). Each graph of the batch is solved exactly as the
+ * single-graph calls solve it; the graphs share the device. `batch->row_ptr` and
+ * `batch->col_idx` are HOST pointers (vc_*_batch) or DEVICE pointers on the context's device
+ * (vc_*_batch_device); `k` (PVC) has count entries, each >= 0. Per graph i (HOST arrays of
+ * count entries):
+ *   status_out[i]  VC_OK, VC_ERR_INVALID_GRAPH (graph i breaks the CSR format) or
+ *                  VC_ERR_BUDGET (graph i used up opts->node_budget, which applies per graph);
+ *   size_out[i]    MVC: tau(G_i); PVC: |S| <= k[i] on yes, -1 on no; -1 unless status is OK;
+ *   yes_out[i]     PVC: 1 or 0 (0 unless status is OK);
+ *   nodes_out[i]   search-tree nodes visited on graph i (may be NULL).
+ * The cover output (may be NULL) has sum(n[i]) bytes, graph i's n[i] bytes after those of the
+ * graphs before it: 1 on its cover, all 0 for PVC no or a status other than VC_OK; it is host
+ * memory for vc_*_batch and device memory for vc_*_batch_device. The call itself returns VC_OK
+ * when every graph has a status, else an error for the whole batch (bad arguments, device or
+ * internal error). `stats` (may be NULL) sums over the batch. */
+int vc_mvc_batch(vc_ctx *ctx, const vc_batch *batch, const vc_options *opts, int32_t *status_out,
+                 int32_t *size_out, uint8_t *cover_out, int64_t *nodes_out, vc_stats *stats);
+int vc_pvc_batch(vc_ctx *ctx, const vc_batch *batch, const int32_t *k, const vc_options *opts,
+                 int32_t *status_out, int32_t *yes_out, int32_t *size_out, uint8_t *cover_out,
+                 int64_t *nodes_out, vc_stats *stats);
+int vc_mvc_batch_device(vc_ctx *ctx, const vc_batch *batch, const vc_options *opts,
+                        int32_t *status_out, int32_t *size_out, uint8_t *cover_dev,
+                        int64_t *nodes_out, vc_stats *stats);
+int vc_pvc_batch_device(vc_ctx *ctx, const vc_batch *batch, const int32_t *k,
+                        const vc_options *opts, int32_t *status_out, int32_t *yes_out,
+                        int32_t *size_out, uint8_t *cover_dev, int64_t *nodes_out,
+                        vc_stats *stats);
 
 /* The greedy approximation that seeds MVC's bound (paper §II-B, §IV-E), on the GPU with one
  * workgroup: apply the degree-one and degree-two-triangle rules, put a vertex of maximum

@@ -35,12 +35,18 @@ ACTIVITIES = ("acquire", "reduce", "branch", "donate", "other", "total",
 EXPORTS = (
     "vc_create", "vc_destroy", "vc_strerror", "vc_last_error", "vc_version",
     "vc_mvc", "vc_pvc", "vc_mvc_device", "vc_pvc_device", "vc_greedy_device",
-    "vc_reduce_device",
+    "vc_reduce_device", "vc_mvc_batch", "vc_pvc_batch", "vc_mvc_batch_device",
+    "vc_pvc_batch_device",
 )
 
 
 class _Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32),
+                ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class _Batch(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("n", ctypes.c_void_p), ("nnz", ctypes.c_void_p),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
 
 
@@ -91,6 +97,20 @@ class Result:
     stats: dict = field(default_factory=dict)
 
 
+@dataclass
+class BatchResult:
+    status: np.ndarray      # int32[count]: OK, ERR_INVALID_GRAPH or ERR_BUDGET per graph
+    size: np.ndarray        # int32[count]: MVC size / PVC cover size, -1 on PVC no or error
+    yes: np.ndarray         # bool[count]: PVC decision (True for MVC answers)
+    nodes: np.ndarray       # int64[count]: search-tree nodes per graph
+    cover: object           # packed covers: numpy uint8[sum n] or the caller's device tensor
+    offsets: np.ndarray     # int64[count + 1]: graph i's cover is cover[offsets[i]:offsets[i+1]]
+    stats: dict = field(default_factory=dict)
+
+    def cover_of(self, i: int):
+        return self.cover[int(self.offsets[i]):int(self.offsets[i + 1])]
+
+
 class VCError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{msg} (status {code})")
@@ -111,6 +131,7 @@ def load_library(path: str = LIB_PATH):
     vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
     i32p = ctypes.POINTER(ctypes.c_int32)
     gp, op, sp = ctypes.POINTER(_Graph), ctypes.POINTER(_Options), ctypes.POINTER(_Stats)
+    bp = ctypes.POINTER(_Batch)
     sig = {
         "vc_create": ([ctypes.POINTER(vp), ctypes.c_int, vp], ctypes.c_int),
         "vc_destroy": ([vp], ctypes.c_int),
@@ -123,6 +144,10 @@ def load_library(path: str = LIB_PATH):
         "vc_pvc_device": ([vp, gp, i32, op, i32p, i32p, vp, sp], ctypes.c_int),
         "vc_greedy_device": ([vp, gp, i32p, vp], ctypes.c_int),
         "vc_reduce_device": ([vp, gp, vp, i32p, i64, i32], ctypes.c_int),
+        "vc_mvc_batch": ([vp, bp, op, vp, vp, vp, vp, sp], ctypes.c_int),
+        "vc_pvc_batch": ([vp, bp, vp, op, vp, vp, vp, vp, vp, sp], ctypes.c_int),
+        "vc_mvc_batch_device": ([vp, bp, op, vp, vp, vp, vp, sp], ctypes.c_int),
+        "vc_pvc_batch_device": ([vp, bp, vp, op, vp, vp, vp, vp, vp, sp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -156,6 +181,22 @@ def _device_graph(row_ptr, col_idx):
         raise ValueError("row_ptr must hold n+1 entries")
     return _Graph(n, col_idx.numel(), row_ptr.data_ptr(),
                   col_idx.data_ptr() if col_idx.numel() else None)
+
+
+def pack_batch(graphs):
+    """Pack CSR graphs one after another (vc_batch layout): returns int32 arrays
+    (n, nnz, row_ptr, col_idx). Each graph keeps its own row pointers and vertex ids."""
+    n = np.array([g.n for g in graphs], np.int32)
+    nnz = np.array([len(g.col_idx) for g in graphs], np.int32)
+    rp = np.concatenate([np.asarray(g.row_ptr, np.int32) for g in graphs]) if graphs \
+        else np.zeros(0, np.int32)
+    ci = np.concatenate([np.asarray(g.col_idx, np.int32) for g in graphs]) if graphs \
+        else np.zeros(0, np.int32)
+    return n, nnz, np.ascontiguousarray(rp), np.ascontiguousarray(ci)
+
+
+def _ptr(a):
+    return a.ctypes.data if a.size else None
 
 
 class Solver:
@@ -257,6 +298,87 @@ class Solver:
         self._check(rc, "vc_pvc_device")
         return Result(size.value, bool(yes.value), cover, _stats_dict(st))
 
+    # ---- batches ----------------------------------------------------------------------------
+
+    def _batch_result(self, count, n, status, size, yes, nodes, cover, st, pvc):
+        c = count
+        return BatchResult(status[:c].copy(), size[:c].copy(),
+                           (yes[:c] != 0) if pvc else (status[:c] == OK),
+                           nodes[:c].copy(), cover, _offsets(n), _stats_dict(st))
+
+    def mvc_batch(self, graphs, options: Options | None = None) -> BatchResult:
+        n, nnz, rp, ci = pack_batch(graphs)
+        cover = np.zeros(max(int(n.sum()), 1), np.uint8)
+        status, size, yes, nodes = _batch_arrays(len(graphs))
+        cb = _Batch(len(graphs), _ptr(n), _ptr(nnz), _ptr(rp), _ptr(ci))
+        st = _Stats()
+        rc = self._lib.vc_mvc_batch(self._ctx, ctypes.byref(cb), self._opts(options),
+                                    status.ctypes.data, size.ctypes.data, cover.ctypes.data,
+                                    nodes.ctypes.data, ctypes.byref(st))
+        self._check(rc, "vc_mvc_batch")
+        return self._batch_result(len(graphs), n, status, size, yes, nodes,
+                                  cover[:int(n.sum())], st, False)
+
+    def pvc_batch(self, graphs, ks, options: Options | None = None) -> BatchResult:
+        n, nnz, rp, ci = pack_batch(graphs)
+        k = np.ascontiguousarray(ks, dtype=np.int32)
+        if k.size != len(graphs):
+            raise ValueError("one k per graph")
+        cover = np.zeros(max(int(n.sum()), 1), np.uint8)
+        status, size, yes, nodes = _batch_arrays(len(graphs))
+        cb = _Batch(len(graphs), _ptr(n), _ptr(nnz), _ptr(rp), _ptr(ci))
+        st = _Stats()
+        rc = self._lib.vc_pvc_batch(self._ctx, ctypes.byref(cb), _ptr(k), self._opts(options),
+                                    status.ctypes.data, yes.ctypes.data, size.ctypes.data,
+                                    cover.ctypes.data, nodes.ctypes.data, ctypes.byref(st))
+        self._check(rc, "vc_pvc_batch")
+        return self._batch_result(len(graphs), n, status, size, yes, nodes,
+                                  cover[:int(n.sum())], st, True)
+
+    def _device_batch(self, n, nnz, row_ptr, col_idx):
+        import torch
+        n = np.ascontiguousarray(n, dtype=np.int32)
+        nnz = np.ascontiguousarray(nnz, dtype=np.int32)
+        for t, name in ((row_ptr, "row_ptr"), (col_idx, "col_idx")):
+            if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.int32 \
+                    or not t.is_contiguous():
+                raise TypeError(f"{name} must be a contiguous int32 device tensor")
+        if row_ptr.numel() != int(n.sum()) + n.size or col_idx.numel() != int(nnz.sum()):
+            raise ValueError("packed row_ptr / col_idx do not match n / nnz")
+        cb = _Batch(n.size, _ptr(n), _ptr(nnz), row_ptr.data_ptr() if row_ptr.numel() else None,
+                    col_idx.data_ptr() if col_idx.numel() else None)
+        return n, nnz, cb
+
+    def mvc_batch_device(self, n, nnz, row_ptr, col_idx, cover=None,
+                         options: Options | None = None) -> BatchResult:
+        n, nnz, cb = self._device_batch(n, nnz, row_ptr, col_idx)
+        self._order_after_torch()
+        status, size, yes, nodes = _batch_arrays(n.size)
+        st = _Stats()
+        rc = self._lib.vc_mvc_batch_device(self._ctx, ctypes.byref(cb), self._opts(options),
+                                           status.ctypes.data, size.ctypes.data,
+                                           cover.data_ptr() if cover is not None else None,
+                                           nodes.ctypes.data, ctypes.byref(st))
+        self._check(rc, "vc_mvc_batch_device")
+        return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, False)
+
+    def pvc_batch_device(self, n, nnz, row_ptr, col_idx, ks, cover=None,
+                         options: Options | None = None) -> BatchResult:
+        n, nnz, cb = self._device_batch(n, nnz, row_ptr, col_idx)
+        k = np.ascontiguousarray(ks, dtype=np.int32)
+        if k.size != n.size:
+            raise ValueError("one k per graph")
+        self._order_after_torch()
+        status, size, yes, nodes = _batch_arrays(n.size)
+        st = _Stats()
+        rc = self._lib.vc_pvc_batch_device(self._ctx, ctypes.byref(cb), _ptr(k),
+                                           self._opts(options), status.ctypes.data,
+                                           yes.ctypes.data, size.ctypes.data,
+                                           cover.data_ptr() if cover is not None else None,
+                                           nodes.ctypes.data, ctypes.byref(st))
+        self._check(rc, "vc_pvc_batch_device")
+        return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, True)
+
     def greedy_device(self, row_ptr, col_idx, cover=None) -> int:
         cg = _device_graph(row_ptr, col_idx)
         self._order_after_torch()
@@ -275,6 +397,17 @@ class Solver:
                                         ctypes.byref(sv), int(bound), int(flags))
         self._check(rc, "vc_reduce_device")
         return sv.value
+
+
+def _batch_arrays(count: int):
+    return (np.zeros(max(count, 1), np.int32), np.zeros(max(count, 1), np.int32),
+            np.zeros(max(count, 1), np.int32), np.zeros(max(count, 1), np.int64))
+
+
+def _offsets(n):
+    off = np.zeros(len(n) + 1, np.int64)
+    np.cumsum(n, out=off[1:])
+    return off
 
 
 def version() -> str:

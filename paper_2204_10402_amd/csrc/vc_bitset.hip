@@ -241,16 +241,18 @@ __device__ __forceinline__ void remove_neighbourhood_bits(Live<W>& L, int v,
   remove_set(L, F);
 }
 
-// A stored node: W words of live bits (lo/hi 32-bit halves), |S|, pending vertex, padding.
-// Lane 0 writes and reads every stored node, so a node pushed on the workgroup's stack is read
-// back in program order, and the worklist publishes it with one release store.
+
+// A stored node: W words of live bits (lo/hi 32-bit halves), |S|, the pending vertex, the
+// instance (launch-local index), padding to a multiple of four words. Lane 0 writes and reads
+// every stored node, so a node pushed on the workgroup's stack is read back in program order,
+// and the worklist publishes it with one release store.
 template <int W>
 constexpr int bits_stride() {
-  return ((2 * W + 2) + 3) & ~3;
+  return ((2 * W + 3) + 3) & ~3;
 }
 
 template <int W>
-__device__ __forceinline__ void bits_store(int32_t* dst, const Live<W>& L, int pending) {
+__device__ __forceinline__ void bits_store(int32_t* dst, const Live<W>& L, int pending, int inst) {
   if (lane_id() == 0) {
 #pragma unroll
     for (int w = 0; w < W; ++w) {
@@ -259,16 +261,14 @@ __device__ __forceinline__ void bits_store(int32_t* dst, const Live<W>& L, int p
     }
     dst[2 * W] = L.s;
     dst[2 * W + 1] = pending;
+    dst[2 * W + 2] = inst;
   }
 }
 
+// Node words read by lane 0 into (uniform) L, pending vertex and instance.
 template <int W>
-__device__ __forceinline__ int bits_load(const int32_t* src, Live<W>& L) {
-  uint32_t x[2 * W + 2];
-  if (lane_id() == 0) {
-#pragma unroll
-    for (int i = 0; i < 2 * W + 2; ++i) x[i] = static_cast<uint32_t>(src[i]);
-  }
+__device__ __forceinline__ void bits_unpack(const uint32_t (&x)[2 * W + 3], Live<W>& L,
+                                            int& pending, int& inst) {
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane(x[2 * w]);
@@ -276,20 +276,47 @@ __device__ __forceinline__ int bits_load(const int32_t* src, Live<W>& L) {
     L.bits[w] = (static_cast<uint64_t>(hi) << 32) | lo;
   }
   L.s = __builtin_amdgcn_readfirstlane(x[2 * W]);
-  return __builtin_amdgcn_readfirstlane(x[2 * W + 1]);  // pending vertex
+  pending = __builtin_amdgcn_readfirstlane(x[2 * W + 1]);
+  inst = __builtin_amdgcn_readfirstlane(x[2 * W + 2]);
 }
 
-// Adjacency into LDS (all rows) and this lane's rows into registers.
 template <int W>
-__device__ __forceinline__ void load_adjacency(const Params& p, uint64_t* adj_lds, Rows<W>& r) {
-  for (int i = threadIdx.x; i < p.n * W; i += blockDim.x) adj_lds[i] = p.bits[i];
+__device__ __forceinline__ void bits_load(const int32_t* src, Live<W>& L, int& pending, int& inst) {
+  uint32_t x[2 * W + 3];
+  if (lane_id() == 0) {
+#pragma unroll
+    for (int i = 0; i < 2 * W + 3; ++i) x[i] = static_cast<uint32_t>(src[i]);
+  }
+  bits_unpack<W>(x, L, pending, inst);
+}
+
+// Instance j: its adjacency rows into LDS (all rows) and this lane's rows into registers.
+template <int W>
+__device__ __forceinline__ int load_adjacency(const Params& p, int j, uint64_t* adj_lds,
+                                              Rows<W>& r) {
+  const Instance in = p.inst[j];
+  const uint64_t* rows = p.bits + static_cast<int64_t>(in.vtx_first) * W;
+  __syncthreads();  // the previous instance's rows are no longer read
+  for (int i = threadIdx.x; i < in.n * W; i += blockDim.x) adj_lds[i] = rows[i];
 #pragma unroll
   for (int wv = 0; wv < W; ++wv) {
     const int v = wv * 64 + lane_id();
 #pragma unroll
-    for (int w = 0; w < W; ++w) r.adj[wv][w] = v < p.n ? p.bits[v * W + w] : 0ull;
+    for (int w = 0; w < W; ++w) r.adj[wv][w] = v < in.n ? rows[v * W + w] : 0ull;
   }
   __syncthreads();
+  return in.n;
+}
+
+// The root of an instance with n vertices: every vertex live, |S| = 0.
+template <int W>
+__device__ __forceinline__ void root_bits(Live<W>& L, int n) {
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const int lo = w * 64, cnt = n - lo;
+    L.bits[w] = cnt <= 0 ? 0ull : (cnt >= 64 ? ~0ull : ((1ull << cnt) - 1ull));
+  }
+  L.s = 0;
 }
 
 template <int W>
@@ -306,22 +333,22 @@ __device__ __forceinline__ void write_cover(uint8_t* cov, const Live<W>& L, int 
 // ticket), so one agent-scope release store orders the node's words before the ticket and one
 // acquire load orders them after it; the result reaches the other lanes by readfirstlane.
 
-// Donate a deferred child to the worklist; true if the worklist took it. The child is the
-// stored node at `oldest` (the bottom of this workgroup's stack) when that is not null, else
-// node L with `pending` as its branch vertex.
+// Donate a deferred child of instance `inst` to the worklist; true if the worklist took it.
+// The child is the stored node at `oldest` (the bottom of this workgroup's stack) when that is
+// not null, else node L with `pending` as its branch vertex.
 template <int W>
 __device__ __forceinline__ bool bits_enqueue(const Params& p, Ctrl& c, const Live<W>& L,
-                                             int pending, const int32_t* oldest) {
+                                             int pending, const int32_t* oldest, int inst) {
   int ok = 0;
   if (lane_id() == 0) {
-    ok = enqueue_reserve(p, c) == 1;
+    ok = enqueue_reserve(p, c, inst) == 1;
     if (ok) {
       int32_t* dst = p.payload + static_cast<size_t>(c.slot) * p.stride;
       if (oldest) {
 #pragma unroll
-        for (int i = 0; i < 2 * W + 2; ++i) dst[i] = oldest[i];
+        for (int i = 0; i < 2 * W + 3; ++i) dst[i] = oldest[i];
       } else {
-        bits_store<W>(dst, L, pending);
+        bits_store<W>(dst, L, pending, inst);
       }
       store_release(p.seq + c.slot, 2u * c.lap + 1u);
     }
@@ -329,18 +356,19 @@ __device__ __forceinline__ bool bits_enqueue(const Params& p, Ctrl& c, const Liv
   return __builtin_amdgcn_readfirstlane(ok);
 }
 
-// Take a node from the worklist. Returns 1 with L / pending set, 0 when the search is over,
-// -1 when it is being stopped. Idle polling as in dequeue_begin.
+// Take work. Returns 1 with L / pending / inst set from a worklist node, 2 with inst set to an
+// unstarted instance (its root), 0 when the launch is over, -1 when it is being stopped. Queued
+// nodes go first, then roots in instance order; idle polling as in dequeue_begin.
 template <int W>
-__device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pending) {
-  int status = 2;
-  uint32_t words[2 * W + 2];
+__device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pending,
+                                            int& inst) {
+  int status = 3;
+  uint32_t words[2 * W + 3];
   if (lane_id() == 0) {
     int polls = 0;
-    while (status == 2) {
+    while (status == 3) {
       int32_t* count = ctr_i32(p, kQCount);
-      if ((polls & 3) == 0 &&
-          (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound)))) {
+      if ((polls & 3) == 0 && search_stopped(p)) {
         status = -1;
       } else if (load_relaxed(count) > 0) {
         if (fetch_add(count, -1) > 0) {
@@ -350,7 +378,7 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pe
           int wait = 0;
           status = 1;
           while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
-            if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) {
+            if (search_stopped(p)) {
               status = -1;
               break;
             }
@@ -359,16 +387,22 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pe
           if (status == 1) {
             const int32_t* src = p.payload + static_cast<size_t>(slot) * p.stride;
 #pragma unroll
-            for (int i = 0; i < 2 * W + 2; ++i) words[i] = static_cast<uint32_t>(src[i]);
+            for (int i = 0; i < 2 * W + 3; ++i) words[i] = static_cast<uint32_t>(src[i]);
             store_release(p.seq + slot, 2u * (lap + 1u));
           }
         } else {
           fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
         }
+      } else if (load_relaxed(ctr_i32(p, kRootNext)) < p.num_inst) {
+        const int32_t r = fetch_add(ctr_i32(p, kRootNext), 1);
+        if (r < p.num_inst) {
+          status = 2;
+          words[2 * W + 2] = static_cast<uint32_t>(r);
+        }
       } else if (load_relaxed(ctr_i32(p, kWork)) == 0) {
-        status = 0;  // nothing queued and nothing held: the search is over
+        status = 0;  // nothing queued, held or unstarted: the launch is over
       }
-      if (status == 2) {
+      if (status == 3) {
         const int units = 1 << (polls < 5 ? polls : 5);
         for (int i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(16);
         ++polls;
@@ -376,157 +410,174 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pe
     }
   }
   status = __builtin_amdgcn_readfirstlane(status);
-  if (status == 1) {
-#pragma unroll
-    for (int w = 0; w < W; ++w) {
-      const uint32_t lo = __builtin_amdgcn_readfirstlane(words[2 * w]);
-      const uint32_t hi = __builtin_amdgcn_readfirstlane(words[2 * w + 1]);
-      L.bits[w] = (static_cast<uint64_t>(hi) << 32) | lo;
-    }
-    L.s = __builtin_amdgcn_readfirstlane(words[2 * W]);
-    pending = __builtin_amdgcn_readfirstlane(words[2 * W + 1]);
-  }
+  if (status == 1) bits_unpack<W>(words, L, pending, inst);
+  else if (status == 2) inst = __builtin_amdgcn_readfirstlane(words[2 * W + 2]);
   return status;
 }
 
 // ---- kernels -----------------------------------------------------------------------------------
 
-// Adjacency bit matrix (n rows of W words) from the validated CSR, and the root node in
-// worklist slot 0: every vertex live, |S| = 0, nothing pending.
-__global__ void bitset_pack_kernel(Params p) {
-  if (*ctr_i32(p, kErrRow) != 0x7FFFFFFF) return;
-  const int W = p.words;
-  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < p.n; v += gridDim.x * blockDim.x) {
-    uint64_t row[4] = {0, 0, 0, 0};
-    for (int j = p.rp[v]; j < p.rp[v + 1]; ++j) {
-      const int u = p.ci[j];
-      row[u >> 6] |= 1ull << (u & 63);
-    }
-    for (int w = 0; w < W; ++w) p.bits[v * W + w] = row[w];
-  }
-  if (blockIdx.x == 0 && threadIdx.x < 4 * ((2 * W + 2 + 3) / 4)) {
-    const int i = threadIdx.x;
-    int32_t x = 0;
-    if (i < 2 * W) {
-      const int w = i >> 1;
-      const int lo = w * 64, hi = lo + 64 < p.n ? lo + 64 : p.n;  // vertices of word w
-      uint64_t m = 0;
-      if (hi > lo) m = hi - lo == 64 ? ~0ull : ((1ull << (hi - lo)) - 1ull);
-      x = static_cast<int32_t>(static_cast<uint32_t>((i & 1) ? (m >> 32) : m));
-    } else if (i == 2 * W + 1) {
-      x = -1;
-    }
-    p.payload[i] = x;
-  }
-}
-
-// Greedy approximation (§II-B), as greedy_kernel, on the bitset node.
+// Greedy approximation (§II-B), as greedy_kernel, on bitset nodes: one workgroup per instance
+// (grid-stride loop over the launch's instances).
 template <int W>
-__global__ void __launch_bounds__(64) bitset_greedy_kernel(Params p, DevResult* res) {
+__global__ void __launch_bounds__(64) bitset_greedy_kernel(Params p) {
   extern __shared__ uint64_t adj_lds[];
-  if (threadIdx.x == 0) {
-    res->err_row = load_relaxed(ctr_i32(p, kErrRow));
-    res->edges0 = load_relaxed(ctr_i32(p, kEdges0)) / 2;
-    res->greedy = 0;
-  }
-  if (load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF) return;
-  Rows<W> r;
-  load_adjacency<W>(p, adj_lds, r);
-  Live<W> L;
-  bits_load<W>(p.payload, L);
-  const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
-  for (;;) {
-    reduce_bits<W>(r, L, adj_lds, unbounded, kRuleDeg1 | kRuleTri);
-    int vmax;
-    int32_t degsum;
-    bits_max_degree<W>(r, L, vmax, degsum);
-    if (degsum == 0) break;
-    remove_vertex_bits<W>(L, vmax);
-  }
-  write_cover<W>(p.covers + static_cast<size_t>(p.greedy_slot) * p.cover_stride, L, p.n);
-  if (threadIdx.x == 0) {
-    *ctr_u64(p, kBestKey) =
-        (static_cast<unsigned long long>(L.s) << 32) | static_cast<uint32_t>(p.greedy_slot);
-    res->greedy = L.s;
+  for (int j = blockIdx.x; j < p.num_inst; j += gridDim.x) {
+    if (__builtin_amdgcn_readfirstlane(load_relaxed(&p.ist[j].err_row)) != kNoRow) continue;
+    Rows<W> r;
+    const int n = load_adjacency<W>(p, j, adj_lds, r);
+    Live<W> L;
+    root_bits<W>(L, n);
+    const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
+    for (;;) {
+      reduce_bits<W>(r, L, adj_lds, unbounded, kRuleDeg1 | kRuleTri);
+      int vmax;
+      int32_t degsum;
+      bits_max_degree<W>(r, L, vmax, degsum);
+      if (degsum == 0) break;
+      remove_vertex_bits<W>(L, vmax);
+    }
+    write_cover<W>(p.covers + p.inst[j].vtx_off, L, n);
+    if (threadIdx.x == 0) {
+      p.ist[j].best = L.s;
+      p.ist[j].greedy = L.s;
+    }
   }
 }
 
-// The hybrid traversal (§IV-A, Fig. 4; termination §IV-C) on bitset nodes.
+// Lane 0: claim / publish a cover of size s for instance j (see claim_solution in the
+// degree-array kernels; the same protocol).
+template <bool PVC>
+__device__ __forceinline__ int bits_claim(const Params& p, int j, int32_t s) {
+  InstState* is = p.ist + j;
+  if (PVC) return atomicCAS(&is->found, 0, 1) == 0;
+  if (atomicMin(&is->best, s) <= s) return 0;
+  lock_acquire(&is->lock);
+  if (load_relaxed(&is->best) == s) return 1;
+  store_release(&is->lock, 0);
+  return 0;
+}
+
+template <bool PVC>
+__device__ __forceinline__ void bits_publish(const Params& p, int j, int32_t s) {
+  InstState* is = p.ist + j;
+  if (PVC) {
+    store_relaxed(&is->best, s);
+    fetch_add(ctr_i32(p, kOpen), -1);
+  } else {
+    store_release(&is->lock, 0);
+  }
+}
+
+__device__ __forceinline__ void bits_report_nodes(const Params& p, int j, int64_t count) {
+  if (count <= 0) return;
+  unsigned long long* total = reinterpret_cast<unsigned long long*>(&p.ist[j].nodes);
+  const unsigned long long before = fetch_add(total, static_cast<unsigned long long>(count));
+  if (p.node_budget > 0 && static_cast<int64_t>(before) + count >= p.node_budget)
+    store_relaxed(&p.ist[j].aborted, 1);
+}
+
+// The hybrid traversal (§IV-A, Fig. 4; termination §IV-C) on bitset nodes, over every instance
+// of the launch (as traverse_kernel).
 template <int W, bool PVC, bool PROF>
 __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   extern __shared__ uint64_t adj_lds[];
   __shared__ Ctrl c;
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
-  const bool skip = load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF ||
-                    load_relaxed(ctr_i32(p, kEdges0)) == 0;
-  if (__builtin_amdgcn_readfirstlane(skip)) {
-    if (tid == 0) p.wg_stats[wg] = WgStats{};
-    return;
-  }
   Rows<W> r;
-  load_adjacency<W>(p, adj_lds, r);
   ActivityClock<PROF> clk;
   clk.begin();
 
   constexpr int kStride = bits_stride<W>();
   int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * kStride;
   // The stack is a ring of depth_cap entries holding [bot, top): pops take the top, donations
-  // take the bottom (the oldest deferred child, nearest its sub-tree root).
+  // take the bottom (the oldest deferred child, nearest its sub-tree root). Every entry belongs
+  // to the instance of the sub-tree being walked.
   int top = 0, bot = 0;
   bool have = false, holding = false;
-  int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0;
+  int cur = -1, cur_n = 0;
+  int32_t cur_k = 0, cur_vtx = 0;
+  int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0, insts = 0;
+  int64_t unreported = 0;
   int max_depth = 0;
-  int64_t budget_mark = 0;
   Live<W> L;
 
   for (;;) {
-    const int stop = __builtin_amdgcn_readfirstlane(
-        load_relaxed(ctr_i32(p, kAbort)) | (PVC ? load_relaxed(ctr_i32(p, kFound)) : 0));
-    const int32_t best =
-        PVC ? 0 : __builtin_amdgcn_readfirstlane(
-                      static_cast<int32_t>(load_relaxed(ctr_u64(p, kBestKey)) >> 32));
-    clk.charge(kActOther);
-    if (stop) break;
-
     if (!have) {
-      int pending;
+      int pending, inst;
       if (top > bot) {
         --top;
-        pending = bits_load<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L);
+        bits_load<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, pending, inst);
         ++pops;
       } else {
         if (holding) {
-          if (tid == 0) fetch_add(ctr_i32(p, kWork), -1);
+          if (tid == 0) release_work(p, cur);
           holding = false;
         }
-        const int got = bits_dequeue<W>(p, L, pending);
-        if (got != 1) {
+        const int got = bits_dequeue<W>(p, L, pending, inst);
+        if (got != 1 && got != 2) {
           clk.charge(kActAcquire);
           break;
         }
         holding = true;
-        ++dequeues;
+        if (got == 1) ++dequeues;
+        clk.charge(kActAcquire);
+        if (inst < 0 || inst >= p.num_inst) {  // cannot happen: every stored node names its instance
+          if (tid == 0) {
+            atomicMax(ctr_i32(p, kError), 2);
+            store_relaxed(ctr_i32(p, kAbort), 1);
+          }
+          break;
+        }
+        if (inst != cur) {
+          if (tid == 0 && cur >= 0) bits_report_nodes(p, cur, unreported);
+          unreported = 0;
+          cur_n = load_adjacency<W>(p, inst, adj_lds, r);
+          const Instance in = p.inst[inst];
+          cur = inst;
+          cur_k = in.k;
+          cur_vtx = in.vtx_off;
+          ++insts;
+        }
+        if (got == 2) {
+          const int rejected = __builtin_amdgcn_readfirstlane(
+              load_relaxed(&p.ist[inst].err_row) != kNoRow);
+          if (rejected) {  // rejected input: no search (PVC: the instance is settled)
+            if (PVC && tid == 0) fetch_add(ctr_i32(p, kOpen), -1);
+            continue;
+          }
+          root_bits<W>(L, cur_n);
+          pending = -1;
+        }
+        clk.charge(kActOther);
       }
-      clk.charge(kActAcquire);
       if (pending >= 0) remove_neighbourhood_bits<W>(L, pending, adj_lds);
       clk.charge(kActBranch);
       have = true;
     }
 
-    ++nodes;
-    if (p.node_budget > 0 && nodes - budget_mark >= p.budget_chunk) {
-      if (tid == 0) {
-        const unsigned long long total =
-            fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
-        if (static_cast<int64_t>(total) + (nodes - budget_mark) >= p.node_budget)
-          store_relaxed(ctr_i32(p, kAbort), 1);
-      }
-      budget_mark = nodes;
+    // node header: global stop, the instance's flags and its current best
+    const int stop = __builtin_amdgcn_readfirstlane(search_stopped(p) ? 1 : 0);
+    const int drop = __builtin_amdgcn_readfirstlane(
+        load_relaxed(&p.ist[cur].aborted) | (PVC ? load_relaxed(&p.ist[cur].found) : 0));
+    const int32_t best = PVC ? 0 : __builtin_amdgcn_readfirstlane(load_relaxed(&p.ist[cur].best));
+    clk.charge(kActOther);
+    if (stop) break;
+    if (drop) {  // answered or out of budget: drop this node and the rest of the sub-tree
+      have = false;
+      top = bot;
+      continue;
     }
 
-    const int64_t bound = PVC ? p.k : static_cast<int64_t>(best) - 1;
-    clk.charge(kActOther);
+    ++nodes;
+    ++unreported;
+    if (p.node_budget > 0 && unreported >= p.budget_chunk) {
+      if (tid == 0) bits_report_nodes(p, cur, unreported);
+      unreported = 0;
+    }
+
+    const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(best) - 1;
     reduce_bits<W>(r, L, adj_lds, bound, p.rules);
     clk.charge(kActReduce);
 
@@ -546,17 +597,12 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     }
     if (edges == 0) {  // a vertex cover of size |S|
       int won = 0;
-      if (tid == 0) {
-        if (PVC) {
-          won = atomicCAS(ctr_i32(p, kFound), 0, wg + 1) == 0;
-        } else {
-          const unsigned long long key =
-              (static_cast<unsigned long long>(L.s) << 32) | static_cast<uint32_t>(wg);
-          won = atomicMin(ctr_u64(p, kBestKey), key) > key;
-        }
+      if (tid == 0) won = bits_claim<PVC>(p, cur, L.s);
+      if (__builtin_amdgcn_readfirstlane(won)) {
+        write_cover<W>(p.covers + cur_vtx, L, cur_n);
+        __threadfence();
+        if (tid == 0) bits_publish<PVC>(p, cur, L.s);
       }
-      if (__builtin_amdgcn_readfirstlane(won))
-        write_cover<W>(p.covers + static_cast<size_t>(wg) * p.cover_stride, L, p.n);
       clk.charge(kActOther);
       have = false;
       continue;
@@ -570,7 +616,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
       const bool from_stack = top > bot;
       const int32_t* oldest =
           from_stack ? stack + static_cast<size_t>(bot % p.depth_cap) * kStride : nullptr;
-      if (bits_enqueue<W>(p, c, L, vmax, oldest)) {
+      if (bits_enqueue<W>(p, c, L, vmax, oldest, cur)) {
         ++enqueues;
         if (from_stack) ++bot;
         else kept_local = false;
@@ -584,7 +630,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         }
         break;
       }
-      bits_store<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, vmax);
+      bits_store<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, vmax, cur);
       ++top;
       ++pushes;
       if (top - bot > max_depth) max_depth = top - bot;
@@ -596,8 +642,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   clk.end();
 
   if (tid == 0) {
-    if (p.node_budget > 0 && nodes > budget_mark)
-      fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
+    if (cur >= 0) bits_report_nodes(p, cur, unreported);
     WgStats w{};
     w.nodes = nodes;
     w.pushes = pushes;
@@ -605,25 +650,26 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     w.enqueues = enqueues;
     w.dequeues = dequeues;
     w.max_depth = max_depth;
+    w.instances = static_cast<int32_t>(insts);
     for (int a = 0; a < kNumActivities; ++a) w.cycles[a] = static_cast<int64_t>(clk.cycles[a]);
     p.wg_stats[wg] = w;
   }
 }
 
-// The reduction rules of one node on a degree array in device memory (-1 = in the cover).
+// The reduction rules of one node on a degree array in device memory (-1 = in the cover),
+// instance 0 of the launch.
 template <int W>
 __global__ void __launch_bounds__(64) bitset_reduce_kernel(Params p, int32_t* deg, int32_t* s,
-                                                           int64_t bound, DevResult* res) {
+                                                           int64_t bound) {
   extern __shared__ uint64_t adj_lds[];
-  if (threadIdx.x == 0) res->err_row = load_relaxed(ctr_i32(p, kErrRow));
-  if (load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF) return;
+  if (__builtin_amdgcn_readfirstlane(load_relaxed(&p.ist[0].err_row)) != kNoRow) return;
   Rows<W> r;
-  load_adjacency<W>(p, adj_lds, r);
+  const int n = load_adjacency<W>(p, 0, adj_lds, r);
   Live<W> L;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const int v = w * 64 + lane_id();
-    L.bits[w] = ballot(v < p.n && deg[v] >= 0);
+    L.bits[w] = ballot(v < n && deg[v] >= 0);
   }
   L.s = __builtin_amdgcn_readfirstlane(*s);
   reduce_bits<W>(r, L, adj_lds, bound, p.rules);
@@ -632,19 +678,12 @@ __global__ void __launch_bounds__(64) bitset_reduce_kernel(Params p, int32_t* de
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const int v = w * 64 + lane_id();
-    if (v < p.n) deg[v] = held_live(L, w) ? d[w] : -1;
+    if (v < n) deg[v] = held_live(L, w) ? d[w] : -1;
   }
   if (threadIdx.x == 0) *s = L.s;
 }
 
 // ---- launchers ---------------------------------------------------------------------------------
-
-hipError_t launch_bitset_pack(const Params& p, hipStream_t stream) {
-  int blocks = (p.n + 255) / 256;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(bitset_pack_kernel, dim3(blocks), dim3(256), 0, stream, p);
-  return hipGetLastError();
-}
 
 template <int W>
 static const void* bitset_traverse_fn(bool pvc, bool prof) {
@@ -663,17 +702,18 @@ static const void* bitset_fn(int words, bool pvc, bool prof) {
   }
 }
 
-size_t bitset_lds_bytes(int n, int words) { return static_cast<size_t>(n) * words * 8; }
+size_t bitset_lds_bytes(int n_max, int words) { return static_cast<size_t>(n_max) * words * 8; }
 
-int bitset_stride(int words) { return ((2 * words + 2) + 3) & ~3; }
+int bitset_stride(int words) { return ((2 * words + 3) + 3) & ~3; }
 
-hipError_t launch_bitset_greedy(const Params& p, DevResult* res, hipStream_t stream) {
-  const size_t lds = bitset_lds_bytes(p.n, p.words);
+hipError_t launch_bitset_greedy(const Params& p, hipStream_t stream) {
+  const size_t lds = bitset_lds_bytes(p.n_max, p.words);
+  const dim3 grid(p.num_inst < 65535 ? p.num_inst : 65535);
   switch (p.words) {
-    case 1: hipLaunchKernelGGL(bitset_greedy_kernel<1>, dim3(1), dim3(64), lds, stream, p, res); break;
-    case 2: hipLaunchKernelGGL(bitset_greedy_kernel<2>, dim3(1), dim3(64), lds, stream, p, res); break;
-    case 3: hipLaunchKernelGGL(bitset_greedy_kernel<3>, dim3(1), dim3(64), lds, stream, p, res); break;
-    default: hipLaunchKernelGGL(bitset_greedy_kernel<4>, dim3(1), dim3(64), lds, stream, p, res); break;
+    case 1: hipLaunchKernelGGL(bitset_greedy_kernel<1>, grid, dim3(64), lds, stream, p); break;
+    case 2: hipLaunchKernelGGL(bitset_greedy_kernel<2>, grid, dim3(64), lds, stream, p); break;
+    case 3: hipLaunchKernelGGL(bitset_greedy_kernel<3>, grid, dim3(64), lds, stream, p); break;
+    default: hipLaunchKernelGGL(bitset_greedy_kernel<4>, grid, dim3(64), lds, stream, p); break;
   }
   return hipGetLastError();
 }
@@ -683,24 +723,24 @@ hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStrea
   void* kargs[] = {&args};
   // plain launch; see launch_traverse for why co-residency is not required
   return hipLaunchKernel(bitset_fn(p.words, pvc, prof), dim3(p.num_wg), dim3(64), kargs,
-                         bitset_lds_bytes(p.n, p.words), stream);
+                         bitset_lds_bytes(p.n_max, p.words), stream);
 }
 
 hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,
-                                DevResult* res, hipStream_t stream) {
-  const size_t lds = bitset_lds_bytes(p.n, p.words);
+                                hipStream_t stream) {
+  const size_t lds = bitset_lds_bytes(p.n_max, p.words);
   switch (p.words) {
-    case 1: hipLaunchKernelGGL(bitset_reduce_kernel<1>, dim3(1), dim3(64), lds, stream, p, deg, s, bound, res); break;
-    case 2: hipLaunchKernelGGL(bitset_reduce_kernel<2>, dim3(1), dim3(64), lds, stream, p, deg, s, bound, res); break;
-    case 3: hipLaunchKernelGGL(bitset_reduce_kernel<3>, dim3(1), dim3(64), lds, stream, p, deg, s, bound, res); break;
-    default: hipLaunchKernelGGL(bitset_reduce_kernel<4>, dim3(1), dim3(64), lds, stream, p, deg, s, bound, res); break;
+    case 1: hipLaunchKernelGGL(bitset_reduce_kernel<1>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
+    case 2: hipLaunchKernelGGL(bitset_reduce_kernel<2>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
+    case 3: hipLaunchKernelGGL(bitset_reduce_kernel<3>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
+    default: hipLaunchKernelGGL(bitset_reduce_kernel<4>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
   }
   return hipGetLastError();
 }
 
-hipError_t bitset_occupancy(int words, bool pvc, bool prof, int n, int* blocks_per_cu) {
+hipError_t bitset_occupancy(int words, bool pvc, bool prof, int n_max, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bitset_fn(words, pvc, prof),
-                                                      64, bitset_lds_bytes(n, words));
+                                                      64, bitset_lds_bytes(n_max, words));
 }
 
 }  // namespace vc

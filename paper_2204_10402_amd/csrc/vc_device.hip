@@ -431,16 +431,6 @@ __device__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int str
   }
 }
 
-// The row pointers a kernel reads: a copy in LDS right after the node when the host found room
-// for it (one LDS access instead of an L2 round trip at the head of every row walk), else the
-// input array itself. Whole workgroup; ends with a barrier.
-__device__ const int32_t* stage_row_ptr(const Params& p, int32_t* st) {
-  if (!p.rp_lds) return p.rp;
-  int32_t* dst = st + p.stride;
-  for (int i = threadIdx.x; i <= p.n; i += blockDim.x) dst[i] = p.rp[i];
-  __syncthreads();
-  return dst;
-}
 
 // Copy a stored node between two device-memory slots with the same thread-to-word mapping as
 // node_store / node_load, so each thread reads back words it wrote itself.
@@ -456,12 +446,64 @@ __device__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stri
   for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
 }
 
-// Whole workgroup: donate a deferred child to the worklist; true if the worklist took it. The
-// child is the stored node at `oldest` (the bottom of this workgroup's stack) when that is not
-// null, else the node in LDS with `pending` as its branch vertex.
+// ---- instances -------------------------------------------------------------------------------
+
+// Whole workgroup: make instance j the one the node operations work on. Its row pointers are
+// copied into LDS right after the node when the launch has room for them (one LDS access
+// instead of an L2 round trip at the head of every row walk); the copy ends with a barrier.
+__device__ Node load_instance(const Params& p, int j, int32_t* st, int32_t* heads) {
+  const Instance in = p.inst[j];
+  const int32_t* rp = p.rp_all + in.rp_off;
+  if (p.rp_lds) {
+    int32_t* dst = st + p.stride;
+    for (int i = threadIdx.x; i <= in.n; i += blockDim.x) dst[i] = rp[i];
+    __syncthreads();
+    rp = dst;
+  }
+  return Node{st, in.n, rp, p.ci_all + in.ci_off, heads};
+}
+
+// Whole workgroup: the root of instance j in LDS -- the input's degree array, s = 0, nothing
+// pending, the instance in the last word. Ends with a barrier.
+__device__ void build_root(const Params& p, const Node nd, int j) {
+  for (int v = threadIdx.x; v < p.stride; v += blockDim.x) {
+    int32_t x = 0;
+    if (v < nd.n) x = nd.rp[v + 1] - nd.rp[v];
+    else if (v == nd.n + 1) x = -1;
+    else if (v == p.stride - 1) x = j;
+    nd.st[v] = x;
+  }
+  __syncthreads();
+}
+
+// Launch-local instance holding packed vertex i (or CSR entry i): the last instance whose
+// first index is <= i. Instances with no vertices (entries) share their first index with the
+// next one, so the search lands on the instance that owns i.
+__device__ __forceinline__ int instance_of_vertex(const Params& p, int64_t i) {
+  int lo = 0, hi = p.num_inst - 1;
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo + 1) >> 1);
+    if (p.inst[mid].vtx_first <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ int instance_of_entry(const Params& p, int64_t i) {
+  int lo = 0, hi = p.num_inst - 1;
+  while (lo < hi) {
+    const int mid = lo + ((hi - lo + 1) >> 1);
+    if (p.inst[mid].ent_first <= i) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---- worklist ---------------------------------------------------------------------------------
+
+// Whole workgroup: donate a deferred child of instance `inst` to the worklist; true if the
+// worklist took it. The child is the stored node at `oldest` (the bottom of this workgroup's
+// stack) when that is not null, else the node in LDS with `pending` as its branch vertex.
 __device__ bool try_enqueue(const Params& p, const Node nd, Ctrl& c, int pending,
-                            const int32_t* oldest) {
-  if (!enqueue_begin(p, c)) return false;
+                            const int32_t* oldest, int inst) {
+  if (!enqueue_begin(p, c, inst)) return false;
   int32_t* dst = p.payload + static_cast<size_t>(c.slot) * p.stride;
   if (oldest) node_copy(dst, oldest, p.stride);
   else node_store(dst, nd.st, p.stride, nd.n, pending);
@@ -469,177 +511,206 @@ __device__ bool try_enqueue(const Params& p, const Node nd, Ctrl& c, int pending
   return true;
 }
 
-// Whole workgroup: take a node from the worklist into LDS. Returns 1 on success, 0 when the
-// whole search is finished, -1 when it is being stopped.
-__device__ int dequeue(const Params& p, const Node nd, Ctrl& c) {
-  const int status = dequeue_begin(p, c);
-  if (status != 1) return status;
-  node_load(nd.st, p.payload + static_cast<size_t>(c.slot) * p.stride, p.stride);
-  dequeue_finish(p, c);
-  return 1;
-}
-
 // ---- kernels ---------------------------------------------------------------------------------
 
-// Zero the control lines, mark every worklist slot free, publish slot 0 (the root, written by
-// prepare_kernel) and the single outstanding sub-tree it stands for.
+// Zero the control lines and the result block, mark every worklist slot free, and set up the
+// per-instance state: nothing rejected yet, one outstanding sub-tree (the root) each. Every
+// instance's root is handed out by the root ticket counter, so the worklist starts empty.
 __global__ void init_kernel(Params p, DevResult* res) {
-  for (int i = threadIdx.x; i < kNumCounters * kCounterStride; i += blockDim.x) p.ctr[i] = 0;
-  for (uint32_t i = threadIdx.x; i < p.q_cap; i += blockDim.x) p.seq[i] = (i == 0) ? 1u : 0u;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    *ctr_i32(p, kQCount) = 1;
-    *ctr_u64(p, kQHead) = 0;
-    *ctr_u64(p, kQTail) = 1;
-    *ctr_i32(p, kWork) = 1;
-    *ctr_u64(p, kBestKey) = ~0ull;
-    *ctr_i32(p, kErrRow) = 0x7FFFFFFF;
-    char* r = reinterpret_cast<char*>(res);
-    for (size_t i = 0; i < sizeof(DevResult); ++i) r[i] = 0;
-    res->wg_nodes_min = INT64_MAX;
+  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int gsize = gridDim.x * blockDim.x;
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i < kNumCounters * kCounterStride; i += blockDim.x) p.ctr[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      *ctr_i32(p, kWork) = p.num_inst;
+      *ctr_i32(p, kOpen) = p.num_inst;
+      char* r = reinterpret_cast<char*>(res);
+      for (size_t i = 0; i < sizeof(DevResult); ++i) r[i] = 0;
+      res->wg_nodes_min = INT64_MAX;
+    }
+  }
+  for (uint32_t i = gtid; i < p.q_cap; i += gsize) p.seq[i] = 0u;
+  for (int j = gtid; j < p.num_inst; j += gsize) {
+    InstState s{};
+    s.err_row = kNoRow;
+    s.best = 0x7FFFFFFF;
+    s.work = 1;
+    s.greedy = -1;
+    p.ist[j] = s;
   }
 }
 
-// Check the CSR (simple undirected graph, §II-A) and write the root node -- the input's
-// degree array, s = 0, no pending vertex -- into worklist slot 0. Index i < stride checks row
-// i's bounds and writes its degree; index i < nnz checks entry i: in range, not a self-loop,
-// larger than the entry before it in its row, and present in reverse. Every read is
-// bounds-checked before it is made, so a malformed input cannot send a thread out of its
-// arrays. The smallest offending row is recorded.
-__global__ void prepare_kernel(Params p) {
-  const int n = p.n, nnz = p.nnz;
-  int32_t* root = p.payload;
-  int32_t local_sum = 0;
-  // the bitset kernels build their own root node (bitset_pack_kernel)
-  const int vertex_items = p.words ? n : p.stride;
-  const int total = vertex_items > nnz ? vertex_items : nnz;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-    if (i < vertex_items) {
-      if (i >= n) {
-        root[i] = (i == n + 1) ? -1 : 0;
-      } else {
-        const int beg = p.rp[i], end = p.rp[i + 1];
-        const bool bad = (i == 0 && beg != 0) || (i == n - 1 && end != nnz) || beg < 0 ||
-                         end < beg || end > nnz;
-        if (bad) atomicMin(ctr_i32(p, kErrRow), i);
-        const int32_t d = bad ? 0 : end - beg;
-        if (!p.words) root[i] = d;
-        local_sum += d;
+// Check every graph of the launch (simple undirected, §II-A). Index i < vertices checks row
+// i's bounds (and, for the bitset kernels, packs the row into adjacency words); index i <
+// entries checks one CSR entry: in range, not a self-loop, larger than the entry before it in
+// its row, and present in reverse. Every read is bounds-checked before it is made, so a
+// malformed input cannot send a thread out of its instance's arrays. Each instance keeps the
+// smallest offending row.
+__global__ void prepare_kernel(Params p, int64_t vertices, int64_t entries) {
+  const int64_t total = vertices > entries ? vertices : entries;
+  const int64_t gsize = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
+       i += gsize) {
+    if (i < vertices) {
+      const int j = instance_of_vertex(p, i);
+      const Instance in = p.inst[j];
+      const int v = static_cast<int>(i - in.vtx_first);
+      const int32_t* rp = p.rp_all + in.rp_off;
+      const int32_t* ci = p.ci_all + in.ci_off;
+      const int beg = rp[v], end = rp[v + 1];
+      const bool bad = (v == 0 && beg != 0) || (v == in.n - 1 && end != in.nnz) || beg < 0 ||
+                       end < beg || end > in.nnz;
+      if (bad) atomicMin(&p.ist[j].err_row, v);
+      if (p.words && !bad) {
+        uint64_t row[4] = {0, 0, 0, 0};
+        for (int e = beg; e < end; ++e) {
+          const int u = ci[e];
+          if (u >= 0 && u < in.n) row[u >> 6] |= 1ull << (u & 63);
+        }
+        uint64_t* dst = p.bits + (static_cast<int64_t>(in.vtx_first) + v) * p.words;
+        for (int w = 0; w < p.words; ++w) dst[w] = row[w];
       }
     }
-    if (i < nnz) {
-      const int v = owner_row(p.rp, n, i);
-      const int beg = p.rp[v], end = p.rp[v + 1];
-      if (beg <= i && i < end && beg >= 0 && end <= nnz) {  // otherwise row bounds are bad
-        const int u = p.ci[i];
-        bool bad = u < 0 || u >= n || u == v || (i > beg && p.ci[i - 1] >= u);
+    if (i < entries) {
+      const int j = instance_of_entry(p, i);
+      const Instance in = p.inst[j];
+      const int e = static_cast<int>(i - in.ent_first);
+      const int32_t* rp = p.rp_all + in.rp_off;
+      const int32_t* ci = p.ci_all + in.ci_off;
+      const int v = owner_row(rp, in.n, e);
+      const int beg = rp[v], end = rp[v + 1];
+      if (beg <= e && e < end && beg >= 0 && end <= in.nnz) {  // otherwise row bounds are bad
+        const int u = ci[e];
+        bool bad = u < 0 || u >= in.n || u == v || (e > beg && ci[e - 1] >= u);
         if (!bad) {
-          const int ub = p.rp[u], ue = p.rp[u + 1];
-          bad = ub < 0 || ue < ub || ue > nnz;
+          const int ub = rp[u], ue = rp[u + 1];
+          bad = ub < 0 || ue < ub || ue > in.nnz;
           if (!bad) {
             int lo = ub, hi = ue;
             while (lo < hi) {
               const int mid = lo + ((hi - lo) >> 1);
-              if (p.ci[mid] < v) lo = mid + 1; else hi = mid;
+              if (ci[mid] < v) lo = mid + 1; else hi = mid;
             }
-            bad = lo >= ue || p.ci[lo] != v;
+            bad = lo >= ue || ci[lo] != v;
           }
         }
-        if (bad) atomicMin(ctr_i32(p, kErrRow), v);
+        if (bad) atomicMin(&p.ist[j].err_row, v);
       }
     }
   }
-  local_sum = wave_sum(local_sum);
-  if (lane_id() == 0 && local_sum) atomicAdd(ctr_i32(p, kEdges0), local_sum);
 }
 
-// Greedy approximation (§II-B, used as the initial best and the stack depth bound, §IV-E):
-// degree-one and degree-two-triangle rules, then a maximum-degree vertex into the cover, until
-// no edge is left. One workgroup. Its cover is the last cover buffer.
-__global__ void __launch_bounds__(1024) greedy_kernel(Params p, DevResult* res) {
+// Greedy approximation (§II-B, used as an instance's first best and for the stack depth bound,
+// §IV-E): degree-one and degree-two-triangle rules, then a maximum-degree vertex into the
+// cover, until no edge is left. One workgroup per instance (a grid-stride loop over the
+// launch's instances); the cover goes to the instance's cover output.
+__global__ void __launch_bounds__(1024) greedy_kernel(Params p) {
   extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
   __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = reinterpret_cast<int32_t*>(lds4);
-  if (threadIdx.x == 0) {
-    const int32_t err_row = load_relaxed(ctr_i32(p, kErrRow));
-    res->err_row = err_row;
-    res->edges0 = load_relaxed(ctr_i32(p, kEdges0)) / 2;
-    res->greedy = 0;
-    c.err = err_row != 0x7FFFFFFF;
-    c.flag_epoch = -1;
-  }
-  __syncthreads();
-  if (c.err) return;
-  const Node nd{st, p.n, stage_row_ptr(p, st), p.ci, heads};
-  node_load(st, p.payload, p.stride);  // the root written by prepare_kernel
-  __syncthreads();
+  if (threadIdx.x == 0) c.flag_epoch = -1;
   int epoch = 0;
-  const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
-  for (;;) {
-    reduce_node(nd, c, unbounded, kRuleDeg1 | kRuleTri, epoch);
-    int vmax, dmax;
-    int32_t degsum;
-    max_degree_and_sum(nd, c, vmax, dmax, degsum);
-    if (degsum == 0) break;
-    remove_vertex(nd, vmax);
-  }
-  const int s = st[p.n];
-  uint8_t* cov = p.covers + static_cast<size_t>(p.greedy_slot) * p.cover_stride;
-  for (int v = threadIdx.x; v < p.n; v += blockDim.x) cov[v] = st[v] == kSent;
-  if (threadIdx.x == 0) {
-    *ctr_u64(p, kBestKey) =
-        (static_cast<unsigned long long>(s) << 32) | static_cast<uint32_t>(p.greedy_slot);
-    res->greedy = s;
+  for (int j = blockIdx.x; j < p.num_inst; j += gridDim.x) {
+    if (threadIdx.x == 0) c.err = load_relaxed(&p.ist[j].err_row) != kNoRow;
+    __syncthreads();
+    const bool skip = c.err;
+    __syncthreads();  // every thread has read c.err before thread 0 writes it again
+    if (skip) continue;
+    const Node nd = load_instance(p, j, st, heads);
+    build_root(p, nd, j);
+    const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
+    for (;;) {
+      reduce_node(nd, c, unbounded, kRuleDeg1 | kRuleTri, epoch);
+      int vmax, dmax;
+      int32_t degsum;
+      max_degree_and_sum(nd, c, vmax, dmax, degsum);
+      if (degsum == 0) break;
+      remove_vertex(nd, vmax);
+    }
+    const int s = st[nd.n];
+    uint8_t* cov = p.covers + p.inst[j].vtx_off;
+    for (int v = threadIdx.x; v < nd.n; v += blockDim.x) cov[v] = st[v] == kSent;
+    if (threadIdx.x == 0) {
+      p.ist[j].best = s;
+      p.ist[j].greedy = s;
+    }
+    __syncthreads();  // the node and row pointers in LDS are read before the next instance
   }
 }
 
-// The hybrid traversal (§IV-A, Fig. 4; PVC differences in §IV-A, termination §IV-C).
+// Thread 0: claim the right to record a cover of size s for instance j (§IV-A: atomic best /
+// found). PVC: the first cover found wins. MVC: a cover wins if it lowers the instance's best;
+// the winner then takes the instance's lock, and keeps it only if no smaller cover has been
+// claimed meanwhile, so the last cover written under the lock is one of the final best size.
+template <bool PVC>
+__device__ int claim_solution(const Params& p, int j, int32_t s) {
+  InstState* is = p.ist + j;
+  if (PVC) return atomicCAS(&is->found, 0, 1) == 0;
+  if (atomicMin(&is->best, s) <= s) return 0;
+  lock_acquire(&is->lock);
+  if (load_relaxed(&is->best) == s) return 1;
+  store_release(&is->lock, 0);
+  return 0;
+}
+
+// Thread 0, after the whole workgroup has written the cover and fenced it: finish the claim.
+template <bool PVC>
+__device__ void publish_solution(const Params& p, int j, int32_t s) {
+  InstState* is = p.ist + j;
+  if (PVC) {
+    store_relaxed(&is->best, s);
+    fetch_add(ctr_i32(p, kOpen), -1);
+  } else {
+    store_release(&is->lock, 0);
+  }
+}
+
+// Thread 0: add this workgroup's nodes on instance j to the instance's counter, and mark the
+// instance out of budget once the counter reaches the per-instance budget.
+__device__ __forceinline__ void report_nodes(const Params& p, int j, int64_t count) {
+  if (count <= 0) return;
+  unsigned long long* total = reinterpret_cast<unsigned long long*>(&p.ist[j].nodes);
+  const unsigned long long before = fetch_add(total, static_cast<unsigned long long>(count));
+  if (p.node_budget > 0 && static_cast<int64_t>(before) + count >= p.node_budget)
+    store_relaxed(&p.ist[j].aborted, 1);
+}
+
+// The hybrid traversal (§IV-A, Fig. 4; PVC differences in §IV-A, termination §IV-C) over every
+// instance of the launch. A workgroup takes the root of an unstarted instance or a node from
+// the worklist, walks that node's sub-tree depth first with its stack, and loads an instance
+// (row pointers) only when the node it takes belongs to another one than the last.
 template <bool PVC, bool PROF>
 __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
   __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = reinterpret_cast<int32_t*>(lds4);
-  const int n = p.n;
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    c.err = load_relaxed(ctr_i32(p, kErrRow)) != 0x7FFFFFFF ||
-            load_relaxed(ctr_i32(p, kEdges0)) == 0;
-    c.flag_epoch = -1;
-  }
-  __syncthreads();
-  if (c.err) {
-    if (tid == 0) p.wg_stats[wg] = WgStats{};
-    return;
-  }
-  const Node nd{st, n, stage_row_ptr(p, st), p.ci, heads};
+  if (tid == 0) c.flag_epoch = -1;
   ActivityClock<PROF> clk;
   clk.begin();
 
   int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * p.stride;
   // The stack is a ring of depth_cap entries holding [bot, top): pops take the top, donations
-  // take the bottom (the oldest deferred child, nearest its sub-tree root).
+  // take the bottom (the oldest deferred child, nearest its sub-tree root). Every entry belongs
+  // to the instance of the sub-tree being walked.
   int top = 0, bot = 0;
   bool have = false;      // a node is in LDS and still to be visited
-  bool holding = false;   // this workgroup holds a sub-tree taken from the worklist
+  bool holding = false;   // this workgroup holds a sub-tree (a root or a worklist node)
+  int cur = -1;           // instance of the node in LDS
+  int32_t cur_k = 0, cur_vtx = 0;
+  Node nd{st, 0, nullptr, nullptr, heads};
   int epoch = 0;
-  int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0;
+  int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0, insts = 0;
+  int64_t unreported = 0;  // nodes on `cur` not yet added to its counter
   int max_depth = 0;
-  int64_t budget_mark = 0;
 
   for (;;) {
-    // node header: global flags and the current best, read once and broadcast
-    if (tid == 0) {
-      c.stop = load_relaxed(ctr_i32(p, kAbort)) | (PVC ? load_relaxed(ctr_i32(p, kFound)) : 0);
-      c.best = PVC ? 0 : static_cast<int32_t>(load_relaxed(ctr_u64(p, kBestKey)) >> 32);
-    }
-    __syncthreads();
-    clk.charge(kActOther);
-    if (c.stop) break;
-
     if (!have) {
+      __syncthreads();  // every thread has read the last broadcast before thread 0 writes
       if (top > bot) {
         --top;
         node_load(st, stack + static_cast<size_t>(top % p.depth_cap) * p.stride, p.stride);
@@ -647,44 +718,94 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         __syncthreads();
       } else {
         if (holding) {
-          if (tid == 0) fetch_add(ctr_i32(p, kWork), -1);
+          if (tid == 0) release_work(p, cur);
           holding = false;
         }
-        const int got = dequeue(p, nd, c);
-        clk.charge(kActAcquire);
-        if (got != 1) break;
+        const int got = dequeue_begin(p, c);
+        if (got != 1 && got != 2) {
+          clk.charge(kActAcquire);
+          break;
+        }
+        int j;
+        if (got == 1) {
+          node_load(st, p.payload + static_cast<size_t>(c.slot) * p.stride, p.stride);
+          dequeue_finish(p, c);  // ends with a barrier: the node is visible to every thread
+          j = st[p.stride - 1];
+          ++dequeues;
+          if (j < 0 || j >= p.num_inst) {  // cannot happen: every stored node names its instance
+            if (tid == 0) {
+              atomicMax(ctr_i32(p, kError), 2);
+              store_relaxed(ctr_i32(p, kAbort), 1);
+            }
+            break;
+          }
+        } else {
+          j = static_cast<int>(c.slot);  // an unstarted instance: its root
+        }
         holding = true;
-        ++dequeues;
+        clk.charge(kActAcquire);
+        if (j != cur) {
+          if (tid == 0 && cur >= 0) report_nodes(p, cur, unreported);
+          unreported = 0;
+          nd = load_instance(p, j, st, heads);
+          const Instance in = p.inst[j];
+          cur = j;
+          cur_k = in.k;
+          cur_vtx = in.vtx_off;
+          ++insts;
+        }
+        if (got == 2) {
+          // c.err, not c.status: slow waves may still be reading the dequeue status
+          if (tid == 0) c.err = load_relaxed(&p.ist[j].err_row) != kNoRow;
+          __syncthreads();
+          if (c.err) {  // rejected input: no search (PVC: the instance is settled)
+            if (PVC && tid == 0) fetch_add(ctr_i32(p, kOpen), -1);
+            continue;
+          }
+          build_root(p, nd, j);
+        }
+        clk.charge(kActOther);
       }
-      clk.charge(kActAcquire);
-      const int pending = st[n + 1];
+      const int pending = st[nd.n + 1];
       if (pending >= 0) {
         __syncthreads();  // every thread has read the pending vertex
-        if (tid == 0) st[n + 1] = -1;
+        if (tid == 0) st[nd.n + 1] = -1;
         remove_neighbourhood(nd, pending);
       }
       clk.charge(kActBranch);
       have = true;
     }
 
-    ++nodes;
-    if (p.node_budget > 0 && nodes - budget_mark >= p.budget_chunk) {
-      if (tid == 0) {
-        const unsigned long long total =
-            fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
-        if (static_cast<int64_t>(total) + (nodes - budget_mark) >= p.node_budget)
-          store_relaxed(ctr_i32(p, kAbort), 1);
-      }
-      budget_mark = nodes;
+    // node header: global stop, the instance's flags and its current best, read once
+    if (tid == 0) {
+      InstState* is = p.ist + cur;
+      c.stop = search_stopped(p);
+      c.drop = load_relaxed(&is->aborted) | (PVC ? load_relaxed(&is->found) : 0);
+      c.best = PVC ? 0 : load_relaxed(&is->best);
+    }
+    __syncthreads();
+    clk.charge(kActOther);
+    if (c.stop) break;
+    if (c.drop) {  // answered or out of budget: drop this node and the rest of the sub-tree
+      have = false;
+      top = bot;
+      continue;
     }
 
-    const int64_t bound = PVC ? p.k : static_cast<int64_t>(c.best) - 1;
-    clk.charge(kActOther);
+    ++nodes;
+    ++unreported;
+    if (p.node_budget > 0 && unreported >= p.budget_chunk) {
+      if (tid == 0) report_nodes(p, cur, unreported);
+      unreported = 0;
+    }
+
+    const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(c.best) - 1;
     reduce_node(nd, c, bound, p.rules, epoch, clk);
     clk.charge(kActReduce);
 
     // stopping condition (§II-B): no cover of size <= bound below this node if r < 0 or
     // |E| > r^2 (every remaining degree is <= r once the high-degree rule has run)
+    const int n = nd.n;
     const int32_t s = st[n];
     const int64_t r = bound - s;
     if (r < 0) {
@@ -701,19 +822,14 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       continue;
     }
     if (edges == 0) {  // a vertex cover of size s
-      if (tid == 0) {
-        if (PVC) {
-          c.status = atomicCAS(ctr_i32(p, kFound), 0, wg + 1) == 0;
-        } else {
-          const unsigned long long key =
-              (static_cast<unsigned long long>(s) << 32) | static_cast<uint32_t>(wg);
-          c.status = atomicMin(ctr_u64(p, kBestKey), key) > key;
-        }
-      }
+      if (tid == 0) c.status = claim_solution<PVC>(p, cur, s);
       __syncthreads();
       if (c.status) {
-        uint8_t* cov = p.covers + static_cast<size_t>(wg) * p.cover_stride;
+        uint8_t* cov = p.covers + cur_vtx;
         for (int v = tid; v < n; v += blockDim.x) cov[v] = st[v] == kSent;
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) publish_solution<PVC>(p, cur, s);
       }
       clk.charge(kActOther);
       have = false;
@@ -728,7 +844,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       const bool from_stack = top > bot;
       const int32_t* oldest =
           from_stack ? stack + static_cast<size_t>(bot % p.depth_cap) * p.stride : nullptr;
-      if (try_enqueue(p, nd, c, vmax, oldest)) {
+      if (try_enqueue(p, nd, c, vmax, oldest, cur)) {
         ++enqueues;
         if (from_stack) ++bot;
         else kept_local = false;
@@ -755,8 +871,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   clk.end();
 
   if (tid == 0) {
-    if (p.node_budget > 0 && nodes > budget_mark)
-      fetch_add(ctr_u64(p, kNodes), static_cast<unsigned long long>(nodes - budget_mark));
+    if (cur >= 0) report_nodes(p, cur, unreported);
     WgStats w{};
     w.nodes = nodes;
     w.pushes = pushes;
@@ -764,73 +879,82 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     w.enqueues = enqueues;
     w.dequeues = dequeues;
     w.max_depth = max_depth;
+    w.instances = static_cast<int32_t>(insts);
     for (int a = 0; a < kNumActivities; ++a) w.cycles[a] = static_cast<int64_t>(clk.cycles[a]);
     p.wg_stats[wg] = w;
   }
 }
 
-// Index of the cover buffer holding the answer: >= 0, or -2 for "no cover" (rejected input,
-// edgeless graph, PVC no).
-__device__ __forceinline__ int32_t answer_buffer(const Params& p, int pvc) {
-  if (*ctr_i32(p, kErrRow) != 0x7FFFFFFF || *ctr_i32(p, kEdges0) == 0) return -2;
-  if (pvc) {
-    const int32_t f = *ctr_i32(p, kFound);
-    return f ? f - 1 : -2;
+// Add each lane's x to *dst (dst may differ between lanes, or be null): one atomic per distinct
+// destination in the wavefront. Whole wavefront, uniform control flow.
+__device__ void add_grouped(int32_t* dst, int32_t x) {
+  bool pending = dst != nullptr && x != 0;
+  const uint64_t mine_addr = reinterpret_cast<uint64_t>(dst);
+  for (;;) {
+    const uint64_t m = __builtin_amdgcn_ballot_w64(pending);
+    if (!m) break;
+    const int leader = first_lane(m);
+    const uint64_t target = readlane64(mine_addr, leader);
+    const bool mine = pending && mine_addr == target;
+    const int32_t sum = wave_sum(mine ? x : 0);
+    if (lane_id() == leader) atomicAdd(reinterpret_cast<int32_t*>(target), sum);
+    if (mine) pending = false;
   }
-  return static_cast<int32_t>(*ctr_u64(p, kBestKey) & 0xFFFFFFFFull);
 }
 
-// After the traversal (256-thread blocks, any grid): pick the answer, copy its cover out, check
-// the cover edge by edge (one thread per CSR entry) and count its vertices, and gather the
+// After the traversal (256-thread blocks, any grid): check each recorded cover edge by edge
+// (one thread per CSR entry) and count its vertices (one thread per vertex); clear the cover
+// output of instances without an answer (rejected, out of budget, PVC no); gather the
 // per-workgroup statistics.
-__global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_t* cover_out,
-                                                       DevResult* res) {
+__global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertices,
+                                                       int64_t entries, DevResult* res) {
   __shared__ int64_t buf[256];
-  const int32_t src = answer_buffer(p, pvc);
-  const bool valid = *ctr_i32(p, kErrRow) == 0x7FFFFFFF;
+  const int64_t total = vertices > entries ? vertices : entries;
+  const int64_t gsize = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x; base < total;
+       base += gsize) {
+    const int64_t i = base + threadIdx.x;
+    int32_t* ones_dst = nullptr;
+    int32_t one = 0;
+    if (i < vertices) {
+      const int j = instance_of_vertex(p, i);
+      const Instance in = p.inst[j];
+      const InstState is = p.ist[j];
+      const bool answer = is.err_row == kNoRow && !is.aborted && (!p.pvc || is.found);
+      uint8_t* cov = p.covers + in.vtx_off;
+      const int v = static_cast<int>(i - in.vtx_first);
+      if (answer) one = cov[v] != 0;
+      else cov[v] = 0;
+      ones_dst = &p.ist[j].cover_count;
+    }
+    add_grouped(ones_dst, one);
+    int32_t* bad_dst = nullptr;
+    int32_t bad = 0;
+    if (i < entries) {
+      const int j = instance_of_entry(p, i);
+      const Instance in = p.inst[j];
+      const InstState is = p.ist[j];
+      const bool answer = is.err_row == kNoRow && !is.aborted && (!p.pvc || is.found);
+      if (answer) {
+        const int32_t* rp = p.rp_all + in.rp_off;
+        const uint8_t* cov = p.covers + in.vtx_off;
+        const int e = static_cast<int>(i - in.ent_first);
+        const int v = owner_row(rp, in.n, e);
+        bad = cov[v] == 0 && cov[p.ci_all[in.ci_off + e]] == 0;
+      }
+      bad_dst = &p.ist[j].uncovered;
+    }
+    add_grouped(bad_dst, bad);
+  }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const int32_t edges0 = *ctr_i32(p, kEdges0) / 2;
-    res->err_row = *ctr_i32(p, kErrRow);
-    res->edges0 = edges0;
     res->aborted = *ctr_i32(p, kAbort);
     res->error = *ctr_i32(p, kError);
     res->q_max_count = *ctr_i32(p, kQMaxCount);
-    if (valid && edges0 == 0) {
-      res->size = 0;
-      res->yes = 1;
-    } else if (valid && pvc) {
-      res->size = -1;
-      res->yes = src >= 0;
-    } else if (valid) {
-      res->size = static_cast<int32_t>(*ctr_u64(p, kBestKey) >> 32);
-      res->yes = 1;
-    }
-  }
-  const uint8_t* from = src >= 0 ? p.covers + static_cast<size_t>(src) * p.cover_stride : nullptr;
-  int32_t bad = 0, ones = 0;
-  if (valid) {
-    const int total = p.n > p.nnz ? p.n : p.nnz;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < total; i += gridDim.x * blockDim.x) {
-      if (i < p.n) {
-        const uint8_t c = from ? from[i] : 0;
-        if (cover_out) cover_out[i] = c;
-        ones += c != 0;
-      }
-      if (i < p.nnz && from) {
-        const int v = owner_row(p.rp, p.n, i);
-        bad += from[v] == 0 && from[p.ci[i]] == 0;
-      }
-    }
-  }
-  bad = wave_sum(bad);
-  ones = wave_sum(ones);
-  if (lane_id() == 0) {
-    if (bad) atomicAdd(&res->uncovered, bad);
-    if (ones) atomicAdd(&res->cover_count, ones);
   }
   // per-workgroup statistics: only the blocks that cover workgroup slots
   if (static_cast<int>(blockIdx.x) * static_cast<int>(blockDim.x) >= p.num_wg) return;
-  int64_t nodes = 0, pushes = 0, pops = 0, enq = 0, deq = 0, mx = 0, mn = INT64_MAX, depth = 0;
+  int64_t nodes = 0, pushes = 0, pops = 0, enq = 0, deq = 0, insts = 0, mx = 0, mn = INT64_MAX,
+          depth = 0;
   int64_t cyc[kNumActivities] = {};
   for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < p.num_wg; w += gridDim.x * blockDim.x) {
     const WgStats s = p.wg_stats[w];
@@ -839,6 +963,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
     pops += s.pops;
     enq += s.enqueues;
     deq += s.dequeues;
+    insts += s.instances;
     mx = s.nodes > mx ? s.nodes : mx;
     mn = s.nodes < mn ? s.nodes : mn;
     depth = s.max_depth > depth ? s.max_depth : depth;
@@ -852,6 +977,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
   pops = block_reduce_256(pops, buf, add);
   enq = block_reduce_256(enq, buf, add);
   deq = block_reduce_256(deq, buf, add);
+  insts = block_reduce_256(insts, buf, add);
   mx = block_reduce_256(mx, buf, hi);
   mn = block_reduce_256(mn, buf, lo);
   depth = block_reduce_256(depth, buf, hi);
@@ -863,6 +989,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
     if (pops) atomicAdd(reinterpret_cast<ull*>(&res->pops), static_cast<ull>(pops));
     if (enq) atomicAdd(reinterpret_cast<ull*>(&res->enqueues), static_cast<ull>(enq));
     if (deq) atomicAdd(reinterpret_cast<ull*>(&res->dequeues), static_cast<ull>(deq));
+    if (insts) atomicAdd(reinterpret_cast<ull*>(&res->instances), static_cast<ull>(insts));
     atomicMax(reinterpret_cast<ull*>(&res->wg_nodes_max), static_cast<ull>(mx));
     atomicMin(reinterpret_cast<ull*>(&res->wg_nodes_min), static_cast<ull>(mn));
     atomicMax(&res->max_depth, static_cast<int32_t>(depth));
@@ -871,51 +998,76 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int pvc, uint8_
   }
 }
 
-// The reduction rules of one node, alone, on a degree array in device memory (one workgroup).
+// The reduction rules of one node, alone, on a degree array in device memory (instance 0 of
+// the launch, one workgroup). A rejected input leaves the degree array alone.
 __global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, int32_t* s,
-                                                      int64_t bound, DevResult* res) {
+                                                      int64_t bound) {
   extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
   __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = reinterpret_cast<int32_t*>(lds4);
   if (threadIdx.x == 0) {
-    const int32_t err_row = load_relaxed(ctr_i32(p, kErrRow));
-    res->err_row = err_row;
-    c.err = err_row != 0x7FFFFFFF;
+    c.err = load_relaxed(&p.ist[0].err_row) != kNoRow;
+    c.flag_epoch = -1;
   }
   __syncthreads();
-  if (c.err) return;  // rejected input: leave the degree array alone
+  if (c.err) return;
+  const Node nd = load_instance(p, 0, st, heads);
+  const int n = nd.n;
   for (int v = threadIdx.x; v < p.stride; v += blockDim.x)
-    st[v] = v < p.n ? deg[v] : (v == p.n ? *s : (v == p.n + 1 ? -1 : 0));
-  if (threadIdx.x == 0) c.flag_epoch = -1;
+    st[v] = v < n ? deg[v] : (v == n ? *s : (v == n + 1 ? -1 : 0));
   __syncthreads();
-  const Node nd{st, p.n, stage_row_ptr(p, st), p.ci, heads};
   int epoch = 0;
   reduce_node(nd, c, bound, p.rules, epoch);
-  for (int v = threadIdx.x; v < p.n; v += blockDim.x) deg[v] = st[v];
-  if (threadIdx.x == 0) *s = st[p.n];
+  for (int v = threadIdx.x; v < n; v += blockDim.x) deg[v] = st[v];
+  if (threadIdx.x == 0) *s = st[n];
+}
+
+// Largest greedy cover size over the launch's instances (the stack depth bound of MVC).
+__global__ void __launch_bounds__(256) max_greedy_kernel(Params p, int32_t* out) {
+  int32_t m = 0;
+  for (int j = threadIdx.x; j < p.num_inst; j += blockDim.x) {
+    const int32_t g = p.ist[j].greedy;
+    m = g > m ? g : m;
+  }
+  m = static_cast<int32_t>(wave_max(static_cast<uint64_t>(static_cast<uint32_t>(m))));
+  __shared__ int32_t part[4];
+  if (lane_id() == 0) part[wave_id()] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int32_t r = part[0];
+    for (int w = 1; w < static_cast<int>(blockDim.x >> 6); ++w) r = part[w] > r ? part[w] : r;
+    *out = r;
+  }
 }
 
 // ---- launchers ---------------------------------------------------------------------------------
 
+static int grid_for(int64_t items, int threads, int cap) {
+  int64_t blocks = (items + threads - 1) / threads;
+  if (blocks < 1) blocks = 1;
+  if (blocks > cap) blocks = cap;
+  return static_cast<int>(blocks);
+}
+
 hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream) {
-  hipLaunchKernelGGL(init_kernel, dim3(1), dim3(256), 0, stream, p, res);
+  const int64_t items = p.num_inst > static_cast<int64_t>(p.q_cap) ? p.num_inst : p.q_cap;
+  hipLaunchKernelGGL(init_kernel, dim3(grid_for(items, 256, 1024)), dim3(256), 0, stream, p, res);
   return hipGetLastError();
 }
 
-hipError_t launch_prepare(const Params& p, hipStream_t stream) {
-  const int threads = 256;
-  const int vertex_items = p.words ? p.n : p.stride;
-  const int items = vertex_items > p.nnz ? vertex_items : p.nnz;
-  int blocks = (items + threads - 1) / threads;
-  if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(prepare_kernel, dim3(blocks), dim3(threads), 0, stream, p);
+hipError_t launch_prepare(const Params& p, int64_t vertices, int64_t entries,
+                          hipStream_t stream) {
+  const int64_t items = vertices > entries ? vertices : entries;
+  hipLaunchKernelGGL(prepare_kernel, dim3(grid_for(items, 256, 4096)), dim3(256), 0, stream, p,
+                     vertices, entries);
   return hipGetLastError();
 }
 
-hipError_t launch_greedy(const Params& p, int32_t wg_size, DevResult* res, hipStream_t stream) {
-  const size_t lds = node_lds_bytes(p.stride, p.n, p.rp_lds);
-  hipLaunchKernelGGL(greedy_kernel, dim3(1), dim3(wg_size), lds, stream, p, res);
+hipError_t launch_greedy(const Params& p, int32_t wg_size, hipStream_t stream) {
+  const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
+  hipLaunchKernelGGL(greedy_kernel, dim3(p.num_inst < 65535 ? p.num_inst : 65535), dim3(wg_size),
+                     lds, stream, p);
   return hipGetLastError();
 }
 
@@ -928,33 +1080,35 @@ static const void* traverse_fn(bool pvc, bool prof) {
 
 // A plain launch: the grid is sized by the occupancy API so that all workgroups are normally
 // resident together, but the search does not depend on it. A workgroup only ever waits for
-// workgroups that have already taken a worklist ticket (and are therefore running); one that
-// starts late finds either work or a zero outstanding-work counter.
+// workgroups that have already taken a worklist ticket or an instance's lock (and are
+// therefore running); one that starts late finds either work or a zero outstanding-work
+// counter.
 hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size,
                            hipStream_t stream) {
-  const size_t lds = node_lds_bytes(p.stride, p.n, p.rp_lds);
+  const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
   Params args = p;
   void* kargs[] = {&args};
   return hipLaunchKernel(traverse_fn(pvc, prof), dim3(p.num_wg), dim3(wg_size), kargs, lds, stream);
 }
 
-hipError_t launch_finalize(bool pvc, const Params& p, uint8_t* cover_out, DevResult* res,
+hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, DevResult* res,
                            hipStream_t stream) {
-  const int threads = 256;
-  int items = p.n > p.nnz ? p.n : p.nnz;
+  int64_t items = vertices > entries ? vertices : entries;
   if (p.num_wg > items) items = p.num_wg;
-  int blocks = (items + threads - 1) / threads;
-  if (blocks < 1) blocks = 1;
-  if (blocks > 1024) blocks = 1024;
-  hipLaunchKernelGGL(finalize_kernel, dim3(blocks), dim3(threads), 0, stream, p, pvc ? 1 : 0,
-                     cover_out, res);
+  hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(items, 256, 1024)), dim3(256), 0, stream, p,
+                     vertices, entries, res);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
-                         int64_t bound, DevResult* res, hipStream_t stream) {
-  const size_t lds = node_lds_bytes(p.stride, p.n, p.rp_lds);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(wg_size), lds, stream, p, deg, s, bound, res);
+                         int64_t bound, hipStream_t stream) {
+  const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(wg_size), lds, stream, p, deg, s, bound);
+  return hipGetLastError();
+}
+
+hipError_t launch_max_greedy(const Params& p, int32_t* out, hipStream_t stream) {
+  hipLaunchKernelGGL(max_greedy_kernel, dim3(1), dim3(256), 0, stream, p, out);
   return hipGetLastError();
 }
 

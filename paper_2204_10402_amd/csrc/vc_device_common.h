@@ -33,6 +33,9 @@ __device__ __forceinline__ uint32_t load_acquire(uint32_t* a) {
 __device__ __forceinline__ void store_release(uint32_t* a, uint32_t v) {
   __hip_atomic_store(a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void store_release(int32_t* a, int32_t v) {
+  __hip_atomic_store(a, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void store_relaxed(int32_t* a, int32_t v) {
   __hip_atomic_store(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -107,10 +110,10 @@ struct Ctrl {
   int32_t status;      // broadcast of a result computed by thread 0
   uint32_t slot;
   uint32_t lap;
-  int32_t best;        // broadcast of the global best size (MVC)
-  int32_t stop;        // broadcast of the found / abort flags
-  int32_t err;         // broadcast: the input graph was rejected
-  int32_t pad;
+  int32_t best;        // broadcast of the current instance's best size (MVC)
+  int32_t stop;        // broadcast: the launch is being stopped
+  int32_t err;         // broadcast: the instance's input graph was rejected
+  int32_t drop;        // broadcast: the current instance is answered or out of budget
   uint64_t red_key[kMaxWaves];
   int32_t red_sum[kMaxWaves];
 };
@@ -165,20 +168,41 @@ __device__ __forceinline__ void backoff(int& spins) {
 }
 
 
+// Is the search being stopped: aborted, or (PVC) every instance answered?
+__device__ __forceinline__ bool search_stopped(const Params& p) {
+  return load_relaxed(ctr_i32(p, kAbort)) != 0 || (p.pvc && load_relaxed(ctr_i32(p, kOpen)) == 0);
+}
+
+// Spin lock taken by one thread for a short critical section with no waits inside (an
+// instance's cover being written); acquire order on success.
+__device__ inline void lock_acquire(int32_t* lock) {
+  int spins = 0;
+  for (;;) {
+    int32_t expected = 0;
+    if (__hip_atomic_compare_exchange_strong(lock, &expected, 1, __ATOMIC_ACQUIRE,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      return;
+    backoff(spins);
+  }
+}
+
 // ---- global worklist -----------------------------------------------------------------------
 // A bounded ring of q_cap node slots (a power of two). Ticket t uses slot t % cap in lap
 // t / cap; seq[slot] = 2*lap means free for lap `lap`, 2*lap + 1 means filled in lap `lap`.
 // `count` is the number of entries producers have reserved and consumers have not: a
 // consumer only takes a ticket after lowering a positive count, so it never waits for a
 // node that will not come. A producer raises the outstanding-work counter before it
-// reserves, so that counter can read zero only when nothing is queued or held.
+// reserves, so that counter can read zero only when nothing is queued, held or unstarted
+// (it starts at the number of instances: one root each).
 
-// Thread 0 tries to reserve a slot for a donated node; returns 1 with c.slot/c.lap set, 0 if
-// the worklist is at its threshold, -1 if the search is being stopped.
-__device__ inline int enqueue_reserve(const Params& p, Ctrl& c) {
+// Thread 0 tries to reserve a slot for a donated node of instance `inst`; returns 1 with
+// c.slot/c.lap set, 0 if the worklist is at its threshold, -1 if the search is being stopped.
+// The instance's and the launch's outstanding-work counters are raised first.
+__device__ inline int enqueue_reserve(const Params& p, Ctrl& c, int inst) {
   int32_t* count = ctr_i32(p, kQCount);
   const int32_t seen = load_relaxed(count);
   if (seen >= static_cast<int32_t>(p.q_threshold)) return 0;
+  fetch_add(&p.ist[inst].work, 1);
   fetch_add(ctr_i32(p, kWork), 1);
   const int32_t before = fetch_add(count, 1);  // stays below cap: threshold + 2 num_wg <= cap
   if (before + 1 > load_relaxed(ctr_i32(p, kQMaxCount))) atomicMax(ctr_i32(p, kQMaxCount), before + 1);
@@ -187,7 +211,7 @@ __device__ inline int enqueue_reserve(const Params& p, Ctrl& c) {
   const uint32_t lap = static_cast<uint32_t>(t / p.q_cap);
   int spins = 0;
   while (load_acquire(p.seq + slot) != 2u * lap) {
-    if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) return -1;
+    if (search_stopped(p)) return -1;
     backoff(spins);
   }
   c.slot = slot;
@@ -197,8 +221,8 @@ __device__ inline int enqueue_reserve(const Params& p, Ctrl& c) {
 
 // Whole workgroup: try to reserve a worklist slot for a donated node. Returns true with
 // c.slot / c.lap set; the caller then writes the node and calls enqueue_publish.
-__device__ inline bool enqueue_begin(const Params& p, Ctrl& c) {
-  if (threadIdx.x == 0) c.status = enqueue_reserve(p, c);
+__device__ inline bool enqueue_begin(const Params& p, Ctrl& c, int inst) {
+  if (threadIdx.x == 0) c.status = enqueue_reserve(p, c, inst);
   __syncthreads();
   return c.status == 1;  // at threshold, or stopping: keep the node locally
 }
@@ -212,19 +236,19 @@ __device__ inline void enqueue_publish(const Params& p, const Ctrl& c) {
   if (threadIdx.x == 0) store_release(p.seq + slot, 2u * lap + 1u);
 }
 
-// Whole workgroup: wait for a worklist entry. Returns 1 with c.slot / c.lap set (the caller
-// reads the node, then calls dequeue_finish), 0 when the whole search is finished, -1 when it
-// is being stopped. An idle workgroup polls the entry count (and, while the list is empty,
-// the outstanding-work counter) with exponential back-off, and looks at the stop flags every
-// fourth poll.
+// Whole workgroup: wait for work. Returns 1 with c.slot / c.lap set for a worklist entry (the
+// caller reads the node, then calls dequeue_finish), 2 with c.slot set to an instance whose
+// search has not started (its root), 0 when the whole launch is finished, -1 when it is being
+// stopped. Queued nodes of started instances go first; roots are taken in instance order. An
+// idle workgroup polls the entry count (and, while the list is empty, the outstanding-work
+// counter) with exponential back-off, and looks at the stop flags every fourth poll.
 __device__ inline int dequeue_begin(const Params& p, Ctrl& c) {
   int polls = 0;
   for (;;) {
     if (threadIdx.x == 0) {
-      int status = 2;  // nothing available yet: retry
+      int status = 3;  // nothing available yet: retry
       int32_t* count = ctr_i32(p, kQCount);
-      if ((polls & 3) == 0 &&
-          (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound)))) {
+      if ((polls & 3) == 0 && search_stopped(p)) {
         status = -1;
       } else if (load_relaxed(count) > 0) {
         if (fetch_add(count, -1) > 0) {
@@ -234,7 +258,7 @@ __device__ inline int dequeue_begin(const Params& p, Ctrl& c) {
           int wait = 0;
           status = 1;
           while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
-            if (load_relaxed(ctr_i32(p, kAbort)) || load_relaxed(ctr_i32(p, kFound))) {
+            if (search_stopped(p)) {
               status = -1;
               break;
             }
@@ -245,10 +269,16 @@ __device__ inline int dequeue_begin(const Params& p, Ctrl& c) {
         } else {
           fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
         }
+      } else if (load_relaxed(ctr_i32(p, kRootNext)) < p.num_inst) {
+        const int32_t r = fetch_add(ctr_i32(p, kRootNext), 1);
+        if (r < p.num_inst) {
+          status = 2;
+          c.slot = static_cast<uint32_t>(r);
+        }
       } else if (load_relaxed(ctr_i32(p, kWork)) == 0) {
-        status = 0;  // nothing queued and nothing held: the search is over
+        status = 0;  // nothing queued, held or unstarted: the launch is over
       }
-      if (status == 2) {
+      if (status == 3) {
         const int units = 1 << (polls < 5 ? polls : 5);
         for (int i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(16);
         ++polls;
@@ -257,9 +287,17 @@ __device__ inline int dequeue_begin(const Params& p, Ctrl& c) {
     }
     __syncthreads();
     const int status = c.status;
-    if (status != 2) return status;
+    if (status != 3) return status;
     __syncthreads();  // every thread has read c.status before thread 0 writes it again
   }
+}
+
+// Thread 0: the workgroup has finished a sub-tree of instance `inst` that it took from the
+// worklist or as a root. The instance's counter is lowered with release order, after
+// everything the workgroup wrote for the instance.
+__device__ inline void release_work(const Params& p, int inst) {
+  __hip_atomic_fetch_add(&p.ist[inst].work, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  fetch_add(ctr_i32(p, kWork), -1);
 }
 
 // Whole workgroup, after every thread has read its part of the node: free the slot.

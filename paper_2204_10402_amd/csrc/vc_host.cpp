@@ -1,7 +1,8 @@
 // vc_host.cpp -- host runtime of libvc.so: contexts, workspace, launch sizing and the C ABI
-// declared in include/vc.h. Every step of the search runs in the HIP kernels of
-// vc_device.hip; this file only checks arguments, sizes and allocates device memory, queues
-// the kernels on the context stream and copies the small result block back.
+// declared in include/vc.h. Every step of the search runs in the HIP kernels of vc_device.hip
+// and vc_bitset.hip; this file only checks arguments, lays out a batch, sizes and allocates
+// device memory, queues the kernels on the context stream and copies the small result blocks
+// back. A single-graph call is a batch of one.
 
 #include <hip/hip_runtime_api.h>
 
@@ -13,6 +14,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "vc.h"
 #include "vc_internal.h"
@@ -24,8 +26,6 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-constexpr int32_t kNoRow = 0x7FFFFFFF;
-
 }  // namespace
 
 struct vc_ctx {
@@ -34,16 +34,23 @@ struct vc_ctx {
   bool own_stream = false;
   hipDeviceProp_t prop{};
   size_t lds_limit_set = 0;
-  DevBuf rp, ci, payload, seq, ctr, stacks, covers, wg_stats, result, cover_tmp, scratch_s, bits;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  DevBuf rp, ci, inst, ist, payload, seq, ctr, stacks, covers, wg_stats, result, scratch, bits;
+  std::vector<hipEvent_t> ev;  // two per launch group
   std::string last_error;
   // occupancy-API answers: (kernel family, pvc, profiled, workgroup size, words, LDS bytes)
   std::map<std::tuple<int, int, int, int, int, size_t>, int> occupancy;
+  // host staging, kept across calls
+  std::vector<vc::Instance> h_inst;
+  std::vector<vc::InstState> h_ist;
+  std::vector<vc::DevResult> h_res;
+  std::vector<uint8_t> h_cover;
 };
 
 namespace {
 
 using vc::DevResult;
+using vc::Instance;
+using vc::InstState;
 using vc::Params;
 
 int fail(vc_ctx* ctx, int code, const std::string& msg) {
@@ -79,6 +86,15 @@ int ensure(vc_ctx* ctx, DevBuf& b, size_t bytes) {
   }
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
   b.bytes = bytes;
+  return VC_OK;
+}
+
+int ensure_events(vc_ctx* ctx, size_t count) {
+  while (ctx->ev.size() < count) {
+    hipEvent_t e = nullptr;
+    VC_HIP(ctx, hipEventCreate(&e));
+    ctx->ev.push_back(e);
+  }
   return VC_OK;
 }
 
@@ -128,31 +144,30 @@ int check_graph_args(vc_ctx* ctx, const vc_graph* g) {
 struct Plan {
   int32_t wg_size = 0;
   int32_t num_wg = 0;
-  int32_t max_wg = 0;  // workgroups the per-workgroup buffers are sized for
   int32_t stride = 0;
-  int32_t cover_stride = 0;
   uint32_t cap = 0;
   uint32_t threshold = 0;
   size_t lds = 0;
-  int32_t words = 0;  // > 0: bitset kernels with this many 64-bit words per node
   int32_t rp_lds = 0;  // degree-array kernels: row_ptr staged in LDS
 };
 
 // Resident workgroups per CU, from the occupancy API, remembered per context.
-int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, int n, int* out) {
+int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, int n_max,
+              int* out) {
   const auto key = std::make_tuple(words ? 1 : 0, pvc ? 1 : 0, prof ? 1 : 0, ws, words, lds);
   const auto it = ctx->occupancy.find(key);
   if (it != ctx->occupancy.end()) {
     *out = it->second;
     return VC_OK;
   }
-  if (words) VC_HIP(ctx, vc::bitset_occupancy(words, pvc, prof, n, out));
+  if (words) VC_HIP(ctx, vc::bitset_occupancy(words, pvc, prof, n_max, out));
   else VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, ws, lds, out));
   ctx->occupancy[key] = *out;
   return VC_OK;
 }
 
-// Bitset kernels up to 256 vertices unless the caller asks for degree arrays.
+// Kernel family of a graph: bitset kernels with ceil(n/64) words up to 256 vertices unless
+// the caller asks for degree arrays (0).
 int choose_words(vc_ctx* ctx, int32_t n, int32_t flags, int32_t* words) {
   const bool force_bits = flags & VC_OPT_BITSETS;
   const bool force_arrays = flags & VC_OPT_DEGREE_ARRAYS;
@@ -162,32 +177,30 @@ int choose_words(vc_ctx* ctx, int32_t n, int32_t flags, int32_t* words) {
   return VC_OK;
 }
 
-// Workgroup size and count (paper §IV-E, adapted): a power-of-two workgroup of about n/4
-// threads; as many workgroups as can be resident at once (all must be, since they wait on
-// each other), fewer if their stacks do not fit in device memory.
-int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl) {
+// Workgroup size and count for one launch (paper §IV-E, adapted): a power-of-two workgroup of
+// about n_max/4 threads; as many workgroups as can be resident at once, fewer if their stacks
+// do not fit in device memory (size_stacks).
+int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int32_t words, const vc_options* o,
+                Plan& pl) {
   const bool prof = o && (o->flags & VC_OPT_PROFILE);
-  int rc = choose_words(ctx, n, o ? o->flags : 0, &pl.words);
-  if (rc) return rc;
-  pl.cover_stride = static_cast<int32_t>(round_up(std::max<int64_t>(n, 1), 256));
   const int cus = ctx->prop.multiProcessorCount;
-  int best_ws = 0, best_occ = 0;
-  if (pl.words) {
-    // one wavefront per workgroup; the adjacency matrix (n * words * 8 bytes) in LDS
-    pl.stride = vc::bitset_stride(pl.words);
-    pl.lds = vc::bitset_lds_bytes(n, pl.words);
+  int best_ws = 0, best_occ = 0, rc;
+  if (words) {
+    // one wavefront per workgroup; the adjacency matrix (n_max * words * 8 bytes) in LDS
+    pl.stride = vc::bitset_stride(words);
+    pl.lds = vc::bitset_lds_bytes(n_max, words);
     best_ws = 64;
     if (o && o->wg_size && o->wg_size != 64)
       return fail(ctx, VC_ERR_INVALID_ARG, "the bitset kernels use 64-thread workgroups");
-    if ((rc = occupancy(ctx, pl.words, pvc, prof, 64, pl.lds, n, &best_occ))) return rc;
+    if ((rc = occupancy(ctx, words, pvc, prof, 64, pl.lds, n_max, &best_occ))) return rc;
   } else {
-    pl.stride = static_cast<int32_t>(round_up(static_cast<int64_t>(n) + 2, 64));
-    pl.lds = vc::node_lds_bytes(pl.stride, n, false);
+    pl.stride = vc::array_stride(n_max);
+    pl.lds = vc::node_lds_bytes(pl.stride, n_max, false);
     const size_t lds_cap = static_cast<size_t>(ctx->prop.maxSharedMemoryPerMultiProcessor);
     if (pl.lds + 1024 > lds_cap)
       return fail(ctx, VC_ERR_INVALID_ARG,
-                  "graph too large for the LDS-resident node (n = " + std::to_string(n) + ")");
-    const size_t lds_rp = vc::node_lds_bytes(pl.stride, n, true);
+                  "graph too large for the LDS-resident node (n = " + std::to_string(n_max) + ")");
+    const size_t lds_rp = vc::node_lds_bytes(pl.stride, n_max, true);
     const size_t lds_max = lds_rp + 1024 <= lds_cap ? lds_rp : pl.lds;
     if (lds_max > 65536 && ctx->lds_limit_set < lds_max) {
       VC_HIP(ctx, vc::set_lds_limit(lds_max));
@@ -201,14 +214,14 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl)
       // time per node falls with more wavefronts per node: take about n/4 threads (four
       // vertices per thread per pass), as a power of two in [64, 1024].
       int ws = 64;
-      while (ws < 1024 && ws * 2 <= std::max(n, 1) / 4) ws *= 2;
+      while (ws < 1024 && ws * 2 <= std::max(n_max, 1) / 4) ws *= 2;
       best_ws = ws;
     }
-    if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, pl.lds, n, &best_occ))) return rc;
+    if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, pl.lds, n_max, &best_occ))) return rc;
     // Keep row_ptr in LDS too when that costs no resident workgroup.
     if (lds_rp + 1024 <= lds_cap) {
       int occ_rp = 0;
-      if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_rp, n, &occ_rp))) return rc;
+      if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_rp, n_max, &occ_rp))) return rc;
       if (occ_rp == best_occ) {
         pl.rp_lds = 1;
         pl.lds = lds_rp;
@@ -221,9 +234,8 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n, const vc_options* o, Plan& pl)
   pl.num_wg = best_occ * cus;
   // Bitset nodes take a few microseconds each, so more than eight workgroups per CU only add
   // contention on the worklist counters (measured on the hard MVC instances).
-  if (pl.words && !(o && o->num_wg > 0)) pl.num_wg = std::min(pl.num_wg, 8 * cus);
+  if (words && !(o && o->num_wg > 0)) pl.num_wg = std::min(pl.num_wg, 8 * cus);
   if (o && o->num_wg > 0) pl.num_wg = std::min(pl.num_wg, o->num_wg);
-  pl.max_wg = pl.num_wg;
 
   // Worklist: capacity and donation threshold (§IV-A). A producer only reserves a slot after
   // reading fewer than `threshold` reserved entries; at most num_wg producers can be past that
@@ -262,173 +274,359 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
-// The whole search on a graph whose CSR already sits in device memory.
-int run_search(vc_ctx* ctx, const vc_graph* g, bool pvc, int64_t k, const vc_options* o,
-               int32_t* size_out, int32_t* yes_out, uint8_t* cover_dev, uint8_t* cover_host,
-               vc_stats* stats, std::chrono::steady_clock::time_point t0) {
-  const int32_t n = g->n;
+// A batch whose packed CSR is already in device memory.
+struct BatchIn {
+  int32_t count = 0;
+  const int32_t* n = nullptr;    // host
+  const int32_t* nnz = nullptr;  // host
+  const int32_t* k = nullptr;    // host, PVC
+  const int32_t* rp = nullptr;   // device, packed
+  const int32_t* ci = nullptr;   // device, packed
+};
+
+// Per-instance results in the caller's order (host arrays; any may be null).
+struct BatchOut {
+  int32_t* status = nullptr;
+  int32_t* size = nullptr;
+  int32_t* yes = nullptr;
+  int64_t* nodes = nullptr;
+  uint8_t* cover_host = nullptr;  // sum of n bytes
+  uint8_t* cover_dev = nullptr;   // sum of n bytes (device)
+  vc_stats* stats = nullptr;
+  bool single = false;            // a batch of one: its status is the call's status
+};
+
+// Instances of one launch: a contiguous slice [begin, end) of the sorted instance table.
+struct Group {
+  int32_t words = 0;
+  int32_t begin = 0, end = 0;
+  int32_t n_max = 0;
+  int32_t k_max = 0;
+  int64_t vertices = 0, entries = 0;
   Plan pl;
-  int rc = plan_launch(ctx, pvc, n, o, pl);
+  int32_t depth_cap = 0;
+};
+
+// Check the host side of a batch: sizes, and that the packed offsets fit their types.
+int check_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, int64_t* total_rp, int64_t* total_n,
+                int64_t* total_nnz) {
+  if (b.count < 0) return fail(ctx, VC_ERR_INVALID_ARG, "negative batch count");
+  if (b.count > 0 && (!b.n || !b.nnz)) return fail(ctx, VC_ERR_INVALID_ARG, "n or nnz is NULL");
+  if (pvc && b.count > 0 && !b.k) return fail(ctx, VC_ERR_INVALID_ARG, "k is NULL");
+  int64_t rp = 0, nv = 0, ne = 0;
+  for (int32_t i = 0; i < b.count; ++i) {
+    if (b.n[i] < 0 || b.nnz[i] < 0)
+      return fail(ctx, VC_ERR_INVALID_ARG, "negative n or nnz (instance " + std::to_string(i) + ")");
+    if (pvc && b.k[i] < 0)
+      return fail(ctx, VC_ERR_INVALID_ARG, "k must be >= 0 (instance " + std::to_string(i) + ")");
+    rp += static_cast<int64_t>(b.n[i]) + 1;
+    nv += b.n[i];
+    ne += b.nnz[i];
+  }
+  if (rp > 0x7FFFFFFF || nv > 0x7FFFFFFF)
+    return fail(ctx, VC_ERR_INVALID_ARG, "batch has more than 2^31 row pointers");
+  if (b.count > 0 && !b.rp) return fail(ctx, VC_ERR_INVALID_ARG, "row_ptr is NULL");
+  if (ne > 0 && !b.ci) return fail(ctx, VC_ERR_INVALID_ARG, "col_idx is NULL");
+  *total_rp = rp;
+  *total_n = nv;
+  *total_nnz = ne;
+  return VC_OK;
+}
+
+std::string bad_row_message(int32_t row) {
+  return "CSR row " + std::to_string(row) +
+         " breaks the format (bounds, order, self-loop, duplicate or symmetry)";
+}
+
+// The whole search for every instance of a batch.
+int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, BatchOut& out,
+              std::chrono::steady_clock::time_point t0) {
+  int64_t total_rp = 0, total_n = 0, total_nnz = 0;
+  int rc = check_batch(ctx, b, pvc, &total_rp, &total_n, &total_nnz);
   if (rc) return rc;
-  const size_t stride_b = static_cast<size_t>(pl.stride) * sizeof(int32_t);
-  if ((rc = ensure(ctx, ctx->payload, static_cast<size_t>(pl.cap) * stride_b))) return rc;
-  if ((rc = ensure(ctx, ctx->seq, static_cast<size_t>(pl.cap) * sizeof(uint32_t)))) return rc;
-  if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
-  if ((rc = ensure(ctx, ctx->covers, static_cast<size_t>(pl.max_wg + 1) * pl.cover_stride))) return rc;
-  if ((rc = ensure(ctx, ctx->wg_stats, static_cast<size_t>(pl.max_wg) * sizeof(vc::WgStats)))) return rc;
-  if ((rc = ensure(ctx, ctx->result, sizeof(DevResult)))) return rc;
-  if ((rc = ensure(ctx, ctx->cover_tmp, static_cast<size_t>(std::max(n, 1))))) return rc;
+  const int32_t flags = o ? o->flags : 0;
+  const bool prof = flags & VC_OPT_PROFILE;
 
-  Params p{};
-  p.n = n;
-  p.stride = pl.stride;
-  p.nnz = g->nnz;
-  p.rules = rules_from_flags(o ? o->flags : 0);
-  p.rp = g->row_ptr;
-  p.ci = g->col_idx;
-  p.payload = static_cast<int32_t*>(ctx->payload.ptr);
-  p.seq = static_cast<uint32_t*>(ctx->seq.ptr);
-  p.ctr = static_cast<int32_t*>(ctx->ctr.ptr);
-  p.covers = static_cast<uint8_t*>(ctx->covers.ptr);
-  p.wg_stats = static_cast<vc::WgStats*>(ctx->wg_stats.ptr);
-  p.k = k;
-  p.node_budget = o ? o->node_budget : 0;
-  // report often enough that the whole grid overshoots the budget by at most about half
-  p.budget_chunk = std::max<int64_t>(1, std::min<int64_t>(1024, p.node_budget / (2 * pl.num_wg)));
-  p.q_cap = pl.cap;
-  p.q_threshold = pl.threshold;
-  p.num_wg = pl.num_wg;
-  p.greedy_slot = pl.max_wg;
-  p.cover_stride = pl.cover_stride;
-  p.words = pl.words;
-  p.rp_lds = pl.rp_lds;
-  if (pl.words) {
-    if ((rc = ensure(ctx, ctx->bits, static_cast<size_t>(n) * pl.words * sizeof(uint64_t)))) return rc;
-    p.bits = static_cast<uint64_t*>(ctx->bits.ptr);
-  }
-  DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
-  hipStream_t s = ctx->stream;
-
-  VC_HIP(ctx, vc::launch_init(p, dres, s));
-  VC_HIP(ctx, vc::launch_prepare(p, s));
-  if (pl.words) VC_HIP(ctx, vc::launch_bitset_pack(p, s));
-
-  DevResult res{};
-  int32_t depth_cap;
-  float greedy_ms = 0.f;
-  if (!pvc) {
-    const int gws = static_cast<int>(std::min<int64_t>(1024, round_up(std::max(n, 1), 64)));
-    VC_HIP(ctx, hipEventRecord(ctx->ev[2], s));
-    if (pl.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, dres, s));
-    else VC_HIP(ctx, vc::launch_greedy(p, gws, dres, s));
-    VC_HIP(ctx, hipEventRecord(ctx->ev[3], s));
-    VC_HIP(ctx, hipMemcpyAsync(&res, dres, sizeof res, hipMemcpyDeviceToHost, s));
-    VC_HIP(ctx, hipStreamSynchronize(s));
-    VC_HIP(ctx, hipEventElapsedTime(&greedy_ms, ctx->ev[2], ctx->ev[3]));
-    if (res.err_row != kNoRow)
-      return fail(ctx, VC_ERR_INVALID_GRAPH,
-                  "CSR row " + std::to_string(res.err_row) +
-                      " breaks the format (bounds, order, self-loop, duplicate or symmetry)");
-    if (res.edges0 == 0) {  // edgeless: the empty set is the minimum cover
-      if (cover_dev) VC_HIP(ctx, hipMemsetAsync(cover_dev, 0, static_cast<size_t>(n), s));
-      VC_HIP(ctx, hipStreamSynchronize(s));
-      if (cover_host) std::memset(cover_host, 0, static_cast<size_t>(n));
-      *size_out = 0;
-      if (stats) {
-        std::memset(stats, 0, sizeof *stats);
-        stats->greedy_size = 0;
-        stats->n = n;
-        stats->greedy_ms = greedy_ms;
-        stats->total_ms = ms_since(t0);
+  // instance table, sorted by kernel family; graphs without vertices are answered here
+  std::vector<int32_t> words(b.count, 0), order;
+  order.reserve(b.count);
+  for (int32_t i = 0; i < b.count; ++i) {
+    if (b.n[i] == 0) {
+      if (b.nnz[i] != 0) {
+        if (out.single) return fail(ctx, VC_ERR_INVALID_GRAPH, "n = 0 but nnz > 0");
       }
-      return VC_OK;
+      continue;
     }
-    // bound = best - 1: a path branches at most best - 1 times (each branching adds to s)
-    depth_cap = std::max(res.greedy, 1);
-  } else {
-    depth_cap = static_cast<int32_t>(std::min<int64_t>(k, n)) + 1;
+    if ((rc = choose_words(ctx, b.n[i], flags, &words[i]))) return rc;
+    order.push_back(i);
   }
-  if ((rc = size_stacks(ctx, pl, depth_cap))) return rc;
-  p.stacks = static_cast<int32_t*>(ctx->stacks.ptr);
-  p.depth_cap = depth_cap;
-  p.num_wg = pl.num_wg;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    const int32_t kx = words[x] ? words[x] : 99, ky = words[y] ? words[y] : 99;
+    return kx < ky;
+  });
+  std::vector<int64_t> rp_off(b.count), ci_off(b.count), vtx_off(b.count);
+  {
+    int64_t r = 0, c = 0, v = 0;
+    for (int32_t i = 0; i < b.count; ++i) {
+      rp_off[i] = r;
+      ci_off[i] = c;
+      vtx_off[i] = v;
+      r += static_cast<int64_t>(b.n[i]) + 1;
+      c += b.nnz[i];
+      v += b.n[i];
+    }
+  }
+  const int32_t m = static_cast<int32_t>(order.size());
+  ctx->h_inst.assign(m, Instance{});
+  std::vector<Group> groups;
+  for (int32_t s = 0; s < m; ++s) {
+    const int32_t i = order[s];
+    if (groups.empty() || groups.back().words != words[i]) {
+      Group g;
+      g.words = words[i];
+      g.begin = s;
+      groups.push_back(g);
+    }
+    Group& g = groups.back();
+    Instance& in = ctx->h_inst[s];
+    in.n = b.n[i];
+    in.nnz = b.nnz[i];
+    in.rp_off = static_cast<int32_t>(rp_off[i]);
+    in.vtx_off = static_cast<int32_t>(vtx_off[i]);
+    in.ci_off = ci_off[i];
+    in.ent_first = g.entries;
+    in.vtx_first = static_cast<int32_t>(g.vertices);
+    in.k = pvc ? b.k[i] : 0;
+    g.end = s + 1;
+    g.n_max = std::max(g.n_max, in.n);
+    g.k_max = std::max(g.k_max, std::min(in.k, in.n));
+    g.vertices += in.n;
+    g.entries += in.nnz;
+  }
+  const int32_t ng = static_cast<int32_t>(groups.size());
+  hipStream_t st = ctx->stream;
 
-  VC_HIP(ctx, hipEventRecord(ctx->ev[0], s));
-  const bool prof = o && (o->flags & VC_OPT_PROFILE);
-  if (pl.words) VC_HIP(ctx, vc::launch_bitset_traverse(pvc, prof, p, s));
-  else VC_HIP(ctx, vc::launch_traverse(pvc, prof, p, pl.wg_size, s));
-  VC_HIP(ctx, hipEventRecord(ctx->ev[1], s));
-  uint8_t* cover_dst = cover_dev ? cover_dev : static_cast<uint8_t*>(ctx->cover_tmp.ptr);
-  VC_HIP(ctx, vc::launch_finalize(pvc, p, cover_dst, dres, s));
-  VC_HIP(ctx, hipMemcpyAsync(&res, dres, sizeof res, hipMemcpyDeviceToHost, s));
-  if (cover_host && n > 0)
-    VC_HIP(ctx, hipMemcpyAsync(cover_host, cover_dst, static_cast<size_t>(n),
-                               hipMemcpyDeviceToHost, s));
-  VC_HIP(ctx, hipStreamSynchronize(s));
-  float kernel_ms = 0.f;
-  VC_HIP(ctx, hipEventElapsedTime(&kernel_ms, ctx->ev[0], ctx->ev[1]));
+  if (m > 0) {
+    if ((rc = ensure(ctx, ctx->inst, static_cast<size_t>(m) * sizeof(Instance)))) return rc;
+    if ((rc = ensure(ctx, ctx->ist, static_cast<size_t>(m) * sizeof(InstState)))) return rc;
+    if ((rc = ensure(ctx, ctx->result, static_cast<size_t>(ng) * sizeof(DevResult)))) return rc;
+    if ((rc = ensure(ctx, ctx->scratch, static_cast<size_t>(ng) * sizeof(int32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
+    if ((rc = ensure_events(ctx, 2 * static_cast<size_t>(ng) + 2))) return rc;
+    VC_HIP(ctx, hipMemcpyAsync(ctx->inst.ptr, ctx->h_inst.data(), static_cast<size_t>(m) * sizeof(Instance),
+                               hipMemcpyHostToDevice, st));
+  }
+  uint8_t* covers = out.cover_dev;
+  if (!covers && total_n > 0) {
+    if ((rc = ensure(ctx, ctx->covers, static_cast<size_t>(total_n)))) return rc;
+    covers = static_cast<uint8_t*>(ctx->covers.ptr);
+  }
 
-  if (res.err_row != kNoRow)
-    return fail(ctx, VC_ERR_INVALID_GRAPH,
-                "CSR row " + std::to_string(res.err_row) +
-                    " breaks the format (bounds, order, self-loop, duplicate or symmetry)");
-  if (res.error)
-    return fail(ctx, VC_ERR_INTERNAL, "device invariant failed (code " +
-                                          std::to_string(res.error) + ": stack overflow)");
-  if (res.aborted) return fail(ctx, VC_ERR_BUDGET, "node budget exhausted");
-  if (pvc && res.yes) res.size = res.cover_count;  // PVC reports the size of the cover found
-  if (res.yes) {
-    if (res.uncovered != 0 || res.cover_count != res.size)
+  // one launch per kernel family, in turn on the context stream
+  const Instance* d_inst = static_cast<const Instance*>(ctx->inst.ptr);
+  InstState* d_ist = static_cast<InstState*>(ctx->ist.ptr);
+  DevResult* d_res = static_cast<DevResult*>(ctx->result.ptr);
+  int32_t* d_greedy = static_cast<int32_t*>(ctx->scratch.ptr);
+  std::vector<Params> params(ng);
+  float greedy_ms = 0.f;
+  for (int32_t gi = 0; gi < ng; ++gi) {
+    Group& g = groups[gi];
+    if ((rc = plan_launch(ctx, pvc, g.n_max, g.words, o, g.pl))) return rc;
+    Plan& pl = g.pl;
+    const size_t stride_b = static_cast<size_t>(pl.stride) * sizeof(int32_t);
+    if ((rc = ensure(ctx, ctx->payload, static_cast<size_t>(pl.cap) * stride_b))) return rc;
+    if ((rc = ensure(ctx, ctx->seq, static_cast<size_t>(pl.cap) * sizeof(uint32_t)))) return rc;
+    if ((rc = ensure(ctx, ctx->wg_stats, static_cast<size_t>(pl.num_wg) * sizeof(vc::WgStats)))) return rc;
+    if (g.words &&
+        (rc = ensure(ctx, ctx->bits, static_cast<size_t>(g.vertices) * g.words * sizeof(uint64_t))))
+      return rc;
+    Params& p = params[gi];
+    p = Params{};
+    p.num_inst = g.end - g.begin;
+    p.stride = pl.stride;
+    p.n_max = g.n_max;
+    p.rules = rules_from_flags(flags);
+    p.inst = d_inst + g.begin;
+    p.ist = d_ist + g.begin;
+    p.rp_all = b.rp;
+    p.ci_all = b.ci;
+    p.payload = static_cast<int32_t*>(ctx->payload.ptr);
+    p.seq = static_cast<uint32_t*>(ctx->seq.ptr);
+    p.ctr = static_cast<int32_t*>(ctx->ctr.ptr);
+    p.covers = covers;
+    p.wg_stats = static_cast<vc::WgStats*>(ctx->wg_stats.ptr);
+    p.node_budget = o ? o->node_budget : 0;
+    // report often enough that the whole grid overshoots a budget by at most about half
+    p.budget_chunk = std::max<int64_t>(1, std::min<int64_t>(1024, p.node_budget / (2 * pl.num_wg)));
+    p.q_cap = pl.cap;
+    p.q_threshold = pl.threshold;
+    p.num_wg = pl.num_wg;
+    p.bits = g.words ? static_cast<uint64_t*>(ctx->bits.ptr) : nullptr;
+    p.words = g.words;
+    p.rp_lds = pl.rp_lds;
+    p.pvc = pvc ? 1 : 0;
+    DevResult* dres = d_res + gi;
+
+    VC_HIP(ctx, vc::launch_init(p, dres, st));
+    VC_HIP(ctx, vc::launch_prepare(p, g.vertices, g.entries, st));
+    if (!pvc) {
+      const int gws = g.words ? 64 : static_cast<int>(std::min<int64_t>(1024, round_up(g.n_max, 64)));
+      hipEvent_t e0 = ctx->ev[2 * ng], e1 = ctx->ev[2 * ng + 1];
+      VC_HIP(ctx, hipEventRecord(e0, st));
+      if (g.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, st));
+      else VC_HIP(ctx, vc::launch_greedy(p, gws, st));
+      VC_HIP(ctx, hipEventRecord(e1, st));
+      VC_HIP(ctx, vc::launch_max_greedy(p, d_greedy + gi, st));
+      int32_t gmax = 0;
+      VC_HIP(ctx, hipMemcpyAsync(&gmax, d_greedy + gi, sizeof gmax, hipMemcpyDeviceToHost, st));
+      VC_HIP(ctx, hipStreamSynchronize(st));
+      float ms = 0.f;
+      VC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+      greedy_ms += ms;
+      // bound = best - 1: a path branches at most best - 1 times (each branching adds to s)
+      g.depth_cap = std::max(gmax, 1);
+    } else {
+      g.depth_cap = g.k_max + 1;
+    }
+    if ((rc = size_stacks(ctx, pl, g.depth_cap))) return rc;
+    p.stacks = static_cast<int32_t*>(ctx->stacks.ptr);
+    p.depth_cap = g.depth_cap;
+    p.num_wg = pl.num_wg;
+    VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi], st));
+    if (g.words) VC_HIP(ctx, vc::launch_bitset_traverse(pvc, prof, p, st));
+    else VC_HIP(ctx, vc::launch_traverse(pvc, prof, p, pl.wg_size, st));
+    VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi + 1], st));
+    VC_HIP(ctx, vc::launch_finalize(p, g.vertices, g.entries, dres, st));
+  }
+
+  ctx->h_ist.resize(m);
+  ctx->h_res.resize(ng);
+  if (m > 0) {
+    VC_HIP(ctx, hipMemcpyAsync(ctx->h_ist.data(), d_ist, static_cast<size_t>(m) * sizeof(InstState),
+                               hipMemcpyDeviceToHost, st));
+    VC_HIP(ctx, hipMemcpyAsync(ctx->h_res.data(), d_res, static_cast<size_t>(ng) * sizeof(DevResult),
+                               hipMemcpyDeviceToHost, st));
+  }
+  if (out.cover_host && total_n > 0) {
+    ctx->h_cover.resize(static_cast<size_t>(total_n));
+    VC_HIP(ctx, hipMemcpyAsync(ctx->h_cover.data(), covers, static_cast<size_t>(total_n),
+                               hipMemcpyDeviceToHost, st));
+  }
+  VC_HIP(ctx, hipStreamSynchronize(st));
+  double kernel_ms = 0.0;
+  for (int32_t gi = 0; gi < ng; ++gi) {
+    float ms = 0.f;
+    VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * gi], ctx->ev[2 * gi + 1]));
+    kernel_ms += ms;
+  }
+
+  // launch-wide failures end the whole call
+  for (const DevResult& r : ctx->h_res) {
+    if (r.error)
       return fail(ctx, VC_ERR_INTERNAL,
-                  "returned cover failed verification: " + std::to_string(res.uncovered) +
-                      " uncovered edge entries, " + std::to_string(res.cover_count) +
-                      " vertices for size " + std::to_string(res.size));
-    if (pvc && res.size > k)
-      return fail(ctx, VC_ERR_INTERNAL, "PVC cover larger than k");
+                  "device invariant failed (code " + std::to_string(r.error) +
+                      (r.error == 1 ? ": stack overflow)" : ": node of an unknown instance)"));
+    if (r.aborted) return fail(ctx, VC_ERR_INTERNAL, "search aborted on the device");
   }
-  *size_out = res.size;
-  if (yes_out) *yes_out = res.yes;
-  if (stats) {
-    std::memset(stats, 0, sizeof *stats);
-    stats->nodes = res.nodes;
-    stats->wg_nodes_max = res.wg_nodes_max;
-    stats->wg_nodes_min = res.wg_nodes_min;
-    stats->stack_pushes = res.pushes;
-    stats->stack_pops = res.pops;
-    stats->wl_enqueues = res.enqueues;
-    stats->wl_dequeues = res.dequeues;
-    stats->max_stack_depth = res.max_depth;
-    stats->greedy_size = pvc ? -1 : res.greedy;
-    stats->wg_size = pl.wg_size;
-    stats->num_wg = pl.num_wg;
-    stats->wl_capacity = static_cast<int32_t>(pl.cap);
-    stats->wl_threshold = static_cast<int32_t>(pl.threshold);
-    stats->depth_cap = depth_cap;
-    stats->n = n;
-    stats->bitset_words = pl.words;
-    stats->node_bytes = pl.words ? 8 * pl.words + 8 : 4 * (n + 2);
-    stats->kernel_ms = kernel_ms;
-    for (int a = 0; a < vc::kNumActivities; ++a) stats->cycles[a] = res.cycles[a];
-    stats->greedy_ms = greedy_ms;
-    stats->total_ms = ms_since(t0);
+  // per-instance answers, checked against the verification done by finalize_kernel
+  std::vector<int32_t> status(b.count, VC_OK), size(b.count, 0), yes(b.count, 1);
+  std::vector<int64_t> nodes(b.count, 0);
+  int32_t first_bad = -1;
+  std::string bad_msg;
+  for (int32_t s = 0; s < m; ++s) {
+    const int32_t i = order[s];
+    const InstState& is = ctx->h_ist[s];
+    nodes[i] = is.nodes;
+    if (is.err_row != vc::kNoRow) {
+      status[i] = VC_ERR_INVALID_GRAPH;
+      size[i] = -1;
+      yes[i] = 0;
+      if (first_bad < 0) first_bad = i, bad_msg = bad_row_message(is.err_row);
+      continue;
+    }
+    if (is.aborted) {
+      status[i] = VC_ERR_BUDGET;
+      size[i] = -1;
+      yes[i] = 0;
+      if (first_bad < 0) first_bad = i, bad_msg = "node budget exhausted";
+      continue;
+    }
+    const bool answered = !pvc || is.found;
+    yes[i] = answered ? 1 : 0;
+    size[i] = answered ? is.best : -1;
+    const bool ok = !answered ? (is.cover_count == 0)
+                              : (is.uncovered == 0 && is.cover_count == is.best &&
+                                 (!pvc || is.best <= b.k[i]));
+    if (!ok)
+      return fail(ctx, VC_ERR_INTERNAL,
+                  "recorded cover of instance " + std::to_string(i) + " failed verification: " +
+                      std::to_string(is.uncovered) + " uncovered edge entries, " +
+                      std::to_string(is.cover_count) + " vertices for size " +
+                      std::to_string(is.best));
+  }
+  for (int32_t i = 0; i < b.count; ++i)
+    if (b.n[i] == 0 && b.nnz[i] != 0) {
+      status[i] = VC_ERR_INVALID_GRAPH;
+      size[i] = -1;
+      yes[i] = 0;
+    }
+  if (out.single && status[0] != VC_OK) return fail(ctx, status[0], bad_msg);
+
+  for (int32_t i = 0; i < b.count; ++i) {
+    if (out.status) out.status[i] = status[i];
+    if (out.size) out.size[i] = size[i];
+    if (out.yes) out.yes[i] = yes[i];
+    if (out.nodes) out.nodes[i] = nodes[i];
+  }
+  if (out.cover_host && total_n > 0)
+    std::memcpy(out.cover_host, ctx->h_cover.data(), static_cast<size_t>(total_n));
+  if (out.stats) {
+    vc_stats* sp = out.stats;
+    std::memset(sp, 0, sizeof *sp);
+    sp->wg_nodes_min = ng ? INT64_MAX : 0;
+    for (int32_t gi = 0; gi < ng; ++gi) {
+      const DevResult& r = ctx->h_res[gi];
+      const Group& g = groups[gi];
+      sp->nodes += r.nodes;
+      sp->wg_nodes_max = std::max(sp->wg_nodes_max, r.wg_nodes_max);
+      sp->wg_nodes_min = std::min(sp->wg_nodes_min, r.wg_nodes_min);
+      sp->stack_pushes += r.pushes;
+      sp->stack_pops += r.pops;
+      sp->wl_enqueues += r.enqueues;
+      sp->wl_dequeues += r.dequeues;
+      sp->max_stack_depth = std::max(sp->max_stack_depth, r.max_depth);
+      sp->wg_size = std::max(sp->wg_size, g.pl.wg_size);
+      sp->num_wg = std::max(sp->num_wg, g.pl.num_wg);
+      sp->wl_capacity = std::max(sp->wl_capacity, static_cast<int32_t>(g.pl.cap));
+      sp->wl_threshold = std::max(sp->wl_threshold, static_cast<int32_t>(g.pl.threshold));
+      sp->depth_cap = std::max(sp->depth_cap, g.depth_cap);
+      sp->n = std::max(sp->n, g.n_max);
+      sp->bitset_words = std::max(sp->bitset_words, g.words);
+      sp->node_bytes = std::max(sp->node_bytes, g.words ? 8 * g.words + 12 : 4 * (g.n_max + 3));
+      for (int a = 0; a < vc::kNumActivities; ++a) sp->cycles[a] += r.cycles[a];
+    }
+    sp->greedy_size = (!pvc && out.single && m == 1) ? ctx->h_ist[0].greedy : -1;
+    sp->kernel_ms = kernel_ms;
+    sp->greedy_ms = greedy_ms;
+    sp->total_ms = ms_since(t0);
   }
   return VC_OK;
 }
 
-// Copy a host CSR into the context's device buffers.
-int upload(vc_ctx* ctx, const vc_graph* g, vc_graph* dev) {
+// Copy a host CSR (one graph, or a packed batch) into the context's device buffers.
+int upload(vc_ctx* ctx, const int32_t* rp, int64_t rp_count, const int32_t* ci, int64_t ci_count,
+           const int32_t** rp_dev, const int32_t** ci_dev) {
   int rc;
-  if ((rc = ensure(ctx, ctx->rp, (static_cast<size_t>(g->n) + 1) * sizeof(int32_t)))) return rc;
-  if ((rc = ensure(ctx, ctx->ci, static_cast<size_t>(std::max(g->nnz, 1)) * sizeof(int32_t)))) return rc;
-  VC_HIP(ctx, hipMemcpyAsync(ctx->rp.ptr, g->row_ptr, (static_cast<size_t>(g->n) + 1) * sizeof(int32_t),
-                             hipMemcpyHostToDevice, ctx->stream));
-  if (g->nnz > 0)
-    VC_HIP(ctx, hipMemcpyAsync(ctx->ci.ptr, g->col_idx, static_cast<size_t>(g->nnz) * sizeof(int32_t),
+  if ((rc = ensure(ctx, ctx->rp, static_cast<size_t>(std::max<int64_t>(rp_count, 1)) * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(ctx, ctx->ci, static_cast<size_t>(std::max<int64_t>(ci_count, 1)) * sizeof(int32_t)))) return rc;
+  if (rp_count > 0)
+    VC_HIP(ctx, hipMemcpyAsync(ctx->rp.ptr, rp, static_cast<size_t>(rp_count) * sizeof(int32_t),
                                hipMemcpyHostToDevice, ctx->stream));
-  dev->n = g->n;
-  dev->nnz = g->nnz;
-  dev->row_ptr = static_cast<const int32_t*>(ctx->rp.ptr);
-  dev->col_idx = static_cast<const int32_t*>(ctx->ci.ptr);
+  if (ci_count > 0)
+    VC_HIP(ctx, hipMemcpyAsync(ctx->ci.ptr, ci, static_cast<size_t>(ci_count) * sizeof(int32_t),
+                               hipMemcpyHostToDevice, ctx->stream));
+  *rp_dev = static_cast<const int32_t*>(ctx->rp.ptr);
+  *ci_dev = static_cast<const int32_t*>(ctx->ci.ptr);
   return VC_OK;
 }
 
@@ -439,7 +637,8 @@ int enter(vc_ctx* ctx) {
   return VC_OK;
 }
 
-int solve(vc_ctx* ctx, const vc_graph* g, bool device_graph, bool pvc, int64_t k,
+// One graph: a batch of one.
+int solve(vc_ctx* ctx, const vc_graph* g, bool device_graph, bool pvc, int32_t k,
           const vc_options* o, int32_t* yes_out, int32_t* size_out, uint8_t* cover_dev,
           uint8_t* cover_host, vc_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -455,46 +654,116 @@ int solve(vc_ctx* ctx, const vc_graph* g, bool device_graph, bool pvc, int64_t k
     if (stats) std::memset(stats, 0, sizeof *stats), stats->total_ms = ms_since(t0);
     return VC_OK;
   }
-  vc_graph dev = *g;
-  if (!device_graph && (rc = upload(ctx, g, &dev))) return rc;
-  return run_search(ctx, &dev, pvc, k, o, size_out, yes_out, cover_dev, cover_host, stats, t0);
+  BatchIn b;
+  b.count = 1;
+  b.n = &g->n;
+  b.nnz = &g->nnz;
+  b.k = &k;
+  if (device_graph) {
+    b.rp = g->row_ptr;
+    b.ci = g->col_idx;
+  } else if ((rc = upload(ctx, g->row_ptr, static_cast<int64_t>(g->n) + 1, g->col_idx, g->nnz,
+                          &b.rp, &b.ci))) {
+    return rc;
+  }
+  BatchOut out;
+  int32_t status = 0, size = 0, yes = 0;
+  out.status = &status;
+  out.size = &size;
+  out.yes = &yes;
+  out.cover_host = cover_host;
+  out.cover_dev = cover_dev;
+  out.stats = stats;
+  out.single = true;
+  if ((rc = run_batch(ctx, b, pvc, o, out, t0))) return rc;
+  *size_out = size;
+  if (yes_out) *yes_out = yes;
+  return VC_OK;
 }
 
-// Validate a device CSR and stage its root node for a one-workgroup kernel (greedy, reduce).
-int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, Params& p) {
+int solve_batch(vc_ctx* ctx, const vc_batch* batch, bool device_graph, bool pvc,
+                const int32_t* k, const vc_options* o, int32_t* status_out, int32_t* yes_out,
+                int32_t* size_out, uint8_t* cover_dev, uint8_t* cover_host, int64_t* nodes_out,
+                vc_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if (!batch) return fail(ctx, VC_ERR_INVALID_ARG, "batch is NULL");
+  if (!status_out || !size_out || (pvc && !yes_out))
+    return fail(ctx, VC_ERR_INVALID_ARG, "output pointer is NULL");
+  if ((rc = check_options(ctx, o))) return rc;
+  BatchIn b;
+  b.count = batch->count;
+  b.n = batch->n;
+  b.nnz = batch->nnz;
+  b.k = k;
+  int64_t total_rp = 0, total_n = 0, total_nnz = 0;
+  if ((rc = check_batch(ctx, BatchIn{b.count, b.n, b.nnz, k, batch->row_ptr, batch->col_idx},
+                        pvc, &total_rp, &total_n, &total_nnz)))
+    return rc;
+  if (device_graph) {
+    b.rp = batch->row_ptr;
+    b.ci = batch->col_idx;
+  } else if ((rc = upload(ctx, batch->row_ptr, total_rp, batch->col_idx, total_nnz, &b.rp, &b.ci))) {
+    return rc;
+  }
+  BatchOut out;
+  out.status = status_out;
+  out.size = size_out;
+  out.yes = yes_out;
+  out.nodes = nodes_out;
+  out.cover_host = cover_host;
+  out.cover_dev = cover_dev;
+  out.stats = stats;
+  return run_batch(ctx, b, pvc, o, out, t0);
+}
+
+// Validate a device CSR (a batch of one) for a one-workgroup kernel (greedy, reduce).
+int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8_t* covers,
+                 Params& p, int32_t* wg_size) {
+  int32_t words = 0;
+  int rc = choose_words(ctx, g->n, flags, &words);
+  if (rc) return rc;
   Plan pl;
   vc_options o{};
-  o.flags = flags & (VC_OPT_DEGREE_ARRAYS | VC_OPT_BITSETS);
-  int rc = plan_launch(ctx, false, g->n, &o, pl);
-  if (rc) return rc;
-  if ((rc = ensure(ctx, ctx->payload, static_cast<size_t>(pl.stride) * sizeof(int32_t)))) return rc;
-  if ((rc = ensure(ctx, ctx->seq, sizeof(uint32_t)))) return rc;
-  if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
-  if ((rc = ensure(ctx, ctx->covers, static_cast<size_t>(pl.cover_stride)))) return rc;
+  if ((rc = plan_launch(ctx, false, g->n, words, &o, pl))) return rc;
+  if ((rc = ensure(ctx, ctx->inst, sizeof(Instance)))) return rc;
+  if ((rc = ensure(ctx, ctx->ist, sizeof(InstState)))) return rc;
   if ((rc = ensure(ctx, ctx->result, sizeof(DevResult)))) return rc;
+  if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(ctx, ctx->seq, sizeof(uint32_t)))) return rc;
+  if (!covers) {
+    if ((rc = ensure(ctx, ctx->covers, static_cast<size_t>(g->n)))) return rc;
+    covers = static_cast<uint8_t*>(ctx->covers.ptr);
+  }
+  if (words && (rc = ensure(ctx, ctx->bits, static_cast<size_t>(g->n) * words * sizeof(uint64_t))))
+    return rc;
+  ctx->h_inst.assign(1, Instance{});
+  Instance& in = ctx->h_inst[0];
+  in.n = g->n;
+  in.nnz = g->nnz;
+  VC_HIP(ctx, hipMemcpyAsync(ctx->inst.ptr, ctx->h_inst.data(), sizeof(Instance),
+                             hipMemcpyHostToDevice, ctx->stream));
   p = Params{};
-  p.n = g->n;
+  p.num_inst = 1;
   p.stride = pl.stride;
-  p.nnz = g->nnz;
+  p.n_max = g->n;
   p.rules = rules;
-  p.rp = g->row_ptr;
-  p.ci = g->col_idx;
-  p.payload = static_cast<int32_t*>(ctx->payload.ptr);
+  p.inst = static_cast<const Instance*>(ctx->inst.ptr);
+  p.ist = static_cast<InstState*>(ctx->ist.ptr);
+  p.rp_all = g->row_ptr;
+  p.ci_all = g->col_idx;
   p.seq = static_cast<uint32_t*>(ctx->seq.ptr);
   p.ctr = static_cast<int32_t*>(ctx->ctr.ptr);
-  p.covers = static_cast<uint8_t*>(ctx->covers.ptr);
+  p.covers = covers;
   p.q_cap = 1;
-  p.cover_stride = pl.cover_stride;
-  p.words = pl.words;
+  p.bits = words ? static_cast<uint64_t*>(ctx->bits.ptr) : nullptr;
+  p.words = words;
   p.rp_lds = pl.rp_lds;
-  if (pl.words) {
-    if ((rc = ensure(ctx, ctx->bits, static_cast<size_t>(g->n) * pl.words * sizeof(uint64_t)))) return rc;
-    p.bits = static_cast<uint64_t*>(ctx->bits.ptr);
-  }
+  *wg_size = words ? 64 : static_cast<int32_t>(std::min<int64_t>(1024, round_up(g->n, 64)));
   DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
   VC_HIP(ctx, vc::launch_init(p, dres, ctx->stream));
-  VC_HIP(ctx, vc::launch_prepare(p, ctx->stream));
-  if (pl.words) VC_HIP(ctx, vc::launch_bitset_pack(p, ctx->stream));
+  VC_HIP(ctx, vc::launch_prepare(p, g->n, g->nnz, ctx->stream));
   return VC_OK;
 }
 
@@ -502,7 +771,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, Param
 
 extern "C" {
 
-const char* vc_version(void) { return "0.1.0"; }
+const char* vc_version(void) { return "0.2.0"; }
 
 const char* vc_strerror(int status) {
   switch (status) {
@@ -537,7 +806,7 @@ int vc_create(vc_ctx** ctx_out, int device, void* hip_stream) {
       ctx->own_stream = e == hipSuccess;
     }
   }
-  for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreate(&ctx->ev[i]);
+  if (e == hipSuccess && ensure_events(ctx, 4) != VC_OK) e = hipErrorUnknown;
   if (e != hipSuccess) {
     vc_destroy(ctx);
     return VC_ERR_DEVICE;
@@ -550,9 +819,9 @@ int vc_destroy(vc_ctx* ctx) {
   if (!ctx) return VC_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,       &ctx->payload, &ctx->seq,
-                    &ctx->ctr,    &ctx->stacks,   &ctx->covers,  &ctx->wg_stats,
-                    &ctx->result, &ctx->cover_tmp, &ctx->scratch_s, &ctx->bits};
+  DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,     &ctx->inst,     &ctx->ist,    &ctx->payload,
+                    &ctx->seq,    &ctx->ctr,    &ctx->stacks,   &ctx->covers, &ctx->wg_stats,
+                    &ctx->result, &ctx->scratch, &ctx->bits};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   for (hipEvent_t ev : ctx->ev)
@@ -582,35 +851,59 @@ int vc_pvc_device(vc_ctx* ctx, const vc_graph* g, int32_t k, const vc_options* o
   return solve(ctx, g, true, true, k, opts, yes_out, size_out, cover_dev, nullptr, stats);
 }
 
+int vc_mvc_batch(vc_ctx* ctx, const vc_batch* batch, const vc_options* opts, int32_t* status_out,
+                 int32_t* size_out, uint8_t* cover_out, int64_t* nodes_out, vc_stats* stats) {
+  return solve_batch(ctx, batch, false, false, nullptr, opts, status_out, nullptr, size_out,
+                     nullptr, cover_out, nodes_out, stats);
+}
+
+int vc_pvc_batch(vc_ctx* ctx, const vc_batch* batch, const int32_t* k, const vc_options* opts,
+                 int32_t* status_out, int32_t* yes_out, int32_t* size_out, uint8_t* cover_out,
+                 int64_t* nodes_out, vc_stats* stats) {
+  return solve_batch(ctx, batch, false, true, k, opts, status_out, yes_out, size_out, nullptr,
+                     cover_out, nodes_out, stats);
+}
+
+int vc_mvc_batch_device(vc_ctx* ctx, const vc_batch* batch, const vc_options* opts,
+                        int32_t* status_out, int32_t* size_out, uint8_t* cover_dev,
+                        int64_t* nodes_out, vc_stats* stats) {
+  return solve_batch(ctx, batch, true, false, nullptr, opts, status_out, nullptr, size_out,
+                     cover_dev, nullptr, nodes_out, stats);
+}
+
+int vc_pvc_batch_device(vc_ctx* ctx, const vc_batch* batch, const int32_t* k,
+                        const vc_options* opts, int32_t* status_out, int32_t* yes_out,
+                        int32_t* size_out, uint8_t* cover_dev, int64_t* nodes_out,
+                        vc_stats* stats) {
+  return solve_batch(ctx, batch, true, true, k, opts, status_out, yes_out, size_out, cover_dev,
+                     nullptr, nodes_out, stats);
+}
+
 int vc_greedy_device(vc_ctx* ctx, const vc_graph* g, int32_t* size_out, uint8_t* cover_dev) {
   int rc = enter(ctx);
   if (rc) return rc;
   if (!size_out) return fail(ctx, VC_ERR_INVALID_ARG, "size_out is NULL");
   if ((rc = check_graph_args(ctx, g))) return rc;
-  const int32_t n = g->n;
-  if (n == 0) {
+  if (g->n == 0) {
     *size_out = 0;
     return VC_OK;
   }
   Params p{};
-  if ((rc = setup_single(ctx, g, vc::kRulesAll, 0, p))) return rc;
-  DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
+  int32_t ws = 0;
+  if ((rc = setup_single(ctx, g, vc::kRulesAll, 0, nullptr, p, &ws))) return rc;
   hipStream_t s = ctx->stream;
-  const int gws = static_cast<int>(std::min<int64_t>(1024, round_up(n, 64)));
-  if (p.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, dres, s));
-  else VC_HIP(ctx, vc::launch_greedy(p, gws, dres, s));
-  DevResult res{};
-  VC_HIP(ctx, hipMemcpyAsync(&res, dres, sizeof res, hipMemcpyDeviceToHost, s));
+  if (p.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, s));
+  else VC_HIP(ctx, vc::launch_greedy(p, ws, s));
+  InstState is{};
+  VC_HIP(ctx, hipMemcpyAsync(&is, p.ist, sizeof is, hipMemcpyDeviceToHost, s));
   VC_HIP(ctx, hipStreamSynchronize(s));
-  if (res.err_row != kNoRow)
-    return fail(ctx, VC_ERR_INVALID_GRAPH, "CSR row " + std::to_string(res.err_row) +
-                                               " breaks the format");
+  if (is.err_row != vc::kNoRow) return fail(ctx, VC_ERR_INVALID_GRAPH, bad_row_message(is.err_row));
   if (cover_dev) {
-    VC_HIP(ctx, hipMemcpyAsync(cover_dev, p.covers, static_cast<size_t>(n),
+    VC_HIP(ctx, hipMemcpyAsync(cover_dev, p.covers, static_cast<size_t>(g->n),
                                hipMemcpyDeviceToDevice, s));
     VC_HIP(ctx, hipStreamSynchronize(s));
   }
-  *size_out = res.greedy;
+  *size_out = is.greedy;
   return VC_OK;
 }
 
@@ -623,26 +916,22 @@ int vc_reduce_device(vc_ctx* ctx, const vc_graph* g, int32_t* deg_dev, int32_t* 
   vc_options o{};
   o.flags = flags;
   if ((rc = check_options(ctx, &o))) return rc;
-  const int32_t n = g->n;
-  if (n == 0) return VC_OK;
+  if (g->n == 0) return VC_OK;
   Params p{};
-  if ((rc = setup_single(ctx, g, rules_from_flags(flags), flags, p))) return rc;
-  if ((rc = ensure(ctx, ctx->scratch_s, sizeof(int32_t)))) return rc;
-  DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
+  int32_t ws = 0;
+  if ((rc = setup_single(ctx, g, rules_from_flags(flags), flags, nullptr, p, &ws))) return rc;
   hipStream_t s = ctx->stream;
-  int32_t* sdev = static_cast<int32_t*>(ctx->scratch_s.ptr);
+  if ((rc = ensure(ctx, ctx->scratch, sizeof(int32_t)))) return rc;
+  int32_t* sdev = static_cast<int32_t*>(ctx->scratch.ptr);
   VC_HIP(ctx, hipMemcpyAsync(sdev, s_inout, sizeof(int32_t), hipMemcpyHostToDevice, s));
-  const int ws = static_cast<int>(std::min<int64_t>(1024, round_up(n, 64)));
-  if (p.words) VC_HIP(ctx, vc::launch_bitset_reduce(p, deg_dev, sdev, bound, dres, s));
-  else VC_HIP(ctx, vc::launch_reduce(p, ws, deg_dev, sdev, bound, dres, s));
-  DevResult res{};
+  if (p.words) VC_HIP(ctx, vc::launch_bitset_reduce(p, deg_dev, sdev, bound, s));
+  else VC_HIP(ctx, vc::launch_reduce(p, ws, deg_dev, sdev, bound, s));
+  InstState is{};
   int32_t s_new = 0;
-  VC_HIP(ctx, hipMemcpyAsync(&res, dres, sizeof res, hipMemcpyDeviceToHost, s));
+  VC_HIP(ctx, hipMemcpyAsync(&is, p.ist, sizeof is, hipMemcpyDeviceToHost, s));
   VC_HIP(ctx, hipMemcpyAsync(&s_new, sdev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   VC_HIP(ctx, hipStreamSynchronize(s));
-  if (res.err_row != kNoRow)
-    return fail(ctx, VC_ERR_INVALID_GRAPH, "CSR row " + std::to_string(res.err_row) +
-                                               " breaks the format");
+  if (is.err_row != vc::kNoRow) return fail(ctx, VC_ERR_INVALID_GRAPH, bad_row_message(is.err_row));
   *s_inout = s_new;
   return VC_OK;
 }

@@ -1,5 +1,12 @@
-// vc_internal.h -- shared between the device code (vc_device.hip) and the host runtime
-// (vc_host.cpp). Not part of the public ABI.
+// vc_internal.h -- shared between the device code (vc_device.hip, vc_bitset.hip) and the host
+// runtime (vc_host.cpp). Not part of the public ABI.
+//
+// Every launch works on a batch of instances; a single call is a batch of one. The graphs of
+// a batch are packed: instance i's n_i + 1 row pointers (its own numbering, starting at 0)
+// sit at rp_off in one row_ptr array, its nnz_i neighbour ids (0..n_i-1) at ci_off in one
+// col_idx array. A search-tree node carries the instance it belongs to; a workgroup takes the
+// root of an unstarted instance or a node from the worklist, and loads that node's instance
+// (its row pointers or adjacency rows) only when it differs from the one it had.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
@@ -17,21 +24,21 @@ enum : int32_t {
   kRulesAll = 15,
 };
 
-// Control words, each on its own 128-byte line so unrelated atomics never share a line.
+constexpr int32_t kNoRow = 0x7FFFFFFF;  // err_row of a graph that passed every check
+
+// Control words of one launch, each on its own 128-byte line so unrelated atomics never share
+// a line.
 enum CounterSlot : int {
-  kQCount = 0,    // int32: worklist entries reserved by producers and not yet by consumers
-  kQHead = 1,     // uint64: next consumer ticket
-  kQTail = 2,     // uint64: next producer ticket
-  kWork = 3,      // int32: sub-trees in the worklist or being walked by a workgroup
-  kBestKey = 4,   // uint64: (best cover size << 32) | index of the cover buffer holding it
-  kFound = 5,     // int32: PVC: 1 + index of the workgroup that found a cover, else 0
-  kAbort = 6,     // int32: non-zero stops every workgroup (budget, internal error)
-  kError = 7,     // int32: internal error code (1 = stack overflow)
-  kNodes = 8,     // uint64: nodes counted against the budget
-  kErrRow = 9,    // int32: first CSR row that breaks the format, INT32_MAX if none
-  kEdges0 = 10,   // int32: |E| of the input graph (sum of degrees / 2)
-  kQMaxCount = 11,// int32: largest worklist count seen by a producer
-  kNumCounters = 12,
+  kQCount = 0,     // int32: worklist entries reserved by producers and not yet by consumers
+  kQHead = 1,      // uint64: next consumer ticket
+  kQTail = 2,      // uint64: next producer ticket
+  kWork = 3,       // int32: sub-trees not finished: unstarted roots, queued or held nodes
+  kRootNext = 4,   // int32: next unstarted instance (root ticket)
+  kOpen = 5,       // int32: PVC: instances still without a cover (0 stops every workgroup)
+  kAbort = 6,      // int32: non-zero stops every workgroup (internal error)
+  kError = 7,      // int32: internal error code (1 = stack overflow, 2 = node of no instance)
+  kQMaxCount = 8,  // int32: largest worklist count seen by a producer
+  kNumCounters = 9,
 };
 constexpr int kCounterStride = 32;  // int32 words per control line (128 bytes)
 
@@ -41,7 +48,7 @@ enum Activity : int {
   kActReduce = 1,   // the reduction rules
   kActBranch = 2,   // max-degree pass and stopping test, removing v_max or N(v_max)
   kActDonate = 3,   // deferring a child: stack pushes and worklist enqueues
-  kActOther = 4,    // flags, bound, budget, recording solutions
+  kActOther = 4,    // flags, bound, budget, recording solutions, loading an instance
   kActTotal = 5,    // the whole kernel, per workgroup
   // parts of kActReduce (degree-array kernels only)
   kActDeg1 = 6,     // degree-one decisions
@@ -58,58 +65,87 @@ struct WgStats {
   int64_t enqueues;
   int64_t dequeues;
   int32_t max_depth;
-  int32_t pad;
+  int32_t instances;  // instances this workgroup loaded (roots and switches)
   int64_t cycles[kNumActivities];
 };
 
-// Everything a search kernel needs; passed by value.
-struct Params {
+// One instance of a batch (device memory, read-only during a launch). The instances of one
+// launch form a contiguous slice of the batch; vtx_first / ent_first number their vertices and
+// CSR entries consecutively across that slice (the index spaces of the prepare and finalize
+// kernels, and the bitset kernels' adjacency rows).
+struct Instance {
   int32_t n;
-  int32_t stride;       // int32 words per stored node: deg[n], s, pending, padding (mult. of 64)
   int32_t nnz;
+  int32_t rp_off;     // first of its n + 1 row pointers in the packed row_ptr
+  int32_t vtx_off;    // its cover is covers[vtx_off .. vtx_off + n) (the caller's packing)
+  int64_t ci_off;     // first of its nnz neighbour ids in the packed col_idx
+  int64_t ent_first;  // launch-local number of its first CSR entry
+  int32_t vtx_first;  // launch-local number of its first vertex
+  int32_t k;          // PVC parameter (>= 0)
+};
+
+// Per-instance search state and results (device memory).
+struct InstState {
+  int32_t err_row;      // first CSR row found to break the format, kNoRow if none
+  int32_t best;         // MVC: best cover size recorded (the greedy's first); PVC: size found
+  int32_t found;        // PVC: 1 once a cover of size <= k is recorded
+  int32_t lock;         // MVC: held while a workgroup writes the instance's cover
+  int32_t work;         // sub-trees of this instance not finished (root, queued, held)
+  int32_t aborted;      // 1 once the instance ran out of its node budget
+  int32_t greedy;       // MVC: size of the greedy cover
+  int32_t uncovered;    // CSR entries the recorded cover leaves uncovered (finalize)
+  int32_t cover_count;  // vertices in the recorded cover (finalize)
+  int32_t pad;
+  int64_t nodes;        // search-tree nodes visited on this instance
+};
+
+// Everything a kernel needs; passed by value.
+struct Params {
+  int32_t num_inst;     // instances of this launch (a contiguous slice of the batch)
+  int32_t stride;       // int32 words per stored node
+  int32_t n_max;        // largest n of this launch
   int32_t rules;
-  const int32_t* __restrict__ rp;
-  const int32_t* __restrict__ ci;
-  int32_t* payload;     // worklist node storage: cap * stride
-  uint32_t* seq;        // worklist slot tickets: cap
+  const Instance* inst;
+  InstState* ist;
+  const int32_t* __restrict__ rp_all;
+  const int32_t* __restrict__ ci_all;
+  int32_t* payload;     // worklist node storage: q_cap * stride
+  uint32_t* seq;        // worklist slot tickets: q_cap
   int32_t* ctr;         // control lines: kNumCounters * kCounterStride
   int32_t* stacks;      // per-workgroup stacks: num_wg * depth_cap * stride
-  uint8_t* covers;      // cover buffers: (num_wg + 1) * cover_stride; the last is the greedy's
+  uint8_t* covers;      // packed covers, one n_i-byte cover per instance
   WgStats* wg_stats;    // num_wg
-  int64_t k;            // PVC parameter
-  int64_t node_budget;  // 0 = none
-  int64_t budget_chunk; // nodes a workgroup visits between two reports to the budget counter
-  uint32_t q_cap;       // power of two
+  int64_t node_budget;  // per instance; 0 = none
+  int64_t budget_chunk; // nodes a workgroup visits between two reports to its instance
+  uint32_t q_cap;       // power of two, >= q_threshold + 2 * num_wg
   uint32_t q_threshold; // donate while count < threshold (0 = never)
   int32_t depth_cap;
   int32_t num_wg;
-  int32_t cover_stride;
-  int32_t greedy_slot;  // cover buffer index of the greedy's cover
-  uint64_t* bits;       // bitset kernels: adjacency rows, n * words 64-bit words
-  int32_t words;        // bitset kernels: 64-bit words per row; 0 selects the degree-array kernels
-  int32_t rp_lds;       // degree-array kernels: copy row_ptr into LDS after the node
+  uint64_t* bits;       // bitset kernels: adjacency rows, words per launch-local vertex
+  int32_t words;        // bitset kernels: words per row of this launch; 0 = degree arrays
+  int32_t rp_lds;       // degree-array kernels: copy the instance's row_ptr into LDS
+  int32_t pvc;          // 1: PVC (instances stop once answered), 0: MVC
+  int32_t pad;
 };
 
-// Dynamic LDS of a degree-array kernel: the node (stride words), then row_ptr if staged.
-inline size_t node_lds_bytes(int32_t stride, int32_t n, bool rp_lds) {
-  const size_t node = static_cast<size_t>(stride) * 4;
-  return rp_lds ? node + ((static_cast<size_t>(n) + 1) * 4 + 15) / 16 * 16 : node;
+// Degree-array node, stored and in LDS: deg[0..n_i), s at n_i, pending vertex at n_i + 1, the
+// instance (launch-local index) in the last word. stride >= n_max + 3, a multiple of 64.
+inline int32_t array_stride(int32_t n_max) {
+  return static_cast<int32_t>((static_cast<int64_t>(n_max) + 3 + 63) / 64 * 64);
 }
 
-// Result block written by the finalize kernel and copied to the host once.
+// Dynamic LDS of a degree-array kernel: the node (stride words), then row_ptr if staged.
+inline size_t node_lds_bytes(int32_t stride, int32_t n_max, bool rp_lds) {
+  const size_t node = static_cast<size_t>(stride) * 4;
+  return rp_lds ? node + ((static_cast<size_t>(n_max) + 1) * 4 + 15) / 16 * 16 : node;
+}
+
+// Launch-wide result block written by the finalize kernel and copied to the host once.
 struct DevResult {
-  int32_t err_row;
-  int32_t edges0;
-  int32_t size;
-  int32_t yes;
-  int32_t greedy;
   int32_t aborted;
   int32_t error;
-  int32_t uncovered;    // edges with no endpoint in the returned cover
-  int32_t cover_count;  // vertices in the returned cover
   int32_t max_depth;
   int32_t q_max_count;
-  int32_t pad;
   int64_t nodes;
   int64_t wg_nodes_max;
   int64_t wg_nodes_min;
@@ -117,35 +153,37 @@ struct DevResult {
   int64_t pops;
   int64_t enqueues;
   int64_t dequeues;
+  int64_t instances;
   int64_t cycles[kNumActivities];
 };
 
-// Kernel launchers (vc_device.hip). All run on `stream`; they return the HIP status of the
-// launch itself.
+// Kernel launchers. All run on `stream`; they return the HIP status of the launch itself.
+// `vertices` / `entries` are totals over the launch's instances (sum of n, sum of nnz).
+
+// vc_device.hip
 hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream);
-hipError_t launch_prepare(const Params& p, hipStream_t stream);
-hipError_t launch_greedy(const Params& p, int32_t wg_size, DevResult* res, hipStream_t stream);
+hipError_t launch_prepare(const Params& p, int64_t vertices, int64_t entries,
+                          hipStream_t stream);
+hipError_t launch_greedy(const Params& p, int32_t wg_size, hipStream_t stream);
 hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size,
                            hipStream_t stream);
-hipError_t launch_finalize(bool pvc, const Params& p, uint8_t* cover_out, DevResult* res,
+hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, DevResult* res,
                            hipStream_t stream);
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
-                         int64_t bound, DevResult* res, hipStream_t stream);
-
-// Bitset kernels (vc_bitset.hip), graphs of at most kMaxBitsetN vertices.
-constexpr int kMaxBitsetN = 256;
-hipError_t launch_bitset_pack(const Params& p, hipStream_t stream);
-hipError_t launch_bitset_greedy(const Params& p, DevResult* res, hipStream_t stream);
-hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStream_t stream);
-hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,
-                                DevResult* res, hipStream_t stream);
-hipError_t bitset_occupancy(int words, bool pvc, bool prof, int n, int* blocks_per_cu);
-size_t bitset_lds_bytes(int n, int words);
-int bitset_stride(int words);
-
-// Resident workgroups per CU for the traversal kernel at this size (occupancy API).
+                         int64_t bound, hipStream_t stream);
 hipError_t traverse_occupancy(bool pvc, bool prof, int32_t wg_size, size_t lds_bytes,
                               int* blocks_per_cu);
 hipError_t set_lds_limit(size_t lds_bytes);
+hipError_t launch_max_greedy(const Params& p, int32_t* out, hipStream_t stream);
+
+// vc_bitset.hip: graphs of at most kMaxBitsetN vertices
+constexpr int kMaxBitsetN = 256;
+hipError_t launch_bitset_greedy(const Params& p, hipStream_t stream);
+hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStream_t stream);
+hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,
+                                hipStream_t stream);
+hipError_t bitset_occupancy(int words, bool pvc, bool prof, int n_max, int* blocks_per_cu);
+size_t bitset_lds_bytes(int n_max, int words);
+int bitset_stride(int words);
 
 }  // namespace vc

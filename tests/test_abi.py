@@ -53,6 +53,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(b._Graph) == 24
     assert ctypes.sizeof(b._Options) == 48
     assert ctypes.sizeof(b._Stats) == 7 * 8 + 10 * 4 + 3 * 8 + 10 * 8
+    assert ctypes.sizeof(b._Batch) == 8 + 4 * 8
 
 
 def test_no_gpu_means_device_error(lib):
@@ -83,3 +84,15 @@ def test_product_package_does_not_use_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "vc_oracle" not in text and "liboracle" not in text, f
+
+
+def test_pack_batch_layout():
+    """The packed batch is each graph's own CSR, one after another."""
+    import graphs as G
+    from paper_2204_10402_amd import _binding as b
+    gs = [G.path(3), G.empty(0), G.cycle(4)]
+    n, nnz, rp, ci = b.pack_batch(gs)
+    assert n.tolist() == [3, 0, 4] and nnz.tolist() == [4, 0, 8]
+    assert rp.tolist() == [0, 1, 3, 4, 0, 0, 2, 4, 6, 8]
+    assert ci.tolist() == [1, 0, 2, 1, 1, 3, 0, 2, 1, 3, 0, 2]
+    assert b._offsets(n).tolist() == [0, 3, 3, 7]
