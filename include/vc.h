@@ -94,7 +94,7 @@ typedef struct {
 
 /* A batch of independent graphs, each in the format above, packed one after the other. */
 typedef struct {
-  int32_t count;           /* number of graphs, >= 0 */
+  int32_t count;           /* number of graphs, 0 <= count <= 2^22 */
   const int32_t *n;        /* HOST, count entries: vertices of graph i */
   const int32_t *nnz;      /* HOST, count entries: stored CSR entries of graph i */
   const int32_t *row_ptr;  /* sum(n[i] + 1) entries: graph i's row_ptr (starting at 0), then

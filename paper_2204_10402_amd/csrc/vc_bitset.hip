@@ -242,14 +242,16 @@ __device__ __forceinline__ void remove_neighbourhood_bits(Live<W>& L, int v,
 }
 
 
-// A stored node: W words of live bits (lo/hi 32-bit halves), |S|, the pending vertex, the
-// instance (launch-local index), padding to a multiple of four words. Lane 0 writes and reads
-// every stored node, so a node pushed on the workgroup's stack is read back in program order,
-// and the worklist publishes it with one release store.
+// A stored node: W words of live bits (lo/hi 32-bit halves), |S|, then one word packing the
+// pending vertex plus one (9 bits, n <= 256) with the instance (launch-local index, shifted
+// left 9), padding to a multiple of four words. Lane 0 writes and reads every stored node, so
+// a node pushed on the workgroup's stack is read back in program order, and the worklist
+// publishes it with one release store.
 template <int W>
 constexpr int bits_stride() {
-  return ((2 * W + 3) + 3) & ~3;
+  return ((2 * W + 2) + 3) & ~3;
 }
+constexpr int kPendingBits = 9;
 
 template <int W>
 __device__ __forceinline__ void bits_store(int32_t* dst, const Live<W>& L, int pending, int inst) {
@@ -260,14 +262,13 @@ __device__ __forceinline__ void bits_store(int32_t* dst, const Live<W>& L, int p
       dst[2 * w + 1] = static_cast<int32_t>(static_cast<uint32_t>(L.bits[w] >> 32));
     }
     dst[2 * W] = L.s;
-    dst[2 * W + 1] = pending;
-    dst[2 * W + 2] = inst;
+    dst[2 * W + 1] = (pending + 1) | (inst << kPendingBits);
   }
 }
 
 // Node words read by lane 0 into (uniform) L, pending vertex and instance.
 template <int W>
-__device__ __forceinline__ void bits_unpack(const uint32_t (&x)[2 * W + 3], Live<W>& L,
+__device__ __forceinline__ void bits_unpack(const uint32_t (&x)[2 * W + 2], Live<W>& L,
                                             int& pending, int& inst) {
 #pragma unroll
   for (int w = 0; w < W; ++w) {
@@ -276,16 +277,17 @@ __device__ __forceinline__ void bits_unpack(const uint32_t (&x)[2 * W + 3], Live
     L.bits[w] = (static_cast<uint64_t>(hi) << 32) | lo;
   }
   L.s = __builtin_amdgcn_readfirstlane(x[2 * W]);
-  pending = __builtin_amdgcn_readfirstlane(x[2 * W + 1]);
-  inst = __builtin_amdgcn_readfirstlane(x[2 * W + 2]);
+  const uint32_t tag = __builtin_amdgcn_readfirstlane(x[2 * W + 1]);
+  pending = static_cast<int>(tag & ((1u << kPendingBits) - 1u)) - 1;
+  inst = static_cast<int>(tag >> kPendingBits);
 }
 
 template <int W>
 __device__ __forceinline__ void bits_load(const int32_t* src, Live<W>& L, int& pending, int& inst) {
-  uint32_t x[2 * W + 3];
+  uint32_t x[2 * W + 2];
   if (lane_id() == 0) {
 #pragma unroll
-    for (int i = 0; i < 2 * W + 3; ++i) x[i] = static_cast<uint32_t>(src[i]);
+    for (int i = 0; i < 2 * W + 2; ++i) x[i] = static_cast<uint32_t>(src[i]);
   }
   bits_unpack<W>(x, L, pending, inst);
 }
@@ -346,7 +348,7 @@ __device__ __forceinline__ bool bits_enqueue(const Params& p, Ctrl& c, const Liv
       int32_t* dst = p.payload + static_cast<size_t>(c.slot) * p.stride;
       if (oldest) {
 #pragma unroll
-        for (int i = 0; i < 2 * W + 3; ++i) dst[i] = oldest[i];
+        for (int i = 0; i < 2 * W + 2; ++i) dst[i] = oldest[i];
       } else {
         bits_store<W>(dst, L, pending, inst);
       }
@@ -363,7 +365,8 @@ template <int W>
 __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pending,
                                             int& inst) {
   int status = 3;
-  uint32_t words[2 * W + 3];
+  uint32_t words[2 * W + 2];
+  int root = 0;
   if (lane_id() == 0) {
     int polls = 0;
     while (status == 3) {
@@ -387,7 +390,7 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pe
           if (status == 1) {
             const int32_t* src = p.payload + static_cast<size_t>(slot) * p.stride;
 #pragma unroll
-            for (int i = 0; i < 2 * W + 3; ++i) words[i] = static_cast<uint32_t>(src[i]);
+            for (int i = 0; i < 2 * W + 2; ++i) words[i] = static_cast<uint32_t>(src[i]);
             store_release(p.seq + slot, 2u * (lap + 1u));
           }
         } else {
@@ -397,7 +400,7 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pe
         const int32_t r = fetch_add(ctr_i32(p, kRootNext), 1);
         if (r < p.num_inst) {
           status = 2;
-          words[2 * W + 2] = static_cast<uint32_t>(r);
+          root = r;
         }
       } else if (load_relaxed(ctr_i32(p, kWork)) == 0) {
         status = 0;  // nothing queued, held or unstarted: the launch is over
@@ -411,7 +414,7 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pe
   }
   status = __builtin_amdgcn_readfirstlane(status);
   if (status == 1) bits_unpack<W>(words, L, pending, inst);
-  else if (status == 2) inst = __builtin_amdgcn_readfirstlane(words[2 * W + 2]);
+  else if (status == 2) inst = __builtin_amdgcn_readfirstlane(root);
   return status;
 }
 
@@ -450,7 +453,7 @@ __global__ void __launch_bounds__(64) bitset_greedy_kernel(Params p) {
 template <bool PVC>
 __device__ __forceinline__ int bits_claim(const Params& p, int j, int32_t s) {
   InstState* is = p.ist + j;
-  if (PVC) return atomicCAS(&is->found, 0, 1) == 0;
+  if (PVC) return (atomicOr(&is->state, kInstFound) & kInstFound) == 0;
   if (atomicMin(&is->best, s) <= s) return 0;
   lock_acquire(&is->lock);
   if (load_relaxed(&is->best) == s) return 1;
@@ -474,7 +477,7 @@ __device__ __forceinline__ void bits_report_nodes(const Params& p, int j, int64_
   unsigned long long* total = reinterpret_cast<unsigned long long*>(&p.ist[j].nodes);
   const unsigned long long before = fetch_add(total, static_cast<unsigned long long>(count));
   if (p.node_budget > 0 && static_cast<int64_t>(before) + count >= p.node_budget)
-    store_relaxed(&p.ist[j].aborted, 1);
+    atomicOr(&p.ist[j].state, kInstOutOfBudget);
 }
 
 // The hybrid traversal (§IV-A, Fig. 4; termination §IV-C) on bitset nodes, over every instance
@@ -501,6 +504,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0, insts = 0;
   int64_t unreported = 0;
   int max_depth = 0;
+  uint32_t headers = 0;  // node headers read so far
   Live<W> L;
 
   for (;;) {
@@ -510,6 +514,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         --top;
         bits_load<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, pending, inst);
         ++pops;
+        clk.charge(kActAcquire);
       } else {
         if (holding) {
           if (tid == 0) release_work(p, cur);
@@ -557,11 +562,14 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
       have = true;
     }
 
-    // node header: global stop, the instance's flags and its current best
-    const int stop = __builtin_amdgcn_readfirstlane(search_stopped(p) ? 1 : 0);
-    const int drop = __builtin_amdgcn_readfirstlane(
-        load_relaxed(&p.ist[cur].aborted) | (PVC ? load_relaxed(&p.ist[cur].found) : 0));
-    const int32_t best = PVC ? 0 : __builtin_amdgcn_readfirstlane(load_relaxed(&p.ist[cur].best));
+    // node header: the instance's flags and current best (one load), and every 16 nodes the
+    // launch-wide stop (idle workgroups also look at it while they wait for work)
+    const uint64_t h = uniform64(inst_header(p, cur));
+    const int32_t state = static_cast<int32_t>(h >> 32);
+    const int stop = (headers++ & 15) == 0
+                         ? __builtin_amdgcn_readfirstlane(search_stopped(p) ? 1 : 0) : 0;
+    const int drop = (state & kInstOutOfBudget) | (PVC ? (state & kInstFound) : 0);
+    const int32_t best = static_cast<int32_t>(static_cast<uint32_t>(h));
     clk.charge(kActOther);
     if (stop) break;
     if (drop) {  // answered or out of budget: drop this node and the rest of the sub-tree
@@ -704,7 +712,7 @@ static const void* bitset_fn(int words, bool pvc, bool prof) {
 
 size_t bitset_lds_bytes(int n_max, int words) { return static_cast<size_t>(n_max) * words * 8; }
 
-int bitset_stride(int words) { return ((2 * words + 3) + 3) & ~3; }
+int bitset_stride(int words) { return ((2 * words + 2) + 3) & ~3; }
 
 hipError_t launch_bitset_greedy(const Params& p, hipStream_t stream) {
   const size_t lds = bitset_lds_bytes(p.n_max, p.words);

@@ -535,9 +535,9 @@ __global__ void init_kernel(Params p, DevResult* res) {
     InstState s{};
     s.err_row = kNoRow;
     s.best = 0x7FFFFFFF;
-    s.work = 1;
     s.greedy = -1;
     p.ist[j] = s;
+    p.work[j] = 1;
   }
 }
 
@@ -647,7 +647,7 @@ __global__ void __launch_bounds__(1024) greedy_kernel(Params p) {
 template <bool PVC>
 __device__ int claim_solution(const Params& p, int j, int32_t s) {
   InstState* is = p.ist + j;
-  if (PVC) return atomicCAS(&is->found, 0, 1) == 0;
+  if (PVC) return (atomicOr(&is->state, kInstFound) & kInstFound) == 0;
   if (atomicMin(&is->best, s) <= s) return 0;
   lock_acquire(&is->lock);
   if (load_relaxed(&is->best) == s) return 1;
@@ -674,7 +674,7 @@ __device__ __forceinline__ void report_nodes(const Params& p, int j, int64_t cou
   unsigned long long* total = reinterpret_cast<unsigned long long*>(&p.ist[j].nodes);
   const unsigned long long before = fetch_add(total, static_cast<unsigned long long>(count));
   if (p.node_budget > 0 && static_cast<int64_t>(before) + count >= p.node_budget)
-    store_relaxed(&p.ist[j].aborted, 1);
+    atomicOr(&p.ist[j].state, kInstOutOfBudget);
 }
 
 // The hybrid traversal (§IV-A, Fig. 4; PVC differences in §IV-A, termination §IV-C) over every
@@ -689,9 +689,13 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   int32_t* st = reinterpret_cast<int32_t*>(lds4);
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
-  if (tid == 0) c.flag_epoch = -1;
+  if (tid == 0) {
+    c.flag_epoch = -1;
+    c.stop = 0;
+  }
   ActivityClock<PROF> clk;
   clk.begin();
+  uint32_t headers = 0;  // thread 0: node headers read so far
 
   int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * p.stride;
   // The stack is a ring of depth_cap entries holding [bot, top): pops take the top, donations
@@ -716,6 +720,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         node_load(st, stack + static_cast<size_t>(top % p.depth_cap) * p.stride, p.stride);
         ++pops;
         __syncthreads();
+        clk.charge(kActAcquire);
       } else {
         if (holding) {
           if (tid == 0) release_work(p, cur);
@@ -776,12 +781,14 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       have = true;
     }
 
-    // node header: global stop, the instance's flags and its current best, read once
+    // node header: the instance's flags and current best (one load), and every 16 nodes
+    // the launch-wide stop (idle workgroups also look at it while they wait for work)
     if (tid == 0) {
-      InstState* is = p.ist + cur;
-      c.stop = search_stopped(p);
-      c.drop = load_relaxed(&is->aborted) | (PVC ? load_relaxed(&is->found) : 0);
-      c.best = PVC ? 0 : load_relaxed(&is->best);
+      const uint64_t h = inst_header(p, cur);
+      const int32_t state = static_cast<int32_t>(h >> 32);
+      if ((headers++ & 15) == 0) c.stop = search_stopped(p);
+      c.drop = (state & kInstOutOfBudget) | (PVC ? (state & kInstFound) : 0);
+      c.best = static_cast<int32_t>(static_cast<uint32_t>(h));
     }
     __syncthreads();
     clk.charge(kActOther);
@@ -920,7 +927,8 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertice
       const int j = instance_of_vertex(p, i);
       const Instance in = p.inst[j];
       const InstState is = p.ist[j];
-      const bool answer = is.err_row == kNoRow && !is.aborted && (!p.pvc || is.found);
+      const bool answer = is.err_row == kNoRow && !(is.state & kInstOutOfBudget) &&
+                          (!p.pvc || (is.state & kInstFound));
       uint8_t* cov = p.covers + in.vtx_off;
       const int v = static_cast<int>(i - in.vtx_first);
       if (answer) one = cov[v] != 0;
@@ -934,7 +942,8 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertice
       const int j = instance_of_entry(p, i);
       const Instance in = p.inst[j];
       const InstState is = p.ist[j];
-      const bool answer = is.err_row == kNoRow && !is.aborted && (!p.pvc || is.found);
+      const bool answer = is.err_row == kNoRow && !(is.state & kInstOutOfBudget) &&
+                          (!p.pvc || (is.state & kInstFound));
       if (answer) {
         const int32_t* rp = p.rp_all + in.rp_off;
         const uint8_t* cov = p.covers + in.vtx_off;

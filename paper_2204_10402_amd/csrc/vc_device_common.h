@@ -168,6 +168,11 @@ __device__ __forceinline__ void backoff(int& spins) {
 }
 
 
+// An instance's best size (low half) and state flags (high half), read as one word.
+__device__ __forceinline__ uint64_t inst_header(const Params& p, int j) {
+  return load_relaxed(reinterpret_cast<unsigned long long*>(&p.ist[j].best));
+}
+
 // Is the search being stopped: aborted, or (PVC) every instance answered?
 __device__ __forceinline__ bool search_stopped(const Params& p) {
   return load_relaxed(ctr_i32(p, kAbort)) != 0 || (p.pvc && load_relaxed(ctr_i32(p, kOpen)) == 0);
@@ -202,7 +207,7 @@ __device__ inline int enqueue_reserve(const Params& p, Ctrl& c, int inst) {
   int32_t* count = ctr_i32(p, kQCount);
   const int32_t seen = load_relaxed(count);
   if (seen >= static_cast<int32_t>(p.q_threshold)) return 0;
-  fetch_add(&p.ist[inst].work, 1);
+  fetch_add(p.work + inst, 1);
   fetch_add(ctr_i32(p, kWork), 1);
   const int32_t before = fetch_add(count, 1);  // stays below cap: threshold + 2 num_wg <= cap
   if (before + 1 > load_relaxed(ctr_i32(p, kQMaxCount))) atomicMax(ctr_i32(p, kQMaxCount), before + 1);
@@ -293,10 +298,9 @@ __device__ inline int dequeue_begin(const Params& p, Ctrl& c) {
 }
 
 // Thread 0: the workgroup has finished a sub-tree of instance `inst` that it took from the
-// worklist or as a root. The instance's counter is lowered with release order, after
-// everything the workgroup wrote for the instance.
+// worklist or as a root.
 __device__ inline void release_work(const Params& p, int inst) {
-  __hip_atomic_fetch_add(&p.ist[inst].work, -1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  fetch_add(p.work + inst, -1);
   fetch_add(ctr_i32(p, kWork), -1);
 }
 

@@ -34,7 +34,8 @@ struct vc_ctx {
   bool own_stream = false;
   hipDeviceProp_t prop{};
   size_t lds_limit_set = 0;
-  DevBuf rp, ci, inst, ist, payload, seq, ctr, stacks, covers, wg_stats, result, scratch, bits;
+  DevBuf rp, ci, inst, ist, iwork, payload, seq, ctr, stacks, covers, wg_stats, result, scratch,
+      bits;
   std::vector<hipEvent_t> ev;  // two per launch group
   std::string last_error;
   // occupancy-API answers: (kernel family, pvc, profiled, workgroup size, words, LDS bytes)
@@ -325,6 +326,8 @@ int check_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, int64_t* total_rp, int6
   }
   if (rp > 0x7FFFFFFF || nv > 0x7FFFFFFF)
     return fail(ctx, VC_ERR_INVALID_ARG, "batch has more than 2^31 row pointers");
+  if (b.count > vc::kMaxLaunchInstances)
+    return fail(ctx, VC_ERR_INVALID_ARG, "batch has more than 2^22 graphs");
   if (b.count > 0 && !b.rp) return fail(ctx, VC_ERR_INVALID_ARG, "row_ptr is NULL");
   if (ne > 0 && !b.ci) return fail(ctx, VC_ERR_INVALID_ARG, "col_idx is NULL");
   *total_rp = rp;
@@ -409,6 +412,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   if (m > 0) {
     if ((rc = ensure(ctx, ctx->inst, static_cast<size_t>(m) * sizeof(Instance)))) return rc;
     if ((rc = ensure(ctx, ctx->ist, static_cast<size_t>(m) * sizeof(InstState)))) return rc;
+    if ((rc = ensure(ctx, ctx->iwork, static_cast<size_t>(m) * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->result, static_cast<size_t>(ng) * sizeof(DevResult)))) return rc;
     if ((rc = ensure(ctx, ctx->scratch, static_cast<size_t>(ng) * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
@@ -448,6 +452,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.rules = rules_from_flags(flags);
     p.inst = d_inst + g.begin;
     p.ist = d_ist + g.begin;
+    p.work = static_cast<int32_t*>(ctx->iwork.ptr) + g.begin;
     p.rp_all = b.rp;
     p.ci_all = b.ci;
     p.payload = static_cast<int32_t*>(ctx->payload.ptr);
@@ -544,14 +549,14 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
       if (first_bad < 0) first_bad = i, bad_msg = bad_row_message(is.err_row);
       continue;
     }
-    if (is.aborted) {
+    if (is.state & vc::kInstOutOfBudget) {
       status[i] = VC_ERR_BUDGET;
       size[i] = -1;
       yes[i] = 0;
       if (first_bad < 0) first_bad = i, bad_msg = "node budget exhausted";
       continue;
     }
-    const bool answered = !pvc || is.found;
+    const bool answered = !pvc || (is.state & vc::kInstFound);
     yes[i] = answered ? 1 : 0;
     size[i] = answered ? is.best : -1;
     const bool ok = !answered ? (is.cover_count == 0)
@@ -602,7 +607,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
       sp->depth_cap = std::max(sp->depth_cap, g.depth_cap);
       sp->n = std::max(sp->n, g.n_max);
       sp->bitset_words = std::max(sp->bitset_words, g.words);
-      sp->node_bytes = std::max(sp->node_bytes, g.words ? 8 * g.words + 12 : 4 * (g.n_max + 3));
+      sp->node_bytes = std::max(sp->node_bytes, g.words ? 8 * g.words + 8 : 4 * (g.n_max + 3));
       for (int a = 0; a < vc::kNumActivities; ++a) sp->cycles[a] += r.cycles[a];
     }
     sp->greedy_size = (!pvc && out.single && m == 1) ? ctx->h_ist[0].greedy : -1;
@@ -729,6 +734,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   if ((rc = plan_launch(ctx, false, g->n, words, &o, pl))) return rc;
   if ((rc = ensure(ctx, ctx->inst, sizeof(Instance)))) return rc;
   if ((rc = ensure(ctx, ctx->ist, sizeof(InstState)))) return rc;
+  if ((rc = ensure(ctx, ctx->iwork, sizeof(int32_t)))) return rc;
   if ((rc = ensure(ctx, ctx->result, sizeof(DevResult)))) return rc;
   if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
   if ((rc = ensure(ctx, ctx->seq, sizeof(uint32_t)))) return rc;
@@ -751,6 +757,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   p.rules = rules;
   p.inst = static_cast<const Instance*>(ctx->inst.ptr);
   p.ist = static_cast<InstState*>(ctx->ist.ptr);
+  p.work = static_cast<int32_t*>(ctx->iwork.ptr);
   p.rp_all = g->row_ptr;
   p.ci_all = g->col_idx;
   p.seq = static_cast<uint32_t*>(ctx->seq.ptr);
@@ -819,7 +826,7 @@ int vc_destroy(vc_ctx* ctx) {
   if (!ctx) return VC_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,     &ctx->inst,     &ctx->ist,    &ctx->payload,
+  DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,     &ctx->inst,     &ctx->ist,    &ctx->iwork, &ctx->payload,
                     &ctx->seq,    &ctx->ctr,    &ctx->stacks,   &ctx->covers, &ctx->wg_stats,
                     &ctx->result, &ctx->scratch, &ctx->bits};
   for (DevBuf* b : bufs)

@@ -84,20 +84,26 @@ struct Instance {
   int32_t k;          // PVC parameter (>= 0)
 };
 
-// Per-instance search state and results (device memory).
+// Per-instance search state and results (device memory). `best` and `state` share one
+// aligned 64-bit word, read with a single load at every search-tree node.
+enum : int32_t {
+  kInstFound = 1,        // PVC: a cover of size <= k has been recorded
+  kInstOutOfBudget = 2,  // the instance used up its node budget
+};
 struct InstState {
-  int32_t err_row;      // first CSR row found to break the format, kNoRow if none
   int32_t best;         // MVC: best cover size recorded (the greedy's first); PVC: size found
-  int32_t found;        // PVC: 1 once a cover of size <= k is recorded
+  int32_t state;        // kInstFound | kInstOutOfBudget
+  int32_t err_row;      // first CSR row found to break the format, kNoRow if none
   int32_t lock;         // MVC: held while a workgroup writes the instance's cover
-  int32_t work;         // sub-trees of this instance not finished (root, queued, held)
-  int32_t aborted;      // 1 once the instance ran out of its node budget
   int32_t greedy;       // MVC: size of the greedy cover
   int32_t uncovered;    // CSR entries the recorded cover leaves uncovered (finalize)
   int32_t cover_count;  // vertices in the recorded cover (finalize)
   int32_t pad;
   int64_t nodes;        // search-tree nodes visited on this instance
 };
+
+// Largest batch a launch takes: a bitset node packs its instance with the pending vertex.
+constexpr int32_t kMaxLaunchInstances = 1 << 22;
 
 // Everything a kernel needs; passed by value.
 struct Params {
@@ -107,6 +113,8 @@ struct Params {
   int32_t rules;
   const Instance* inst;
   InstState* ist;
+  int32_t* work;        // per instance: sub-trees not finished (root, queued, held). Kept apart
+                        // from InstState: its atomics would slow the per-node header loads
   const int32_t* __restrict__ rp_all;
   const int32_t* __restrict__ ci_all;
   int32_t* payload;     // worklist node storage: q_cap * stride
