@@ -4,17 +4,28 @@ one MI355X, inputs resident in device memory.
     python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-cpu-baseline]
 
 A step solves every instance of the workload once, inputs resident in device memory:
+  --mode batch   one batched call for all of them (vc_pvc_batch_device / vc_mvc_batch_device;
+                 the default)
   --mode single  one device-form call per instance (vc_pvc_device / vc_mvc_device)
-  --mode batch   one batched call for all of them (vc_pvc_batch_device / vc_mvc_batch_device)
+After the timed steps, one untimed pass of single calls gives each instance's time-to-solve
+and the throughput of the plain form (one persistent launch per instance).
 Workloads (seeded, synthetic):
   planted-pvc    PVC on planted-cover graphs n=5000, |C|=400, 40,000 edges (75% C-rest),
                  k in {400, 399}, seeds 0-3: 8 solves per step (default)
   er60-mvc       MVC on G(60, 0.10), seed 0
   hard-mvc       MVC on random 5-regular n=120 and G(150, 0.08), seeds 0-7: 16 solves
   planted-batch  4,096 planted-cover PVC instances, n uniform in [40, 400], average degree in
-                 [3, 12], |C| = 0.3n, k = |C| (even i) or |C| - 1 (odd i), master seed 0;
-                 also timed once with one launch per instance for comparison
+                 [3, 12], |C| = 0.3n, k = |C| (even i) or |C| - 1 (odd i), master seed 0
 Prints one JSON line on stdout; progress goes to stderr.
+
+HBM traffic of the traversal kernel (roofline "traffic"): two rocprofv3 counter runs of
+    python bench.py --workload W --traffic-probe
+one with --pmc FETCH_SIZE and one with --pmc WRITE_SIZE, each writing CSV under a directory;
+the probe also runs a plain elementwise kernel over 512 MiB (read once, written once) whose
+counters calibrate the units.
+    python bench.py --workload W --summarize-traffic FETCH_DIR WRITE_DIR
+then writes profiles/traverse_kernel_W_traffic.md, which later runs read while the kernel
+sources are unchanged.
 """
 
 import argparse
@@ -72,6 +83,13 @@ def algorithmic_bytes(gs, st):
     return st["node_bytes"] * copies + sum(4 * (g.n + 1 + g.nnz) for g in gs)
 
 
+COPY_BYTES = 512 << 20
+
+
+def traffic_path(workload):
+    return os.path.join(ROOT, "profiles", f"traverse_kernel_{workload}_traffic.md")
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for f in ("vc_device.hip", "vc_bitset.hip", "vc_device_common.h", "vc_internal.h"):
@@ -81,17 +99,63 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload):
-    """HBM bytes per traversal launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, if a profile of the
-    current kernel source is on file under profiles/."""
-    path = os.path.join(ROOT, "profiles", f"traverse_kernel_{workload}_traffic.json")
+    """HBM bytes per traversal launch from rocprofv3 FETCH_SIZE/WRITE_SIZE, if a summary for
+    the current kernel sources is on file under profiles/ (a JSON block in the .md)."""
     try:
-        with open(path) as f:
-            doc = json.load(f)
-    except (OSError, ValueError):
+        with open(traffic_path(workload)) as f:
+            text = f.read()
+        doc = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, ValueError, IndexError):
         return None
     if doc.get("kernel_source_hash") != kernel_source_hash():
         return None
     return doc.get("hbm_bytes_per_launch")
+
+
+def read_counter_csv(directory, counter):
+    """(kernel name, value) of every dispatch in a rocprofv3 --pmc CSV under `directory`."""
+    import csv
+    rows = []
+    for dirpath, _, files in os.walk(directory):
+        for f in files:
+            if f.endswith("counter_collection.csv"):
+                with open(os.path.join(dirpath, f)) as fh:
+                    for r in csv.DictReader(fh):
+                        if r.get("Counter_Name") == counter:
+                            rows.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    if not rows:
+        raise SystemExit(f"no {counter} rows under {directory}")
+    return rows
+
+
+def summarize_traffic(workload, fetch_dir, write_dir):
+    """Per-launch HBM bytes of the traversal kernels from the two counter runs, each scaled by
+    what the same counter reads for the calibration copy (COPY_BYTES read and written)."""
+    out = {"workload": workload, "kernel_source_hash": kernel_source_hash()}
+    for counter, directory in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = read_counter_csv(directory, counter)
+        copy = [v for k, v in rows if "copy" in k.lower() or "elementwise" in k.lower()]
+        trav = [v for k, v in rows if "traverse_kernel" in k]
+        if not copy or not trav:
+            raise SystemExit(f"{counter}: calibration copy or traversal dispatches missing")
+        scale = COPY_BYTES / max(copy)  # bytes per counter unit
+        out[counter] = {"dispatches": len(trav), "raw_mean": statistics.mean(trav),
+                        "calibration_raw": max(copy), "bytes_per_unit": scale,
+                        "bytes_per_launch": statistics.mean(trav) * scale}
+    out["hbm_bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + \
+        out["WRITE_SIZE"]["bytes_per_launch"]
+    with open(traffic_path(workload), "w") as f:
+        f.write(f"# HBM traffic of the traversal kernel, workload {workload}\n\n"
+                "Two rocprofv3 counter runs of the traffic probe, then the summary:\n\n"
+                f"    rocprofv3 --pmc FETCH_SIZE --output-format csv -d FETCH_DIR -- "
+                f"python3 bench.py --workload {workload} --traffic-probe\n"
+                f"    rocprofv3 --pmc WRITE_SIZE --output-format csv -d WRITE_DIR -- "
+                f"python3 bench.py --workload {workload} --traffic-probe\n"
+                f"    python bench.py --workload {workload} --summarize-traffic FETCH_DIR WRITE_DIR\n\n"
+                "Each counter is scaled by its reading for a plain elementwise kernel over "
+                f"{COPY_BYTES >> 20} MiB (read once, written once) in the same run.\n\n"
+                "```json\n" + json.dumps(out, indent=1) + "\n```\n")
+    print(json.dumps(out))
 
 
 def cpu_baseline(workload, insts):
@@ -137,15 +201,20 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="planted-pvc", choices=WORKLOADS)
-    ap.add_argument("--mode", default=None, choices=["single", "batch"],
-                    help="default: batch for planted-batch, single otherwise")
+    ap.add_argument("--mode", default="batch", choices=["single", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="run 2 steps and a calibration copy, for rocprofv3 --pmc")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     a = ap.parse_args()
     if a.gpus != 1:
         log("bench.py measures one GPU: the traversal runs on a single MI355X and no multi-GPU "
             "path is built; run with --gpus 1")
         sys.exit(2)
-    mode = a.mode or ("batch" if a.workload == "planted-batch" else "single")
+    if a.summarize_traffic:
+        summarize_traffic(a.workload, *a.summarize_traffic)
+        return
+    mode = a.mode
 
     import numpy as np
     import torch
@@ -195,6 +264,16 @@ def main():
             record.append((gs, r.stats, dt, len(gs)))
 
     step = run_batch if mode == "batch" else run_single
+    if a.traffic_probe:
+        for _ in range(2):
+            step(None)
+        src = torch.ones(COPY_BYTES, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 1, out=dst)  # an elementwise kernel: COPY_BYTES read, COPY_BYTES written
+        torch.cuda.synchronize()
+        log("traffic probe done")
+        return
     for i in range(a.warmup):
         step(None)
         log(f"warmup {i + 1}/{a.warmup} done")
@@ -235,9 +314,9 @@ def main():
                    "wl_capacity": last["wl_capacity"], "wl_threshold": last["wl_threshold"]},
         "nodes_per_step": nodes // a.steps,
         "instances_per_s": solved / wall,
-        "time_to_solve_ms": {"median": 1000 * statistics.median(dt for _, _, dt, _ in rec),
-                             "max": 1000 * max(dt for _, _, dt, _ in rec),
-                             "per": "call" if mode == "batch" else "instance"},
+        "call_ms": {"median": 1000 * statistics.median(dt for _, _, dt, _ in rec),
+                    "max": 1000 * max(dt for _, _, dt, _ in rec),
+                    "per": "batched call" if mode == "batch" else "single call"},
         "kernel_ms_avg": 1000 * avg_kernel_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
@@ -246,17 +325,21 @@ def main():
                      + (" (all launches of a call)" if mode == "batch" else ""),
                      "algorithmic_bytes_per_launch": alg_bytes / calls},
     }
-    if a.workload == "planted-batch":
-        # the plain form: one device-form call (one persistent launch) per instance, once
-        log("timing one launch per instance for comparison")
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        run_single(None)
-        torch.cuda.synchronize()
-        plain = time.perf_counter() - t
-        out["per_instance_launches"] = {"instances_per_s": len(insts) / plain,
-                                        "seconds": round(plain, 3)}
-        out["batched_over_per_instance"] = out["instances_per_s"] / (len(insts) / plain)
+    # one untimed pass of single calls: per-instance time-to-solve, and the plain form's rate
+    log("one pass of single calls (time-to-solve per instance)")
+    torch.cuda.synchronize()
+    single = []
+    t = time.perf_counter()
+    run_single(single)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t
+    tts = sorted(1000 * dt for _, _, dt, _ in single)
+    out["single_calls"] = {
+        "instances_per_s": len(insts) / plain, "seconds": round(plain, 4),
+        "nodes_per_s": sum(st["nodes"] for _, st, _, _ in single) / plain,
+        "time_to_solve_ms": {"median": statistics.median(tts),
+                             "p99": tts[int(0.99 * (len(tts) - 1))], "max": tts[-1]}}
+    out["batched_over_single_calls"] = out["instances_per_s"] / (len(insts) / plain)
     if not a.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample")
         out["cpu_baseline"] = cpu_baseline(a.workload, insts)

@@ -71,8 +71,8 @@ __device__ __forceinline__ int32_t wave_incl_max(int32_t x) {
 
 // Walk the CSR rows [beg, end) held by the lanes of a wavefront (empty where beg >= end) as one
 // list, 64 consecutive entries per step, so rows of any length keep every lane busy and
-// neighbouring lanes read neighbouring entries. fn(x, tag) runs for every entry x = ci[j], with
-// `tag` the value the row's owner lane passed in. The owner of each entry of a step comes from
+// neighbouring lanes read neighbouring entries. fn(x, tag, j) runs for every entry x = ci[j],
+// with `tag` the value the row's owner lane passed in; it runs in divergent code. The owner of each entry of a step comes from
 // head flags: every row writes its lane into `heads` (this wavefront's 64 LDS words) at its
 // first position in the step, and a max-scan over the lanes carries it forward. Eight steps
 // are issued together, with unconditional loads (an index past the list reads entry 0, whose
@@ -87,7 +87,7 @@ __device__ __forceinline__ void wave_expand_rows(const int32_t* __restrict__ ci,
   const int total = __builtin_amdgcn_readlane(incl, 63);
   constexpr int kUnroll = 8;
   for (int t0 = 0; t0 < total; t0 += 64 * kUnroll) {
-    int xs[kUnroll], tags[kUnroll];
+    int xs[kUnroll], tags[kUnroll], js[kUnroll];
     bool ok[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -106,12 +106,13 @@ __device__ __forceinline__ void wave_expand_rows(const int32_t* __restrict__ ci,
         const int oe = shfl(excl, src);
         tags[u] = shfl(tag, src);
         ok[u] = t < total;
-        xs[u] = ci[ok[u] ? ob + (t - oe) : 0];  // not read until every step has issued
+        js[u] = ok[u] ? ob + (t - oe) : 0;
+        xs[u] = ci[js[u]];  // not read until every step has issued
       }
     }
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u)
-      if (ok[u]) fn(xs[u], tags[u]);
+      if (ok[u]) fn(xs[u], tags[u], js[u]);
   }
 }
 
@@ -143,31 +144,34 @@ __device__ __forceinline__ void for_each_batch(const int32_t* st, int n, Pred pr
   if (count) process(held, count);
 }
 
-// Remove every marked vertex (paper §IV-B): each live unmarked neighbour of a marked vertex
-// loses one degree per marked neighbour, then marked vertices become kSent and s grows by
-// their number. Called right after a barrier that ends a decide step.
+// Remove every marked vertex (paper §IV-B): marked vertices become kSent and s grows by their
+// number; each live unmarked neighbour of a marked vertex loses one degree per marked
+// neighbour. A marked vertex is set to kSent by the lane that finds it in the same scan that
+// collects the rows to walk: the walks only decrement entries that are live and unmarked, so
+// a vertex seen as marked or as kSent is skipped either way. Called right after a barrier that
+// ends a decide step; ends with a barrier.
 __device__ void apply_marks(const Node nd) {
   const int n = nd.n;
   int32_t* st = nd.st;
-  for_each_batch(st, n, [](int, int32_t d) { return d >= 0 && (d & kFlag); },
+  int cnt = 0;
+  for_each_batch(st, n,
+                 [&](int v, int32_t d) {
+                   const bool marked = d >= 0 && (d & kFlag);
+                   if (marked) {
+                     st[v] = kSent;
+                     ++cnt;
+                   }
+                   return marked;
+                 },
                  [&](int f, int count) {
                    const bool mine = lane_id() < count;
                    wave_expand_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[f] : 0,
                                     mine ? nd.rp[f + 1] : 0, f,
-                                    [&](int x, int) {
+                                    [&](int x, int, int) {
                                       const int32_t dx = st[x];
                                       if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
                                     });
                  });
-  __syncthreads();
-  int cnt = 0;
-  for (int v = threadIdx.x; v < n; v += blockDim.x) {
-    const int32_t d = st[v];
-    if (d >= 0 && (d & kFlag)) {
-      st[v] = kSent;
-      ++cnt;
-    }
-  }
   cnt = wave_sum(cnt);
   if (lane_id() == 0 && cnt) atomicAdd(&st[n], cnt);
   __syncthreads();
@@ -184,7 +188,7 @@ __device__ void decide_degree_one(const Node nd, Ctrl& c, int epoch) {
                    const bool mine = lane_id() < count;
                    wave_expand_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[cv] : 0,
                                     mine ? nd.rp[cv + 1] : 0, cv,
-                                    [&](int u, int v) {
+                                    [&](int u, int v, int) {
                                       const int32_t du = st[u];
                                       if (du < 0) return;  // not the live neighbour of v
                                       if ((du & kDegMask) != 1 || u < v) {
@@ -513,9 +517,9 @@ __device__ bool try_enqueue(const Params& p, const Node nd, Ctrl& c, int pending
 
 // ---- kernels ---------------------------------------------------------------------------------
 
-// Zero the control lines and the result block, mark every worklist slot free, and set up the
-// per-instance state: nothing rejected yet, one outstanding sub-tree (the root) each. Every
-// instance's root is handed out by the root ticket counter, so the worklist starts empty.
+// Zero the control lines and the result block and mark every worklist slot free (the host
+// uploads the fresh per-instance state with the instance table). Every instance's root is
+// handed out by the root ticket counter, so the worklist starts empty.
 __global__ void init_kernel(Params p, DevResult* res) {
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int gsize = gridDim.x * blockDim.x;
@@ -531,14 +535,6 @@ __global__ void init_kernel(Params p, DevResult* res) {
     }
   }
   for (uint32_t i = gtid; i < p.q_cap; i += gsize) p.seq[i] = 0u;
-  for (int j = gtid; j < p.num_inst; j += gsize) {
-    InstState s{};
-    s.err_row = kNoRow;
-    s.best = 0x7FFFFFFF;
-    s.greedy = -1;
-    p.ist[j] = s;
-    p.work[j] = 1;
-  }
 }
 
 // Check every graph of the launch (simple undirected, §II-A). Index i < vertices checks row
@@ -910,50 +906,48 @@ __device__ void add_grouped(int32_t* dst, int32_t x) {
 }
 
 // After the traversal (256-thread blocks, any grid): check each recorded cover edge by edge
-// (one thread per CSR entry) and count its vertices (one thread per vertex); clear the cover
-// output of instances without an answer (rejected, out of budget, PVC no); gather the
-// per-workgroup statistics.
+// and count its vertices. One wavefront per 64 consecutive vertices of the launch: a vertex in
+// the cover covers its whole row, so only the rows of vertices outside it are walked (as one
+// list, one lane per entry), and each entry of such a row must lead into the cover; an
+// uncovered edge is counted from each end. Clear the cover output of instances without an
+// answer (rejected, out of budget, PVC no); gather the per-workgroup statistics. Packed entry
+// offsets must fit in int32.
 __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertices,
                                                        int64_t entries, DevResult* res) {
   __shared__ int64_t buf[256];
-  const int64_t total = vertices > entries ? vertices : entries;
-  const int64_t gsize = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t base = static_cast<int64_t>(blockIdx.x) * blockDim.x; base < total;
-       base += gsize) {
-    const int64_t i = base + threadIdx.x;
+  __shared__ int32_t heads[4 * 64];
+  (void)entries;
+  const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
+  for (int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id();
+       w * 64 < vertices; w += waves) {
+    const int64_t i = w * 64 + lane_id();
     int32_t* ones_dst = nullptr;
     int32_t one = 0;
+    int beg = 0, end = 0, j = 0;
     if (i < vertices) {
-      const int j = instance_of_vertex(p, i);
+      j = instance_of_vertex(p, i);
       const Instance in = p.inst[j];
       const InstState is = p.ist[j];
       const bool answer = is.err_row == kNoRow && !(is.state & kInstOutOfBudget) &&
                           (!p.pvc || (is.state & kInstFound));
       uint8_t* cov = p.covers + in.vtx_off;
       const int v = static_cast<int>(i - in.vtx_first);
-      if (answer) one = cov[v] != 0;
-      else cov[v] = 0;
+      if (answer) {
+        one = cov[v] != 0;
+        if (!one) {
+          const int32_t* rp = p.rp_all + in.rp_off;
+          beg = static_cast<int>(in.ci_off) + rp[v];
+          end = static_cast<int>(in.ci_off) + rp[v + 1];
+        }
+      } else {
+        cov[v] = 0;
+      }
       ones_dst = &p.ist[j].cover_count;
     }
     add_grouped(ones_dst, one);
-    int32_t* bad_dst = nullptr;
-    int32_t bad = 0;
-    if (i < entries) {
-      const int j = instance_of_entry(p, i);
-      const Instance in = p.inst[j];
-      const InstState is = p.ist[j];
-      const bool answer = is.err_row == kNoRow && !(is.state & kInstOutOfBudget) &&
-                          (!p.pvc || (is.state & kInstFound));
-      if (answer) {
-        const int32_t* rp = p.rp_all + in.rp_off;
-        const uint8_t* cov = p.covers + in.vtx_off;
-        const int e = static_cast<int>(i - in.ent_first);
-        const int v = owner_row(rp, in.n, e);
-        bad = cov[v] == 0 && cov[p.ci_all[in.ci_off + e]] == 0;
-      }
-      bad_dst = &p.ist[j].uncovered;
-    }
-    add_grouped(bad_dst, bad);
+    wave_expand_rows(p.ci_all, heads + 64 * wave_id(), beg, end, j, [&](int u, int jj, int) {
+      if (p.covers[p.inst[jj].vtx_off + u] == 0) atomicAdd(&p.ist[jj].uncovered, 1);
+    });
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     res->aborted = *ctr_i32(p, kAbort);
@@ -1060,8 +1054,7 @@ static int grid_for(int64_t items, int threads, int cap) {
 }
 
 hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream) {
-  const int64_t items = p.num_inst > static_cast<int64_t>(p.q_cap) ? p.num_inst : p.q_cap;
-  hipLaunchKernelGGL(init_kernel, dim3(grid_for(items, 256, 1024)), dim3(256), 0, stream, p, res);
+  hipLaunchKernelGGL(init_kernel, dim3(grid_for(p.q_cap, 256, 1024)), dim3(256), 0, stream, p, res);
   return hipGetLastError();
 }
 
@@ -1102,7 +1095,7 @@ hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size
 
 hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, DevResult* res,
                            hipStream_t stream) {
-  int64_t items = vertices > entries ? vertices : entries;
+  int64_t items = vertices;
   if (p.num_wg > items) items = p.num_wg;
   hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(items, 256, 1024)), dim3(256), 0, stream, p,
                      vertices, entries, res);

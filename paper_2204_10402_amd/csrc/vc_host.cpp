@@ -34,17 +34,15 @@ struct vc_ctx {
   bool own_stream = false;
   hipDeviceProp_t prop{};
   size_t lds_limit_set = 0;
-  DevBuf rp, ci, inst, ist, iwork, payload, seq, ctr, stacks, covers, wg_stats, result, scratch,
-      bits;
+  // meta: the instance table, per-instance state, work counters and result blocks of a call,
+  // mirrored in pinned host memory so that each call makes one copy in and one copy out
+  DevBuf rp, ci, meta, payload, seq, ctr, stacks, covers, wg_stats, scratch, bits;
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
   std::vector<hipEvent_t> ev;  // two per launch group
   std::string last_error;
   // occupancy-API answers: (kernel family, pvc, profiled, workgroup size, words, LDS bytes)
   std::map<std::tuple<int, int, int, int, int, size_t>, int> occupancy;
-  // host staging, kept across calls
-  std::vector<vc::Instance> h_inst;
-  std::vector<vc::InstState> h_ist;
-  std::vector<vc::DevResult> h_res;
-  std::vector<uint8_t> h_cover;
 };
 
 namespace {
@@ -88,6 +86,56 @@ int ensure(vc_ctx* ctx, DevBuf& b, size_t bytes) {
   if (e != hipSuccess) return hip_fail(ctx, e, "hipMalloc");
   b.bytes = bytes;
   return VC_OK;
+}
+
+// Grow-only pinned host buffer (the mirror of the meta buffer).
+int ensure_pinned(vc_ctx* ctx, size_t bytes) {
+  if (ctx->pinned_bytes >= bytes) return VC_OK;
+  if (ctx->pinned) {
+    hipError_t e = hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipHostFree");
+  }
+  hipError_t e = hipHostMalloc(&ctx->pinned, bytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    ctx->pinned = nullptr;
+    return hip_fail(ctx, e, "hipHostMalloc");
+  }
+  ctx->pinned_bytes = bytes;
+  return VC_OK;
+}
+
+// Byte offsets of the meta regions: [Instance m | InstState m | work m | DevResult ng |
+// greedy maxima ng] in device memory and its pinned mirror; the mirror also holds the host
+// cover staging after them.
+struct MetaLayout {
+  size_t inst = 0, ist = 0, work = 0, res = 0, gmax = 0, dev_end = 0, cover = 0, host_end = 0;
+};
+
+MetaLayout meta_layout(int32_t m, int32_t ng, int64_t cover_bytes) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  MetaLayout L;
+  L.ist = al(static_cast<size_t>(m) * sizeof(vc::Instance));
+  L.work = L.ist + al(static_cast<size_t>(m) * sizeof(vc::InstState));
+  L.res = L.work + al(static_cast<size_t>(m) * sizeof(int32_t));
+  L.gmax = L.res + al(static_cast<size_t>(ng) * sizeof(vc::DevResult));
+  L.dev_end = L.gmax + al(static_cast<size_t>(ng) * sizeof(int32_t));
+  L.cover = L.dev_end;
+  L.host_end = L.cover + al(static_cast<size_t>(cover_bytes));
+  return L;
+}
+
+// Fresh per-instance state: nothing rejected yet, no cover, one outstanding sub-tree (the root).
+void init_state(vc::InstState* is, int32_t* work, int32_t m) {
+  for (int32_t j = 0; j < m; ++j) {
+    vc::InstState s{};
+    s.err_row = vc::kNoRow;
+    s.best = 0x7FFFFFFF;
+    s.greedy = -1;
+    is[j] = s;
+    work[j] = 1;
+  }
 }
 
 int ensure_events(vc_ctx* ctx, size_t count) {
@@ -326,6 +374,7 @@ int check_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, int64_t* total_rp, int6
   }
   if (rp > 0x7FFFFFFF || nv > 0x7FFFFFFF)
     return fail(ctx, VC_ERR_INVALID_ARG, "batch has more than 2^31 row pointers");
+  if (ne > 0x7FFFFFFF) return fail(ctx, VC_ERR_INVALID_ARG, "batch has more than 2^31 CSR entries");
   if (b.count > vc::kMaxLaunchInstances)
     return fail(ctx, VC_ERR_INVALID_ARG, "batch has more than 2^22 graphs");
   if (b.count > 0 && !b.rp) return fail(ctx, VC_ERR_INVALID_ARG, "row_ptr is NULL");
@@ -380,18 +429,33 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     }
   }
   const int32_t m = static_cast<int32_t>(order.size());
-  ctx->h_inst.assign(m, Instance{});
+  // groups first (the layout needs their number), then the table straight into pinned memory
   std::vector<Group> groups;
-  for (int32_t s = 0; s < m; ++s) {
-    const int32_t i = order[s];
-    if (groups.empty() || groups.back().words != words[i]) {
+  for (int32_t s = 0; s < m; ++s)
+    if (groups.empty() || groups.back().words != words[order[s]]) {
       Group g;
-      g.words = words[i];
+      g.words = words[order[s]];
       g.begin = s;
       groups.push_back(g);
     }
-    Group& g = groups.back();
-    Instance& in = ctx->h_inst[s];
+  const int32_t ng = static_cast<int32_t>(groups.size());
+  const MetaLayout L = meta_layout(m, ng, out.cover_host ? total_n : 0);
+  if ((rc = ensure(ctx, ctx->meta, L.dev_end))) return rc;
+  if ((rc = ensure_pinned(ctx, L.host_end))) return rc;
+  char* host = static_cast<char*>(ctx->pinned);
+  char* dev = static_cast<char*>(ctx->meta.ptr);
+  Instance* h_inst = reinterpret_cast<Instance*>(host + L.inst);
+  InstState* h_ist = reinterpret_cast<InstState*>(host + L.ist);
+  DevResult* h_res = reinterpret_cast<DevResult*>(host + L.res);
+  int32_t* h_gmax = reinterpret_cast<int32_t*>(host + L.gmax);
+  init_state(h_ist, reinterpret_cast<int32_t*>(host + L.work), m);
+  int32_t gcur = -1;
+  for (int32_t s = 0; s < m; ++s) {
+    const int32_t i = order[s];
+    if (gcur < 0 || groups[gcur].words != words[i]) ++gcur;
+    Group& g = groups[gcur];
+    Instance& in = h_inst[s];
+    in = Instance{};
     in.n = b.n[i];
     in.nnz = b.nnz[i];
     in.rp_off = static_cast<int32_t>(rp_off[i]);
@@ -406,19 +470,13 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     g.vertices += in.n;
     g.entries += in.nnz;
   }
-  const int32_t ng = static_cast<int32_t>(groups.size());
   hipStream_t st = ctx->stream;
 
   if (m > 0) {
-    if ((rc = ensure(ctx, ctx->inst, static_cast<size_t>(m) * sizeof(Instance)))) return rc;
-    if ((rc = ensure(ctx, ctx->ist, static_cast<size_t>(m) * sizeof(InstState)))) return rc;
-    if ((rc = ensure(ctx, ctx->iwork, static_cast<size_t>(m) * sizeof(int32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->result, static_cast<size_t>(ng) * sizeof(DevResult)))) return rc;
-    if ((rc = ensure(ctx, ctx->scratch, static_cast<size_t>(ng) * sizeof(int32_t)))) return rc;
     if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
     if ((rc = ensure_events(ctx, 2 * static_cast<size_t>(ng) + 2))) return rc;
-    VC_HIP(ctx, hipMemcpyAsync(ctx->inst.ptr, ctx->h_inst.data(), static_cast<size_t>(m) * sizeof(Instance),
-                               hipMemcpyHostToDevice, st));
+    // one copy in: instance table, fresh per-instance state and work counters
+    VC_HIP(ctx, hipMemcpyAsync(dev, host, L.res, hipMemcpyHostToDevice, st));
   }
   uint8_t* covers = out.cover_dev;
   if (!covers && total_n > 0) {
@@ -427,10 +485,11 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   }
 
   // one launch per kernel family, in turn on the context stream
-  const Instance* d_inst = static_cast<const Instance*>(ctx->inst.ptr);
-  InstState* d_ist = static_cast<InstState*>(ctx->ist.ptr);
-  DevResult* d_res = static_cast<DevResult*>(ctx->result.ptr);
-  int32_t* d_greedy = static_cast<int32_t*>(ctx->scratch.ptr);
+  const Instance* d_inst = reinterpret_cast<const Instance*>(dev + L.inst);
+  InstState* d_ist = reinterpret_cast<InstState*>(dev + L.ist);
+  int32_t* d_work = reinterpret_cast<int32_t*>(dev + L.work);
+  DevResult* d_res = reinterpret_cast<DevResult*>(dev + L.res);
+  int32_t* d_greedy = reinterpret_cast<int32_t*>(dev + L.gmax);
   std::vector<Params> params(ng);
   float greedy_ms = 0.f;
   for (int32_t gi = 0; gi < ng; ++gi) {
@@ -452,7 +511,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.rules = rules_from_flags(flags);
     p.inst = d_inst + g.begin;
     p.ist = d_ist + g.begin;
-    p.work = static_cast<int32_t*>(ctx->iwork.ptr) + g.begin;
+    p.work = d_work + g.begin;
     p.rp_all = b.rp;
     p.ci_all = b.ci;
     p.payload = static_cast<int32_t*>(ctx->payload.ptr);
@@ -482,9 +541,9 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
       else VC_HIP(ctx, vc::launch_greedy(p, gws, st));
       VC_HIP(ctx, hipEventRecord(e1, st));
       VC_HIP(ctx, vc::launch_max_greedy(p, d_greedy + gi, st));
-      int32_t gmax = 0;
-      VC_HIP(ctx, hipMemcpyAsync(&gmax, d_greedy + gi, sizeof gmax, hipMemcpyDeviceToHost, st));
+      VC_HIP(ctx, hipMemcpyAsync(h_gmax + gi, d_greedy + gi, sizeof(int32_t), hipMemcpyDeviceToHost, st));
       VC_HIP(ctx, hipStreamSynchronize(st));
+      const int32_t gmax = h_gmax[gi];
       float ms = 0.f;
       VC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
       greedy_ms += ms;
@@ -504,19 +563,12 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     VC_HIP(ctx, vc::launch_finalize(p, g.vertices, g.entries, dres, st));
   }
 
-  ctx->h_ist.resize(m);
-  ctx->h_res.resize(ng);
-  if (m > 0) {
-    VC_HIP(ctx, hipMemcpyAsync(ctx->h_ist.data(), d_ist, static_cast<size_t>(m) * sizeof(InstState),
-                               hipMemcpyDeviceToHost, st));
-    VC_HIP(ctx, hipMemcpyAsync(ctx->h_res.data(), d_res, static_cast<size_t>(ng) * sizeof(DevResult),
-                               hipMemcpyDeviceToHost, st));
-  }
-  if (out.cover_host && total_n > 0) {
-    ctx->h_cover.resize(static_cast<size_t>(total_n));
-    VC_HIP(ctx, hipMemcpyAsync(ctx->h_cover.data(), covers, static_cast<size_t>(total_n),
-                               hipMemcpyDeviceToHost, st));
-  }
+  // one copy out: per-instance state, work counters and result blocks
+  if (m > 0)
+    VC_HIP(ctx, hipMemcpyAsync(host + L.ist, dev + L.ist, L.gmax - L.ist, hipMemcpyDeviceToHost, st));
+  uint8_t* h_cover = reinterpret_cast<uint8_t*>(host + L.cover);
+  if (out.cover_host && total_n > 0)
+    VC_HIP(ctx, hipMemcpyAsync(h_cover, covers, static_cast<size_t>(total_n), hipMemcpyDeviceToHost, st));
   VC_HIP(ctx, hipStreamSynchronize(st));
   double kernel_ms = 0.0;
   for (int32_t gi = 0; gi < ng; ++gi) {
@@ -526,7 +578,8 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   }
 
   // launch-wide failures end the whole call
-  for (const DevResult& r : ctx->h_res) {
+  for (int32_t gi = 0; gi < ng; ++gi) {
+    const DevResult& r = h_res[gi];
     if (r.error)
       return fail(ctx, VC_ERR_INTERNAL,
                   "device invariant failed (code " + std::to_string(r.error) +
@@ -540,7 +593,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   std::string bad_msg;
   for (int32_t s = 0; s < m; ++s) {
     const int32_t i = order[s];
-    const InstState& is = ctx->h_ist[s];
+    const InstState& is = h_ist[s];
     nodes[i] = is.nodes;
     if (is.err_row != vc::kNoRow) {
       status[i] = VC_ERR_INVALID_GRAPH;
@@ -584,13 +637,13 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     if (out.nodes) out.nodes[i] = nodes[i];
   }
   if (out.cover_host && total_n > 0)
-    std::memcpy(out.cover_host, ctx->h_cover.data(), static_cast<size_t>(total_n));
+    std::memcpy(out.cover_host, h_cover, static_cast<size_t>(total_n));
   if (out.stats) {
     vc_stats* sp = out.stats;
     std::memset(sp, 0, sizeof *sp);
     sp->wg_nodes_min = ng ? INT64_MAX : 0;
     for (int32_t gi = 0; gi < ng; ++gi) {
-      const DevResult& r = ctx->h_res[gi];
+      const DevResult& r = h_res[gi];
       const Group& g = groups[gi];
       sp->nodes += r.nodes;
       sp->wg_nodes_max = std::max(sp->wg_nodes_max, r.wg_nodes_max);
@@ -610,7 +663,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
       sp->node_bytes = std::max(sp->node_bytes, g.words ? 8 * g.words + 8 : 4 * (g.n_max + 3));
       for (int a = 0; a < vc::kNumActivities; ++a) sp->cycles[a] += r.cycles[a];
     }
-    sp->greedy_size = (!pvc && out.single && m == 1) ? ctx->h_ist[0].greedy : -1;
+    sp->greedy_size = (!pvc && out.single && m == 1) ? h_ist[0].greedy : -1;
     sp->kernel_ms = kernel_ms;
     sp->greedy_ms = greedy_ms;
     sp->total_ms = ms_since(t0);
@@ -732,10 +785,9 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   Plan pl;
   vc_options o{};
   if ((rc = plan_launch(ctx, false, g->n, words, &o, pl))) return rc;
-  if ((rc = ensure(ctx, ctx->inst, sizeof(Instance)))) return rc;
-  if ((rc = ensure(ctx, ctx->ist, sizeof(InstState)))) return rc;
-  if ((rc = ensure(ctx, ctx->iwork, sizeof(int32_t)))) return rc;
-  if ((rc = ensure(ctx, ctx->result, sizeof(DevResult)))) return rc;
+  const MetaLayout L = meta_layout(1, 1, 0);
+  if ((rc = ensure(ctx, ctx->meta, L.dev_end))) return rc;
+  if ((rc = ensure_pinned(ctx, L.host_end))) return rc;
   if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
   if ((rc = ensure(ctx, ctx->seq, sizeof(uint32_t)))) return rc;
   if (!covers) {
@@ -744,20 +796,22 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   }
   if (words && (rc = ensure(ctx, ctx->bits, static_cast<size_t>(g->n) * words * sizeof(uint64_t))))
     return rc;
-  ctx->h_inst.assign(1, Instance{});
-  Instance& in = ctx->h_inst[0];
+  char* host = static_cast<char*>(ctx->pinned);
+  char* dev = static_cast<char*>(ctx->meta.ptr);
+  Instance& in = *reinterpret_cast<Instance*>(host + L.inst);
+  in = Instance{};
   in.n = g->n;
   in.nnz = g->nnz;
-  VC_HIP(ctx, hipMemcpyAsync(ctx->inst.ptr, ctx->h_inst.data(), sizeof(Instance),
-                             hipMemcpyHostToDevice, ctx->stream));
+  init_state(reinterpret_cast<InstState*>(host + L.ist), reinterpret_cast<int32_t*>(host + L.work), 1);
+  VC_HIP(ctx, hipMemcpyAsync(dev, host, L.res, hipMemcpyHostToDevice, ctx->stream));
   p = Params{};
   p.num_inst = 1;
   p.stride = pl.stride;
   p.n_max = g->n;
   p.rules = rules;
-  p.inst = static_cast<const Instance*>(ctx->inst.ptr);
-  p.ist = static_cast<InstState*>(ctx->ist.ptr);
-  p.work = static_cast<int32_t*>(ctx->iwork.ptr);
+  p.inst = reinterpret_cast<const Instance*>(dev + L.inst);
+  p.ist = reinterpret_cast<InstState*>(dev + L.ist);
+  p.work = reinterpret_cast<int32_t*>(dev + L.work);
   p.rp_all = g->row_ptr;
   p.ci_all = g->col_idx;
   p.seq = static_cast<uint32_t*>(ctx->seq.ptr);
@@ -768,7 +822,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   p.words = words;
   p.rp_lds = pl.rp_lds;
   *wg_size = words ? 64 : static_cast<int32_t>(std::min<int64_t>(1024, round_up(g->n, 64)));
-  DevResult* dres = static_cast<DevResult*>(ctx->result.ptr);
+  DevResult* dres = reinterpret_cast<DevResult*>(dev + L.res);
   VC_HIP(ctx, vc::launch_init(p, dres, ctx->stream));
   VC_HIP(ctx, vc::launch_prepare(p, g->n, g->nnz, ctx->stream));
   return VC_OK;
@@ -826,11 +880,12 @@ int vc_destroy(vc_ctx* ctx) {
   if (!ctx) return VC_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-  DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,     &ctx->inst,     &ctx->ist,    &ctx->iwork, &ctx->payload,
-                    &ctx->seq,    &ctx->ctr,    &ctx->stacks,   &ctx->covers, &ctx->wg_stats,
-                    &ctx->result, &ctx->scratch, &ctx->bits};
+  DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,       &ctx->meta,     &ctx->payload, &ctx->seq,
+                    &ctx->ctr,    &ctx->stacks,   &ctx->covers,   &ctx->wg_stats, &ctx->scratch,
+                    &ctx->bits};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   for (hipEvent_t ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -901,9 +956,11 @@ int vc_greedy_device(vc_ctx* ctx, const vc_graph* g, int32_t* size_out, uint8_t*
   hipStream_t s = ctx->stream;
   if (p.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, s));
   else VC_HIP(ctx, vc::launch_greedy(p, ws, s));
-  InstState is{};
-  VC_HIP(ctx, hipMemcpyAsync(&is, p.ist, sizeof is, hipMemcpyDeviceToHost, s));
+  InstState* h_is =
+      reinterpret_cast<InstState*>(static_cast<char*>(ctx->pinned) + meta_layout(1, 1, 0).ist);
+  VC_HIP(ctx, hipMemcpyAsync(h_is, p.ist, sizeof(InstState), hipMemcpyDeviceToHost, s));
   VC_HIP(ctx, hipStreamSynchronize(s));
+  const InstState is = *h_is;
   if (is.err_row != vc::kNoRow) return fail(ctx, VC_ERR_INVALID_GRAPH, bad_row_message(is.err_row));
   if (cover_dev) {
     VC_HIP(ctx, hipMemcpyAsync(cover_dev, p.covers, static_cast<size_t>(g->n),
@@ -933,11 +990,13 @@ int vc_reduce_device(vc_ctx* ctx, const vc_graph* g, int32_t* deg_dev, int32_t* 
   VC_HIP(ctx, hipMemcpyAsync(sdev, s_inout, sizeof(int32_t), hipMemcpyHostToDevice, s));
   if (p.words) VC_HIP(ctx, vc::launch_bitset_reduce(p, deg_dev, sdev, bound, s));
   else VC_HIP(ctx, vc::launch_reduce(p, ws, deg_dev, sdev, bound, s));
-  InstState is{};
+  InstState* h_is =
+      reinterpret_cast<InstState*>(static_cast<char*>(ctx->pinned) + meta_layout(1, 1, 0).ist);
   int32_t s_new = 0;
-  VC_HIP(ctx, hipMemcpyAsync(&is, p.ist, sizeof is, hipMemcpyDeviceToHost, s));
+  VC_HIP(ctx, hipMemcpyAsync(h_is, p.ist, sizeof(InstState), hipMemcpyDeviceToHost, s));
   VC_HIP(ctx, hipMemcpyAsync(&s_new, sdev, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   VC_HIP(ctx, hipStreamSynchronize(s));
+  const InstState is = *h_is;
   if (is.err_row != vc::kNoRow) return fail(ctx, VC_ERR_INVALID_GRAPH, bad_row_message(is.err_row));
   *s_inout = s_new;
   return VC_OK;
