@@ -203,6 +203,9 @@ def main():
     ap.add_argument("--workload", default="planted-pvc", choices=WORKLOADS)
     ap.add_argument("--mode", default="batch", choices=["single", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="fixed launch knobs instead of VC_OPT_AUTOTUNE (the warm-up steps "
+                         "absorb the trial launches of the first call)")
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run 2 steps and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -240,13 +243,15 @@ def main():
     torch.cuda.synchronize()
     solver = vc.Solver(0, stream=torch.cuda.current_stream(dev))
 
+    opts = vc.Options(flags=0 if a.no_autotune else vc.OPT_AUTOTUNE)
+
     def run_single(record):
         for g, k, rp, ci, cover in resident:
             t = time.perf_counter()
             if kind == "pvc":
-                r = solver.pvc_device(rp, ci, k, cover)
+                r = solver.pvc_device(rp, ci, k, cover, options=opts)
             else:
-                r = solver.mvc_device(rp, ci, cover)
+                r = solver.mvc_device(rp, ci, cover, options=opts)
             dt = time.perf_counter() - t
             if record is not None:
                 record.append(([g], r.stats, dt, 1))
@@ -254,9 +259,11 @@ def main():
     def run_batch(record):
         t = time.perf_counter()
         if kind == "pvc":
-            r = solver.pvc_batch_device(n_arr, nnz_arr, rp_all_d, ci_all_d, ks, cover_all_d)
+            r = solver.pvc_batch_device(n_arr, nnz_arr, rp_all_d, ci_all_d, ks, cover_all_d,
+                                        options=opts)
         else:
-            r = solver.mvc_batch_device(n_arr, nnz_arr, rp_all_d, ci_all_d, cover_all_d)
+            r = solver.mvc_batch_device(n_arr, nnz_arr, rp_all_d, ci_all_d, cover_all_d,
+                                        options=opts)
         dt = time.perf_counter() - t
         if not (r.status == 0).all():
             raise SystemExit("a batched instance failed: status " + str(np.unique(r.status)))
@@ -310,6 +317,7 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": a.workload, "mode": mode, "instances": len(insts), **cfg,
+                   "autotune": not a.no_autotune,
                    "wg_size": last["wg_size"], "num_wg": last["num_wg"],
                    "wl_capacity": last["wl_capacity"], "wl_threshold": last["wl_threshold"]},
         "nodes_per_step": nodes // a.steps,
@@ -327,6 +335,8 @@ def main():
     }
     # one untimed pass of single calls: per-instance time-to-solve, and the plain form's rate
     log("one pass of single calls (time-to-solve per instance)")
+    if not a.no_autotune:
+        run_single(None)  # single calls are their own size class: tune them untimed first
     torch.cuda.synchronize()
     single = []
     t = time.perf_counter()

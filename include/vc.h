@@ -66,6 +66,12 @@ extern "C" {
 #define VC_OPT_BITSETS 0x40       /* use the bitset kernels (the default up to 256 vertices;
                                      VC_ERR_INVALID_ARG above): a node is the set of live
                                      vertices, held in registers */
+#define VC_OPT_AUTOTUNE 0x80      /* pick workgroup size, grid size and donation threshold of
+                                     each launch by timing trial launches the first time this
+                                     context sees its kernel family, problem, options and size
+                                     class (n_max and number of graphs, by powers of two), and
+                                     reuse the choice afterwards; ignored when any launch knob
+                                     of vc_options is set */
 
 typedef struct vc_ctx vc_ctx;
 

@@ -28,6 +28,7 @@ OPT_NO_EDGE_PRUNE = 0x8
 OPT_PROFILE = 0x10
 OPT_DEGREE_ARRAYS = 0x20
 OPT_BITSETS = 0x40
+OPT_AUTOTUNE = 0x80
 ACTIVITIES = ("acquire", "reduce", "branch", "donate", "other", "total",
               "reduce_deg1", "reduce_tri", "reduce_high", "reduce_apply")
 

@@ -660,7 +660,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     w.max_depth = max_depth;
     w.instances = static_cast<int32_t>(insts);
     for (int a = 0; a < kNumActivities; ++a) w.cycles[a] = static_cast<int64_t>(clk.cycles[a]);
-    p.wg_stats[wg] = w;
+    publish_wg_stats(p, wg, w);
   }
 }
 

@@ -884,7 +884,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     w.max_depth = max_depth;
     w.instances = static_cast<int32_t>(insts);
     for (int a = 0; a < kNumActivities; ++a) w.cycles[a] = static_cast<int64_t>(clk.cycles[a]);
-    p.wg_stats[wg] = w;
+    publish_wg_stats(p, wg, w);
   }
 }
 
@@ -910,11 +910,10 @@ __device__ void add_grouped(int32_t* dst, int32_t x) {
 // the cover covers its whole row, so only the rows of vertices outside it are walked (as one
 // list, one lane per entry), and each entry of such a row must lead into the cover; an
 // uncovered edge is counted from each end. Clear the cover output of instances without an
-// answer (rejected, out of budget, PVC no); gather the per-workgroup statistics. Packed entry
-// offsets must fit in int32.
+// answer (rejected, out of budget, PVC no). (The traversal's workgroups add their statistics
+// to the result block themselves.) Packed entry offsets must fit in int32.
 __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertices,
                                                        int64_t entries, DevResult* res) {
-  __shared__ int64_t buf[256];
   __shared__ int32_t heads[4 * 64];
   (void)entries;
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
@@ -953,51 +952,6 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertice
     res->aborted = *ctr_i32(p, kAbort);
     res->error = *ctr_i32(p, kError);
     res->q_max_count = *ctr_i32(p, kQMaxCount);
-  }
-  // per-workgroup statistics: only the blocks that cover workgroup slots
-  if (static_cast<int>(blockIdx.x) * static_cast<int>(blockDim.x) >= p.num_wg) return;
-  int64_t nodes = 0, pushes = 0, pops = 0, enq = 0, deq = 0, insts = 0, mx = 0, mn = INT64_MAX,
-          depth = 0;
-  int64_t cyc[kNumActivities] = {};
-  for (int w = blockIdx.x * blockDim.x + threadIdx.x; w < p.num_wg; w += gridDim.x * blockDim.x) {
-    const WgStats s = p.wg_stats[w];
-    nodes += s.nodes;
-    pushes += s.pushes;
-    pops += s.pops;
-    enq += s.enqueues;
-    deq += s.dequeues;
-    insts += s.instances;
-    mx = s.nodes > mx ? s.nodes : mx;
-    mn = s.nodes < mn ? s.nodes : mn;
-    depth = s.max_depth > depth ? s.max_depth : depth;
-    for (int a = 0; a < kNumActivities; ++a) cyc[a] += s.cycles[a];
-  }
-  auto add = [](int64_t x, int64_t y) { return x + y; };
-  auto hi = [](int64_t x, int64_t y) { return x > y ? x : y; };
-  auto lo = [](int64_t x, int64_t y) { return x < y ? x : y; };
-  nodes = block_reduce_256(nodes, buf, add);
-  pushes = block_reduce_256(pushes, buf, add);
-  pops = block_reduce_256(pops, buf, add);
-  enq = block_reduce_256(enq, buf, add);
-  deq = block_reduce_256(deq, buf, add);
-  insts = block_reduce_256(insts, buf, add);
-  mx = block_reduce_256(mx, buf, hi);
-  mn = block_reduce_256(mn, buf, lo);
-  depth = block_reduce_256(depth, buf, hi);
-  for (int a = 0; a < kNumActivities; ++a) cyc[a] = block_reduce_256(cyc[a], buf, add);
-  if (threadIdx.x == 0) {
-    using ull = unsigned long long;
-    if (nodes) atomicAdd(reinterpret_cast<ull*>(&res->nodes), static_cast<ull>(nodes));
-    if (pushes) atomicAdd(reinterpret_cast<ull*>(&res->pushes), static_cast<ull>(pushes));
-    if (pops) atomicAdd(reinterpret_cast<ull*>(&res->pops), static_cast<ull>(pops));
-    if (enq) atomicAdd(reinterpret_cast<ull*>(&res->enqueues), static_cast<ull>(enq));
-    if (deq) atomicAdd(reinterpret_cast<ull*>(&res->dequeues), static_cast<ull>(deq));
-    if (insts) atomicAdd(reinterpret_cast<ull*>(&res->instances), static_cast<ull>(insts));
-    atomicMax(reinterpret_cast<ull*>(&res->wg_nodes_max), static_cast<ull>(mx));
-    atomicMin(reinterpret_cast<ull*>(&res->wg_nodes_min), static_cast<ull>(mn));
-    atomicMax(&res->max_depth, static_cast<int32_t>(depth));
-    for (int a = 0; a < kNumActivities; ++a)
-      if (cyc[a]) atomicAdd(reinterpret_cast<ull*>(&res->cycles[a]), static_cast<ull>(cyc[a]));
   }
 }
 
@@ -1095,8 +1049,7 @@ hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size
 
 hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, DevResult* res,
                            hipStream_t stream) {
-  int64_t items = vertices;
-  if (p.num_wg > items) items = p.num_wg;
+  const int64_t items = vertices;
   hipLaunchKernelGGL(finalize_kernel, dim3(grid_for(items, 256, 1024)), dim3(256), 0, stream, p,
                      vertices, entries, res);
   return hipGetLastError();

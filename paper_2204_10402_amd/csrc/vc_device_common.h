@@ -347,18 +347,29 @@ struct ActivityClock {
   }
 };
 
-// Sum / max / min over a 256-thread workgroup through shared memory.
-template <typename Op>
-__device__ int64_t block_reduce_256(int64_t v, int64_t* buf, Op op) {
-  buf[threadIdx.x] = v;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (static_cast<int>(threadIdx.x) < h) buf[threadIdx.x] = op(buf[threadIdx.x], buf[threadIdx.x + h]);
-    __syncthreads();
-  }
-  const int64_t r = buf[0];
-  __syncthreads();
-  return r;
+// Thread 0 of an exiting traversal workgroup: record its statistics and, if it took any work,
+// add them into the launch's result block (sums, largest and smallest node count, deepest
+// stack, one more active workgroup). Idle workgroups add nothing, so a short launch with many
+// idle workgroups does not queue thousands of atomics on one line.
+__device__ inline void publish_wg_stats(const Params& p, int wg, const WgStats& w) {
+  using ull = unsigned long long;
+  p.wg_stats[wg] = w;
+  if (w.instances == 0 && w.nodes == 0) return;
+  DevResult* r = p.res;
+  atomicAdd(&r->active_wgs, 1);
+  auto add = [](int64_t* dst, int64_t x) {
+    if (x) atomicAdd(reinterpret_cast<ull*>(dst), static_cast<ull>(x));
+  };
+  add(&r->nodes, w.nodes);
+  add(&r->pushes, w.pushes);
+  add(&r->pops, w.pops);
+  add(&r->enqueues, w.enqueues);
+  add(&r->dequeues, w.dequeues);
+  add(&r->instances, w.instances);
+  for (int a = 0; a < kNumActivities; ++a) add(&r->cycles[a], w.cycles[a]);
+  atomicMax(reinterpret_cast<ull*>(&r->wg_nodes_max), static_cast<ull>(w.nodes));
+  atomicMin(reinterpret_cast<ull*>(&r->wg_nodes_min), static_cast<ull>(w.nodes));
+  if (w.max_depth) atomicMax(&r->max_depth, w.max_depth);
 }
 
 }  // namespace vc

@@ -43,6 +43,8 @@ struct vc_ctx {
   std::string last_error;
   // occupancy-API answers: (kernel family, pvc, profiled, workgroup size, words, LDS bytes)
   std::map<std::tuple<int, int, int, int, int, size_t>, int> occupancy;
+  // autotuner choices: (bitset words, pvc, flags, log2 n_max, log2 instances) -> knobs
+  std::map<std::tuple<int, int, int, int, int>, std::tuple<int, int, int>> tuned;
 };
 
 namespace {
@@ -174,7 +176,7 @@ int check_options(vc_ctx* ctx, const vc_options* o) {
     return fail(ctx, VC_ERR_INVALID_ARG, "negative option value");
   const int32_t known = VC_OPT_NO_DEGREE_ONE | VC_OPT_NO_TRIANGLE | VC_OPT_NO_HIGH_DEGREE |
                         VC_OPT_NO_EDGE_PRUNE | VC_OPT_PROFILE | VC_OPT_DEGREE_ARRAYS |
-                        VC_OPT_BITSETS;
+                        VC_OPT_BITSETS | VC_OPT_AUTOTUNE;
   if (o->flags & ~known) return fail(ctx, VC_ERR_INVALID_ARG, "unknown option flag");
   if ((o->flags & VC_OPT_DEGREE_ARRAYS) && (o->flags & VC_OPT_BITSETS))
     return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_DEGREE_ARRAYS and VC_OPT_BITSETS exclude each other");
@@ -492,17 +494,25 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   int32_t* d_greedy = reinterpret_cast<int32_t*>(dev + L.gmax);
   std::vector<Params> params(ng);
   float greedy_ms = 0.f;
-  for (int32_t gi = 0; gi < ng; ++gi) {
+  const int cus = ctx->prop.multiProcessorCount;
+
+  // Everything of one launch group up to (and, if `final`, including) the cover check, with
+  // the knobs of `go` and, if thr_div > 0, a donation threshold of num_wg / thr_div.
+  auto run_group = [&](int32_t gi, const vc_options* go, int thr_div, bool final) -> int {
     Group& g = groups[gi];
-    if ((rc = plan_launch(ctx, pvc, g.n_max, g.words, o, g.pl))) return rc;
+    int rc2;
+    if ((rc2 = plan_launch(ctx, pvc, g.n_max, g.words, go, g.pl))) return rc2;
     Plan& pl = g.pl;
+    if (thr_div > 0)
+      pl.threshold = static_cast<uint32_t>(std::min<int64_t>(
+          std::max<int64_t>(16, pl.num_wg / thr_div), static_cast<int64_t>(pl.cap) - 2 * pl.num_wg));
     const size_t stride_b = static_cast<size_t>(pl.stride) * sizeof(int32_t);
-    if ((rc = ensure(ctx, ctx->payload, static_cast<size_t>(pl.cap) * stride_b))) return rc;
-    if ((rc = ensure(ctx, ctx->seq, static_cast<size_t>(pl.cap) * sizeof(uint32_t)))) return rc;
-    if ((rc = ensure(ctx, ctx->wg_stats, static_cast<size_t>(pl.num_wg) * sizeof(vc::WgStats)))) return rc;
+    if ((rc2 = ensure(ctx, ctx->payload, static_cast<size_t>(pl.cap) * stride_b))) return rc2;
+    if ((rc2 = ensure(ctx, ctx->seq, static_cast<size_t>(pl.cap) * sizeof(uint32_t)))) return rc2;
+    if ((rc2 = ensure(ctx, ctx->wg_stats, static_cast<size_t>(pl.num_wg) * sizeof(vc::WgStats)))) return rc2;
     if (g.words &&
-        (rc = ensure(ctx, ctx->bits, static_cast<size_t>(g.vertices) * g.words * sizeof(uint64_t))))
-      return rc;
+        (rc2 = ensure(ctx, ctx->bits, static_cast<size_t>(g.vertices) * g.words * sizeof(uint64_t))))
+      return rc2;
     Params& p = params[gi];
     p = Params{};
     p.num_inst = g.end - g.begin;
@@ -530,6 +540,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.rp_lds = pl.rp_lds;
     p.pvc = pvc ? 1 : 0;
     DevResult* dres = d_res + gi;
+    p.res = dres;
 
     VC_HIP(ctx, vc::launch_init(p, dres, st));
     VC_HIP(ctx, vc::launch_prepare(p, g.vertices, g.entries, st));
@@ -546,13 +557,13 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
       const int32_t gmax = h_gmax[gi];
       float ms = 0.f;
       VC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-      greedy_ms += ms;
+      if (final) greedy_ms += ms;
       // bound = best - 1: a path branches at most best - 1 times (each branching adds to s)
       g.depth_cap = std::max(gmax, 1);
     } else {
       g.depth_cap = g.k_max + 1;
     }
-    if ((rc = size_stacks(ctx, pl, g.depth_cap))) return rc;
+    if ((rc2 = size_stacks(ctx, pl, g.depth_cap))) return rc2;
     p.stacks = static_cast<int32_t*>(ctx->stacks.ptr);
     p.depth_cap = g.depth_cap;
     p.num_wg = pl.num_wg;
@@ -560,7 +571,73 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     if (g.words) VC_HIP(ctx, vc::launch_bitset_traverse(pvc, prof, p, st));
     else VC_HIP(ctx, vc::launch_traverse(pvc, prof, p, pl.wg_size, st));
     VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi + 1], st));
-    VC_HIP(ctx, vc::launch_finalize(p, g.vertices, g.entries, dres, st));
+    if (final) VC_HIP(ctx, vc::launch_finalize(p, g.vertices, g.entries, dres, st));
+    return VC_OK;
+  };
+
+  // Fresh per-instance state of one group again (the pinned mirror still holds it).
+  auto reset_group = [&](int32_t gi) -> int {
+    const Group& g = groups[gi];
+    const size_t cnt = static_cast<size_t>(g.end - g.begin);
+    VC_HIP(ctx, hipMemcpyAsync(d_ist + g.begin, h_ist + g.begin, cnt * sizeof(InstState),
+                               hipMemcpyHostToDevice, st));
+    VC_HIP(ctx, hipMemcpyAsync(d_work + g.begin, reinterpret_cast<int32_t*>(host + L.work) + g.begin,
+                               cnt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    return VC_OK;
+  };
+
+  const bool explicit_knobs = o && (o->wg_size || o->num_wg || o->wl_capacity || o->wl_threshold);
+  const bool autotune = (flags & VC_OPT_AUTOTUNE) && !explicit_knobs;
+  for (int32_t gi = 0; gi < ng; ++gi) {
+    Group& g = groups[gi];
+    vc_options go = o ? *o : vc_options{};
+    int thr_div = 0;
+    if (autotune) {
+      auto lg = [](int64_t x) { int l = 0; while ((int64_t(1) << l) < x) ++l; return l; };
+      const auto key = std::make_tuple(g.words, pvc ? 1 : 0, flags & ~VC_OPT_AUTOTUNE, lg(g.n_max),
+                                       lg(g.end - g.begin));
+      auto it = ctx->tuned.find(key);
+      if (it == ctx->tuned.end()) {
+        // trial launches over a small grid; the default knobs are one of the candidates
+        std::vector<std::tuple<int, int, int>> cand;  // (wg_size, num_wg, threshold divisor)
+        cand.emplace_back(0, 0, 0);
+        if (g.words) {
+          for (int mult : {1, 2, 4, 8})
+            for (int div : {8, 2}) cand.emplace_back(0, mult * cus, div);
+        } else {
+          Plan base;
+          if ((rc = plan_launch(ctx, pvc, g.n_max, 0, &go, base))) return rc;
+          for (int ws : {base.wg_size / 2, base.wg_size, base.wg_size * 2})
+            if (ws >= 64 && ws <= 1024)
+              for (int div : {8, 1}) cand.emplace_back(ws, 0, div);
+        }
+        float best_ms = 0.f;
+        std::tuple<int, int, int> best = cand[0];
+        for (const auto& c : cand) {
+          vc_options t = go;
+          t.wg_size = std::get<0>(c);
+          t.num_wg = std::get<1>(c);
+          if ((rc = reset_group(gi))) return rc;
+          rc = run_group(gi, &t, std::get<2>(c), false);
+          if (rc == VC_ERR_INVALID_ARG || rc == VC_ERR_NO_MEMORY) continue;  // does not fit
+          if (rc) return rc;
+          VC_HIP(ctx, hipStreamSynchronize(st));
+          float ms = 0.f;
+          VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * gi], ctx->ev[2 * gi + 1]));
+          if (best_ms == 0.f || ms < best_ms) {
+            best_ms = ms;
+            best = c;
+          }
+        }
+        ctx->last_error.clear();
+        it = ctx->tuned.emplace(key, best).first;
+        if ((rc = reset_group(gi))) return rc;
+      }
+      go.wg_size = std::get<0>(it->second);
+      go.num_wg = std::get<1>(it->second);
+      thr_div = std::get<2>(it->second);
+    }
+    if ((rc = run_group(gi, &go, thr_div, true))) return rc;
   }
 
   // one copy out: per-instance state, work counters and result blocks
@@ -647,7 +724,9 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
       const Group& g = groups[gi];
       sp->nodes += r.nodes;
       sp->wg_nodes_max = std::max(sp->wg_nodes_max, r.wg_nodes_max);
-      sp->wg_nodes_min = std::min(sp->wg_nodes_min, r.wg_nodes_min);
+      // idle workgroups do not report: any idle one makes the minimum zero
+      sp->wg_nodes_min = std::min<int64_t>(
+          sp->wg_nodes_min, r.active_wgs < g.pl.num_wg ? 0 : r.wg_nodes_min);
       sp->stack_pushes += r.pushes;
       sp->stack_pops += r.pops;
       sp->wl_enqueues += r.enqueues;
@@ -823,6 +902,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   p.rp_lds = pl.rp_lds;
   *wg_size = words ? 64 : static_cast<int32_t>(std::min<int64_t>(1024, round_up(g->n, 64)));
   DevResult* dres = reinterpret_cast<DevResult*>(dev + L.res);
+  p.res = dres;
   VC_HIP(ctx, vc::launch_init(p, dres, ctx->stream));
   VC_HIP(ctx, vc::launch_prepare(p, g->n, g->nnz, ctx->stream));
   return VC_OK;

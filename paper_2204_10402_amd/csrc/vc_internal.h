@@ -105,6 +105,8 @@ struct InstState {
 // Largest batch a launch takes: a bitset node packs its instance with the pending vertex.
 constexpr int32_t kMaxLaunchInstances = 1 << 22;
 
+struct DevResult;
+
 // Everything a kernel needs; passed by value.
 struct Params {
   int32_t num_inst;     // instances of this launch (a contiguous slice of the batch)
@@ -123,6 +125,7 @@ struct Params {
   int32_t* stacks;      // per-workgroup stacks: num_wg * depth_cap * stride
   uint8_t* covers;      // packed covers, one n_i-byte cover per instance
   WgStats* wg_stats;    // num_wg
+  DevResult* res;       // launch result block: every workgroup adds its statistics at exit
   int64_t node_budget;  // per instance; 0 = none
   int64_t budget_chunk; // nodes a workgroup visits between two reports to its instance
   uint32_t q_cap;       // power of two, >= q_threshold + 2 * num_wg
@@ -154,6 +157,8 @@ struct DevResult {
   int32_t error;
   int32_t max_depth;
   int32_t q_max_count;
+  int32_t active_wgs;   // workgroups that took any work (only they add their statistics)
+  int32_t pad;
   int64_t nodes;
   int64_t wg_nodes_max;
   int64_t wg_nodes_min;

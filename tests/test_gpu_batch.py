@@ -199,3 +199,29 @@ def test_empty_batch_and_bad_arguments(solver):
     with pytest.raises(vc.VCError) as ei:
         solver.mvc_batch([G.path(300)], vc.Options(flags=vc.OPT_BITSETS))
     assert ei.value.code == vc.ERR_INVALID_ARG
+
+
+def test_autotuned_batches_keep_answers(torch_cuda, oracle_lib):
+    """With VC_OPT_AUTOTUNE the first call times trial launches and later calls reuse the
+    choice; answers and PVC-no node counts stay the oracle's either way."""
+    import paper_2204_10402_amd as vc
+    s = vc.Solver(0)  # a fresh context: nothing tuned yet
+    try:
+        gs = mixed_graphs(11, count=20)
+        o = vc.Options(flags=vc.OPT_AUTOTUNE)
+        first = s.mvc_batch(gs, o)
+        second = s.mvc_batch(gs, o)
+        for i, g in enumerate(gs):
+            want = oracle.mvc(g).size
+            assert first.size[i] == second.size[i] == want, i
+            check_cover(g, second.cover_of(i), want)
+        ks = [max(int(x) - 1, 0) for x in first.size]
+        p = s.pvc_batch(gs, ks, o)
+        for i, g in enumerate(gs):
+            if not p.yes[i]:
+                assert p.nodes[i] == oracle.pvc(g, ks[i]).nodes
+        # explicit knobs switch the tuner off
+        fixed = s.mvc_batch(gs, vc.Options(flags=vc.OPT_AUTOTUNE, num_wg=5))
+        assert fixed.stats["num_wg"] <= 5 and fixed.size.tolist() == first.size.tolist()
+    finally:
+        s.close()
