@@ -16,6 +16,11 @@ Workloads (seeded, synthetic):
   hard-mvc       MVC on random 5-regular n=120 and G(150, 0.08), seeds 0-7: 16 solves
   planted-batch  4,096 planted-cover PVC instances, n uniform in [40, 400], average degree in
                  [3, 12], |C| = 0.3n, k = |C| (even i) or |C| - 1 (odd i), master seed 0
+  serving        the stored request stream tests/golden/serving_trace.json (2,000 requests
+                 arriving as a Poisson process of 2,000 per second; n log-uniform in
+                 [50, 2000]; ER, planted-cover and 3-5-regular graphs; MVC or PVC) replayed in
+                 real time into a vc_server (continuous batching); compared with the plain form
+                 (one worker, one request per launch, in arrival order)
 Prints one JSON line on stdout; progress goes to stderr.
 
 HBM traffic of the traversal kernel (roofline "traffic"): two rocprofv3 counter runs of
@@ -71,7 +76,107 @@ def instances(workload):
     raise SystemExit(f"unknown workload {workload}")
 
 
-WORKLOADS = ["planted-pvc", "er60-mvc", "hard-mvc", "planted-batch"]
+WORKLOADS = ["planted-pvc", "er60-mvc", "hard-mvc", "planted-batch", "serving"]
+TRACE = os.path.join(ROOT, "tests", "golden", "serving_trace.json")
+
+
+def _trace_graph(args):
+    import graphs as G
+    seed, draw = args
+    return G.serving_draw(seed, draw)[1]
+
+
+def replay(vc, graphs, reqs, server_kw, label):
+    """Submit every request at its arrival time (relative to the start) from a second thread
+    while this one polls; returns the per-request results and the wall time."""
+    import threading
+    srv = vc.Server(0, **server_kw)
+    results = {}
+    tickets = [None] * len(reqs)
+    t_start = time.perf_counter()
+
+    def submitter():
+        for i, (g, r) in enumerate(zip(graphs, reqs)):
+            due = t_start + r["t_ms"] / 1000.0
+            while True:
+                left = due - time.perf_counter()
+                if left <= 0:
+                    break
+                time.sleep(min(left, 0.0005) if left > 0.0002 else 0)
+            tickets[i] = srv.submit(g, r["problem"], r.get("k", 0), cover=False)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    while len(results) < len(reqs):
+        for out in srv.poll(timeout_ms=20):
+            results[out["ticket"]] = out
+        if not th.is_alive() and len(results) < len(reqs) and time.perf_counter() - t_start > 600:
+            raise SystemExit(f"{label}: results missing")
+    th.join()
+    wall = time.perf_counter() - t_start
+    srv.close()
+    return [results[t] for t in tickets], wall
+
+
+def serving_summary(res, wall, reqs):
+    lat = sorted(r["done_ms"] - r["submit_ms"] for r in res)
+    first = min(r["submit_ms"] for r in res)
+    last = max(r["done_ms"] for r in res)
+    pct = lambda q: lat[min(len(lat) - 1, int(q * len(lat)))]
+    return {"instances_per_s": len(res) / ((last - first) / 1000.0),
+            "latency_ms": {"p50": pct(0.50), "p90": pct(0.90), "p99": pct(0.99), "max": lat[-1]},
+            "nodes": int(sum(r["nodes"] for r in res)), "wall_s": round(wall, 3),
+            "mean_batch": statistics.mean(r["batch_size"] for r in res),
+            "span_ms": last - first}
+
+
+def serving_main(a):
+    import multiprocessing as mp
+    import paper_2204_10402_amd as vc
+    with open(TRACE) as f:
+        trace = json.load(f)
+    reqs = trace["requests"]
+    log(f"regenerating {len(reqs)} graphs")
+    with mp.get_context("fork").Pool(16) as pool:
+        graphs = pool.map(_trace_graph, [(trace["master_seed"], r["draw"]) for r in reqs], chunksize=8)
+    served = dict(workers=4, max_batch=256, wg_per_request=8)
+    plain = dict(workers=1, max_batch=1, wg_per_request=8)
+    for i in range(a.warmup):
+        replay(vc, graphs[:200], reqs[:200], served, "warm-up")
+        log(f"warmup {i + 1}/{a.warmup} done")
+    runs = []
+    for i in range(a.steps):
+        res, wall = replay(vc, graphs, reqs, served, "served")
+        bad = [r for r, q in zip(res, reqs) if r["status"] != 0 or
+               (q["problem"] == "mvc" and r["size"] != q["tau"]) or
+               (q["problem"] == "pvc" and bool(r["yes"]) != q["yes"])]
+        if bad:
+            raise SystemExit(f"{len(bad)} served answers differ from the trace's oracle answers")
+        runs.append(serving_summary(res, wall, reqs))
+        log(f"step {i + 1}/{a.steps} done: {runs[-1]['instances_per_s']:.0f} requests/s")
+    log("replaying the plain form (one worker, one request per launch)")
+    pres, pwall = replay(vc, graphs, reqs, plain, "plain")
+    base = serving_summary(pres, pwall, reqs)
+    best = max(runs, key=lambda r: r["instances_per_s"])
+    med = sorted(runs, key=lambda r: r["instances_per_s"])[len(runs) // 2]
+    out = {
+        "metric": METRIC,
+        "value": med["instances_per_s"],
+        "unit": "instances/s",
+        "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": 1000.0 * statistics.mean(r["wall_s"] for r in runs),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "serving", "requests": len(reqs), "rate_per_s": trace["rate_per_s"],
+                   "oracle_node_cap": trace["node_cap"], "discard_rate": trace["discard_rate"],
+                   **served},
+        "latency_ms": med["latency_ms"],
+        "served": med, "best_step": best,
+        "plain_sequential": base,
+        "served_over_plain": med["instances_per_s"] / base["instances_per_s"],
+        "nodes_per_s": med["nodes"] / (med["span_ms"] / 1000.0),
+    }
+    print(json.dumps(out), flush=True)
 
 
 def algorithmic_bytes(gs, st):
@@ -216,6 +321,9 @@ def main():
         sys.exit(2)
     if a.summarize_traffic:
         summarize_traffic(a.workload, *a.summarize_traffic)
+        return
+    if a.workload == "serving":
+        serving_main(a)
         return
     mode = a.mode
 

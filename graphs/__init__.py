@@ -13,6 +13,7 @@ from .generators import (
     erdos_renyi,
     planted_cover,
     planted_batch,
+    serving_draw,
     random_regular,
     complete,
     cycle,
@@ -31,7 +32,7 @@ from .generators import (
 __all__ = [
     "CSRGraph", "from_edges", "edges_of", "disjoint_union",
     "erdos_renyi", "planted_cover",
-    "planted_batch", "random_regular", "complete", "cycle", "path",
+    "planted_batch", "serving_draw", "random_regular", "complete", "cycle", "path",
     "complete_bipartite", "star", "empty", "complete_multipartite", "hypercube", "grid",
     "petersen", "random_bipartite", "random_small",
 ]

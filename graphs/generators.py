@@ -224,3 +224,39 @@ def petersen() -> CSRGraph:
     u, v = zip(*(outer + spokes + inner))
     return from_edges(10, u, v, meta={"family": "petersen"})
 
+
+
+def serving_draw(master_seed: int, i: int) -> tuple[dict, CSRGraph]:
+    """Draw number ``i`` of a served request stream, from ``default_rng([master_seed, i])``:
+    n = round(exp(U[ln 50, ln 2000])); family uniform over
+      - "er": G(n, d/(n-1)) with average degree d uniform in [4, 10),
+      - "planted": planted cover |C| = floor(0.3 n), m = round(d n / 2) edges, d uniform in
+        [3, 12), 75 % C-rest (capped at what the structure allows),
+      - "regular": random d-regular, d uniform in {3, 4, 5} (n + 1 when n d is odd);
+    problem "mvc" or "pvc" with probability 1/2 each. Returns (description, graph).
+    """
+    rng = np.random.default_rng([master_seed, i])
+    n = int(round(np.exp(rng.uniform(np.log(50), np.log(2000)))))
+    family = ("er", "planted", "regular")[int(rng.integers(0, 3))]
+    problem = ("mvc", "pvc")[int(rng.integers(0, 2))]
+    sub = int(rng.integers(0, 2**31))
+    desc = {"draw": i, "family": family, "problem": problem, "sub_seed": sub}
+    if family == "er":
+        d = float(rng.uniform(4, 10))
+        g = erdos_renyi(n, d / (n - 1), sub)
+        desc.update(avg_degree=d)
+    elif family == "planted":
+        d = float(rng.uniform(3, 12))
+        c = int(0.3 * n)
+        m = int(round(d * n / 2))
+        m = min(m, int(round((c * (n - c)) / 0.75)) - 1, c * (n - c) + c * (c - 1) // 2 - 1)
+        g = planted_cover(n, c, m, 0.75, sub)
+        desc.update(avg_degree=d, cover=c, m=m)
+    else:
+        d = int(rng.integers(3, 6))
+        if (n * d) % 2:
+            n += 1
+        g = random_regular(n, d, sub)
+        desc.update(degree=d)
+    desc["n"] = n
+    return desc, g

@@ -74,6 +74,7 @@ extern "C" {
                                      of vc_options is set */
 
 typedef struct vc_ctx vc_ctx;
+typedef struct vc_server vc_server;
 
 typedef struct {
   int32_t n;
@@ -208,6 +209,59 @@ int vc_pvc_batch_device(vc_ctx *ctx, const vc_batch *batch, const int32_t *k,
                         const vc_options *opts, int32_t *status_out, int32_t *yes_out,
                         int32_t *size_out, uint8_t *cover_dev, int64_t *nodes_out,
                         vc_stats *stats);
+
+/* ---- serving: continuous batching of a request stream ----------------------------------
+ * A server owns `workers` threads, each with its own context (device workspace and stream).
+ * Submitted requests are queued with a copy of their graph. A free worker takes the oldest
+ * waiting request's problem kind and, in arrival order, every waiting request of that kind
+ * that fits the memory budget (at most max_batch), and solves them as one batch (as
+ * vc_mvc_batch / vc_pvc_batch) with wg_per_request traversal workgroups per request; requests
+ * arriving meanwhile are taken by other workers, so batches overlap on the device. Each result
+ * is exactly the answer the single-graph call gives for that graph (size, decision, a verified
+ * cover). The budget counts the node stacks a batch provisions (workgroups x depth bound x
+ * node bytes); a request that alone exceeds it runs when nothing else is in flight. */
+#define VC_PROBLEM_MVC 0
+#define VC_PROBLEM_PVC 1
+
+typedef struct {
+  int32_t workers;         /* concurrent batches; 0 = 4 */
+  int32_t max_batch;       /* requests per batch at most; 0 = 256 */
+  int64_t memory_budget;   /* bytes of node stacks in flight at most; 0 = 1/4 of free memory */
+  int32_t wg_per_request;  /* traversal workgroups per request of a batch; 0 = 8 */
+  int32_t reserved[3];     /* must be zero */
+} vc_server_options;
+
+typedef struct {
+  int64_t ticket;          /* from vc_server_submit */
+  int32_t status;          /* VC_OK, VC_ERR_INVALID_GRAPH, VC_ERR_BUDGET, or the batch's error */
+  int32_t size;            /* MVC: tau(G); PVC: |S| <= k on yes, -1 on no; -1 on error */
+  int32_t yes;             /* PVC decision (1 for an MVC answer) */
+  int32_t batch_size;      /* requests in the batch that solved it */
+  int32_t worker;          /* the worker (stream) that ran the batch */
+  int32_t pad;
+  int64_t nodes;           /* search-tree nodes visited on this graph */
+  double submit_ms;        /* times on the server's clock (ms since vc_server_create) */
+  double start_ms;
+  double done_ms;
+} vc_served;
+
+/* Create a server on `device`. `opts` (may be NULL) applies to every batch; its num_wg and
+ * VC_OPT_AUTOTUNE are not accepted (the grid follows the batch size). */
+int vc_server_create(vc_server **server_out, int device, const vc_server_options *sopts,
+                     const vc_options *opts);
+/* Queue one request: `g` holds HOST pointers and is copied before the call returns; k is
+ * used for VC_PROBLEM_PVC. `cover_out` (may be NULL; n bytes of host memory that must stay
+ * valid until the result is polled) receives the cover before the result is reported. */
+int vc_server_submit(vc_server *server, const vc_graph *g, int32_t problem, int32_t k,
+                     uint8_t *cover_out, int64_t *ticket_out);
+/* Move up to `max` finished results to `out`, in completion order; if none is ready, wait up
+ * to timeout_ms for one. *count_out is the number moved. */
+int vc_server_poll(vc_server *server, vc_served *out, int32_t max, int32_t timeout_ms,
+                   int32_t *count_out);
+/* Requests waiting and requests in running batches (either may be NULL). */
+int vc_server_pending(vc_server *server, int32_t *queued, int32_t *running);
+/* Finish the running batches, drop the waiting requests, release everything. */
+int vc_server_destroy(vc_server *server);
 
 /* The greedy approximation that seeds MVC's bound (paper §II-B, §IV-E), on the GPU with one
  * workgroup: apply the degree-one and degree-two-triangle rules, put a vertex of maximum

@@ -37,8 +37,12 @@ EXPORTS = (
     "vc_create", "vc_destroy", "vc_strerror", "vc_last_error", "vc_version",
     "vc_mvc", "vc_pvc", "vc_mvc_device", "vc_pvc_device", "vc_greedy_device",
     "vc_reduce_device", "vc_mvc_batch", "vc_pvc_batch", "vc_mvc_batch_device",
-    "vc_pvc_batch_device",
+    "vc_pvc_batch_device", "vc_server_create", "vc_server_submit", "vc_server_poll",
+    "vc_server_pending", "vc_server_destroy",
 )
+
+PROBLEM_MVC = 0
+PROBLEM_PVC = 1
 
 
 class _Graph(ctypes.Structure):
@@ -49,6 +53,20 @@ class _Graph(ctypes.Structure):
 class _Batch(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("n", ctypes.c_void_p), ("nnz", ctypes.c_void_p),
                 ("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p)]
+
+
+class _ServerOptions(ctypes.Structure):
+    _fields_ = [("workers", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64), ("wg_per_request", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+class _Served(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32), ("size", ctypes.c_int32),
+                ("yes", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("worker", ctypes.c_int32), ("pad", ctypes.c_int32), ("nodes", ctypes.c_int64),
+                ("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double)]
 
 
 class _Options(ctypes.Structure):
@@ -149,6 +167,12 @@ def load_library(path: str = LIB_PATH):
         "vc_pvc_batch": ([vp, bp, vp, op, vp, vp, vp, vp, vp, sp], ctypes.c_int),
         "vc_mvc_batch_device": ([vp, bp, op, vp, vp, vp, vp, sp], ctypes.c_int),
         "vc_pvc_batch_device": ([vp, bp, vp, op, vp, vp, vp, vp, vp, sp], ctypes.c_int),
+        "vc_server_create": ([ctypes.POINTER(vp), ctypes.c_int, ctypes.POINTER(_ServerOptions), op],
+                             ctypes.c_int),
+        "vc_server_submit": ([vp, gp, i32, i32, vp, ctypes.POINTER(i64)], ctypes.c_int),
+        "vc_server_poll": ([vp, ctypes.POINTER(_Served), i32, i32, i32p], ctypes.c_int),
+        "vc_server_pending": ([vp, i32p, i32p], ctypes.c_int),
+        "vc_server_destroy": ([vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -409,6 +433,79 @@ def _offsets(n):
     off = np.zeros(len(n) + 1, np.int64)
     np.cumsum(n, out=off[1:])
     return off
+
+
+class Server:
+    """Continuous batching of a request stream (vc_server_*): submit graphs as they arrive,
+    poll finished results. Each worker runs batches on its own context and stream."""
+
+    def __init__(self, device: int = 0, workers: int = 0, max_batch: int = 0,
+                 memory_budget: int = 0, wg_per_request: int = 0,
+                 options: Options | None = None):
+        self._lib = load_library()
+        self._srv = ctypes.c_void_p()
+        so = _ServerOptions(workers, max_batch, memory_budget, wg_per_request)
+        rc = self._lib.vc_server_create(ctypes.byref(self._srv), int(device), ctypes.byref(so),
+                                        ctypes.byref(options._c()) if options else None)
+        if rc != OK:
+            raise VCError(rc, f"vc_server_create: {self._lib.vc_strerror(rc).decode()}")
+        self._covers = {}
+        self._buf = (_Served * 1024)()
+
+    def submit(self, g, problem: str, k: int = 0, cover: bool = True) -> int:
+        """Queue graph `g` (host CSR, copied) for "mvc" or "pvc" with parameter k."""
+        cg, keep = _host_graph(g)
+        code = {"mvc": PROBLEM_MVC, "pvc": PROBLEM_PVC}[problem]
+        buf = np.zeros(max(g.n, 1), np.uint8) if cover else None
+        ticket = ctypes.c_int64()
+        rc = self._lib.vc_server_submit(self._srv, ctypes.byref(cg), code, int(k),
+                                        buf.ctypes.data if buf is not None else None,
+                                        ctypes.byref(ticket))
+        if rc != OK:
+            raise VCError(rc, f"vc_server_submit: {self._lib.vc_strerror(rc).decode()}")
+        if buf is not None:
+            self._covers[ticket.value] = (buf, g.n)
+        return ticket.value
+
+    def poll(self, timeout_ms: int = 0, max_results: int = 1024) -> list[dict]:
+        """Finished results (waits up to timeout_ms when none is ready)."""
+        count = ctypes.c_int32()
+        m = min(max_results, len(self._buf))
+        rc = self._lib.vc_server_poll(self._srv, self._buf, m, int(timeout_ms),
+                                      ctypes.byref(count))
+        if rc != OK:
+            raise VCError(rc, "vc_server_poll")
+        out = []
+        for i in range(count.value):
+            r = self._buf[i]
+            d = {name: getattr(r, name) for name, _ in _Served._fields_ if name != "pad"}
+            cov = self._covers.pop(r.ticket, None)
+            if cov is not None:
+                d["cover"] = cov[0][:cov[1]]
+            out.append(d)
+        return out
+
+    def pending(self) -> tuple[int, int]:
+        q, r = ctypes.c_int32(), ctypes.c_int32()
+        self._lib.vc_server_pending(self._srv, ctypes.byref(q), ctypes.byref(r))
+        return q.value, r.value
+
+    def close(self):
+        if self._srv:
+            self._lib.vc_server_destroy(self._srv)
+            self._srv = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libvc.so")
-SOURCES = ["vc_device.hip", "vc_bitset.hip", "vc_host.cpp"]
+SOURCES = ["vc_device.hip", "vc_bitset.hip", "vc_host.cpp", "vc_server.cpp"]
 ARCH = os.environ.get("VC_OFFLOAD_ARCH", "gfx950")
 
 
@@ -31,7 +31,7 @@ def hipcc() -> str:
 
 def command(out: str) -> list[str]:
     return [
-        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
         # no packed-FP32 instructions anywhere (the library has no float arithmetic anyway)
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",

@@ -54,6 +54,8 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(b._Options) == 48
     assert ctypes.sizeof(b._Stats) == 7 * 8 + 10 * 4 + 3 * 8 + 10 * 8
     assert ctypes.sizeof(b._Batch) == 8 + 4 * 8
+    assert ctypes.sizeof(b._ServerOptions) == 4 + 4 + 8 + 4 + 3 * 4
+    assert ctypes.sizeof(b._Served) == 8 + 6 * 4 + 8 + 3 * 8
 
 
 def test_no_gpu_means_device_error(lib):
