@@ -139,8 +139,8 @@ def serving_main(a):
     log(f"regenerating {len(reqs)} graphs")
     with mp.get_context("fork").Pool(16) as pool:
         graphs = pool.map(_trace_graph, [(trace["master_seed"], r["draw"]) for r in reqs], chunksize=8)
-    served = dict(workers=4, max_batch=256, wg_per_request=8)
-    plain = dict(workers=1, max_batch=1, wg_per_request=8)
+    served = dict(workers=4, max_batch=32, wg_per_request=256)
+    plain = dict(workers=1, max_batch=1, wg_per_request=1 << 16)  # one request, the whole GPU
     for i in range(a.warmup):
         replay(vc, graphs[:200], reqs[:200], served, "warm-up")
         log(f"warmup {i + 1}/{a.warmup} done")
@@ -157,6 +157,14 @@ def serving_main(a):
     log("replaying the plain form (one worker, one request per launch)")
     pres, pwall = replay(vc, graphs, reqs, plain, "plain")
     base = serving_summary(pres, pwall, reqs)
+    # capacity: the same requests all submitted at once
+    burst = [dict(r, t_ms=0.0) for r in reqs]
+    log("saturation: all requests at once, served and plain")
+    sres, swall = replay(vc, graphs, burst, served, "served, saturated")
+    pres2, pwall2 = replay(vc, graphs, burst, plain, "plain, saturated")
+    sat = {"served": serving_summary(sres, swall, burst),
+           "plain": serving_summary(pres2, pwall2, burst)}
+    sat["served_over_plain"] = sat["served"]["instances_per_s"] / sat["plain"]["instances_per_s"]
     best = max(runs, key=lambda r: r["instances_per_s"])
     med = sorted(runs, key=lambda r: r["instances_per_s"])[len(runs) // 2]
     out = {
@@ -174,6 +182,7 @@ def serving_main(a):
         "served": med, "best_step": best,
         "plain_sequential": base,
         "served_over_plain": med["instances_per_s"] / base["instances_per_s"],
+        "saturated": sat,
         "nodes_per_s": med["nodes"] / (med["span_ms"] / 1000.0),
     }
     print(json.dumps(out), flush=True)

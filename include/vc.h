@@ -96,7 +96,9 @@ typedef struct {
   int64_t node_budget;  /* stop with VC_ERR_BUDGET after about this many nodes (per graph
                            of a batch); 0 = none */
   int32_t flags;        /* VC_OPT_* */
-  int32_t reserved[5];  /* must be zero */
+  int32_t grid_share;   /* > 0: use at most 1/grid_share of the co-resident grid (callers that
+                           run several launches side by side); 0 = all of it */
+  int32_t reserved[4];  /* must be zero */
 } vc_options;
 
 /* A batch of independent graphs, each in the format above, packed one after the other. */
@@ -216,7 +218,8 @@ int vc_pvc_batch_device(vc_ctx *ctx, const vc_batch *batch, const int32_t *k,
  * waiting request's problem kind and, in arrival order, every waiting request of that kind
  * that fits the memory budget (at most max_batch), and solves them as one batch (as
  * vc_mvc_batch / vc_pvc_batch) with wg_per_request traversal workgroups per request; requests
- * arriving meanwhile are taken by other workers, so batches overlap on the device. Each result
+ * arriving meanwhile are taken by other workers, so batches overlap on the device (each batch's
+ * grid is at most 1/workers of the co-resident grid). Each result
  * is exactly the answer the single-graph call gives for that graph (size, decision, a verified
  * cover). The budget counts the node stacks a batch provisions (workgroups x depth bound x
  * node bytes); a request that alone exceeds it runs when nothing else is in flight. */
@@ -225,9 +228,10 @@ int vc_pvc_batch_device(vc_ctx *ctx, const vc_batch *batch, const int32_t *k,
 
 typedef struct {
   int32_t workers;         /* concurrent batches; 0 = 4 */
-  int32_t max_batch;       /* requests per batch at most; 0 = 256 */
+  int32_t max_batch;       /* requests per batch at most; 0 = 32 */
   int64_t memory_budget;   /* bytes of node stacks in flight at most; 0 = 1/4 of free memory */
-  int32_t wg_per_request;  /* traversal workgroups per request of a batch; 0 = 8 */
+  int32_t wg_per_request;  /* traversal workgroups per request of a batch, up to an equal share
+                              of the device per worker; 0 = 256 */
   int32_t reserved[3];     /* must be zero */
 } vc_server_options;
 

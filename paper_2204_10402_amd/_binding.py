@@ -73,7 +73,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("num_wg", ctypes.c_int32),
                 ("wl_capacity", ctypes.c_int32), ("wl_threshold", ctypes.c_int32),
                 ("node_budget", ctypes.c_int64), ("flags", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("grid_share", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class _Stats(ctypes.Structure):
@@ -99,12 +99,14 @@ class Options:
     wl_threshold: int = 0
     node_budget: int = 0
     flags: int = 0
+    grid_share: int = 0
 
     def _c(self) -> _Options:
         o = _Options()
         o.wg_size, o.num_wg = self.wg_size, self.num_wg
         o.wl_capacity, o.wl_threshold = self.wl_capacity, self.wl_threshold
         o.node_budget, o.flags = self.node_budget, self.flags
+        o.grid_share = self.grid_share
         return o
 
 

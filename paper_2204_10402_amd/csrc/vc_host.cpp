@@ -172,7 +172,8 @@ int check_options(vc_ctx* ctx, const vc_options* o) {
     if (r != 0) return fail(ctx, VC_ERR_INVALID_ARG, "vc_options.reserved must be zero");
   if (o->wg_size != 0 && (o->wg_size < 64 || o->wg_size > 1024 || o->wg_size % 64 != 0))
     return fail(ctx, VC_ERR_INVALID_ARG, "wg_size must be 0 or a multiple of 64 in [64, 1024]");
-  if (o->num_wg < 0 || o->wl_capacity < 0 || o->wl_threshold < -1 || o->node_budget < 0)
+  if (o->num_wg < 0 || o->wl_capacity < 0 || o->wl_threshold < -1 || o->node_budget < 0 ||
+      o->grid_share < 0)
     return fail(ctx, VC_ERR_INVALID_ARG, "negative option value");
   const int32_t known = VC_OPT_NO_DEGREE_ONE | VC_OPT_NO_TRIANGLE | VC_OPT_NO_HIGH_DEGREE |
                         VC_OPT_NO_EDGE_PRUNE | VC_OPT_PROFILE | VC_OPT_DEGREE_ARRAYS |
@@ -286,6 +287,7 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int32_t words, const vc_op
   // Bitset nodes take a few microseconds each, so more than eight workgroups per CU only add
   // contention on the worklist counters (measured on the hard MVC instances).
   if (words && !(o && o->num_wg > 0)) pl.num_wg = std::min(pl.num_wg, 8 * cus);
+  if (o && o->grid_share > 0) pl.num_wg = std::max(1, pl.num_wg / o->grid_share);
   if (o && o->num_wg > 0) pl.num_wg = std::min(pl.num_wg, o->num_wg);
 
   // Worklist: capacity and donation threshold (§IV-A). A producer only reserves a slot after

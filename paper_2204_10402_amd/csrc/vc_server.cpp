@@ -6,8 +6,8 @@
 // the oldest waiting request's problem kind (MVC or PVC) and, in arrival order, every waiting
 // request of that kind that fits the memory budget (up to max_batch), and solves them as one
 // batch (vc_mvc_batch / vc_pvc_batch: one persistent launch per kernel family) with a grid of
-// wg_per_request workgroups per request. While it runs, other workers admit the requests that
-// arrive meanwhile, so batches overlap on the device. The budget counts the node stacks a batch
+// wg_per_request workgroups per request, at most 1/W of the co-resident grid. While it runs,
+// other workers admit the requests that arrive meanwhile, so batches overlap on the device. The budget counts the node stacks a batch
 // provisions (workgroups x depth bound x node bytes); a request that alone exceeds it runs
 // when nothing else is in flight. Each result carries the submission, start and completion
 // times on the server's clock.
@@ -41,13 +41,14 @@ struct Request {
   int64_t footprint = 0;
 };
 
-// Bytes of node stacks a request adds to a batch: its workgroups times the depth bound times
+// Bytes of node stacks a request adds to a batch: its workgroups (at most one per CU's worth,
+// 256, since a batch's grid is capped by its share of the device) times the depth bound times
 // the stored node size of its kernel family.
 int64_t footprint(int32_t n, int32_t problem, int32_t k, int32_t wg_per_request) {
   const int64_t depth = problem == VC_PROBLEM_PVC ? std::min<int64_t>(k, n) + 1 : n;
   const int64_t node = n <= vc::kMaxBitsetN ? vc::bitset_stride((std::max(n, 1) + 63) / 64) * 4
                                             : static_cast<int64_t>(vc::array_stride(n)) * 4;
-  return static_cast<int64_t>(wg_per_request) * depth * node;
+  return std::min<int64_t>(wg_per_request, 256) * depth * node;
 }
 
 }  // namespace
@@ -136,7 +137,9 @@ void vc_server::worker_main(int w) {
     cover.assign(static_cast<size_t>(std::max<int64_t>(total_n, 1)), 0);
     vc_batch b{count, n.data(), nnz.data(), rp.data(), ci.empty() ? nullptr : ci.data()};
     vc_options o = opts;
-    o.num_wg = std::max(1, std::min(1 << 20, so.wg_per_request * count));
+    o.num_wg = static_cast<int32_t>(
+        std::max<int64_t>(1, std::min<int64_t>(1 << 20, int64_t{so.wg_per_request} * count)));
+    o.grid_share = so.workers;  // side by side with the other workers' batches
     int rc = problem == VC_PROBLEM_PVC
                  ? vc_pvc_batch(ctx, &b, k.data(), &o, status.data(), yes.data(), size.data(),
                                 cover.data(), nodes.data(), nullptr)
@@ -186,10 +189,11 @@ int vc_server_create(vc_server** out, int device, const vc_server_options* sopts
   if (so.workers < 0 || so.max_batch < 0 || so.memory_budget < 0 || so.wg_per_request < 0)
     return VC_ERR_INVALID_ARG;
   if (so.workers == 0) so.workers = 4;
-  if (so.max_batch == 0) so.max_batch = 256;
-  if (so.wg_per_request == 0) so.wg_per_request = 8;
+  if (so.max_batch == 0) so.max_batch = 32;
+  if (so.wg_per_request == 0) so.wg_per_request = 256;
   if (so.workers > 64) return VC_ERR_INVALID_ARG;
-  if (opts && (opts->num_wg || (opts->flags & VC_OPT_AUTOTUNE))) return VC_ERR_INVALID_ARG;
+  if (opts && (opts->num_wg || opts->grid_share || (opts->flags & VC_OPT_AUTOTUNE)))
+    return VC_ERR_INVALID_ARG;
   if (so.memory_budget == 0) {
     size_t free_b = 0, total_b = 0;
     if (hipSetDevice(device) != hipSuccess || hipMemGetInfo(&free_b, &total_b) != hipSuccess)
