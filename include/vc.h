@@ -66,6 +66,11 @@ extern "C" {
 #define VC_OPT_BITSETS 0x40       /* use the bitset kernels (the default up to 256 vertices;
                                      VC_ERR_INVALID_ARG above): a node is the set of live
                                      vertices, held in registers */
+#define VC_OPT_STACK_ONLY 0x100   /* ablation: the StackOnly method the paper compares with
+                                     (§V-A): no worklist; workgroup w takes the sub-trees at
+                                     depth start_depth numbered w, w + grid, ..., walks down
+                                     to each from the root and walks it with its own stack.
+                                     One graph per call (a batch of one). */
 #define VC_OPT_AUTOTUNE 0x80      /* pick workgroup size, grid size and donation threshold of
                                      each launch by timing trial launches the first time this
                                      context sees its kernel family, problem, options and size
@@ -98,7 +103,9 @@ typedef struct {
   int32_t flags;        /* VC_OPT_* */
   int32_t grid_share;   /* > 0: use at most 1/grid_share of the co-resident grid (callers that
                            run several launches side by side); 0 = all of it */
-  int32_t reserved[4];  /* must be zero */
+  int32_t start_depth;  /* with VC_OPT_STACK_ONLY: depth of the sub-trees handed out, 1..24;
+                           0 = 12 */
+  int32_t reserved[3];  /* must be zero */
 } vc_options;
 
 /* A batch of independent graphs, each in the format above, packed one after the other. */
@@ -115,8 +122,9 @@ typedef struct {
 /* Per-call statistics. A search-tree node is one visit: a node is taken from the stack or
  * the worklist (or continued in place) and the reduction rules run on it. */
 typedef struct {
-  int64_t nodes;          /* nodes visited, all workgroups */
-  int64_t wg_nodes_max;   /* most nodes visited by one workgroup */
+  int64_t nodes;          /* search-tree nodes visited, each counted once */
+  int64_t wg_nodes_max;   /* most nodes visited by one workgroup (with VC_OPT_STACK_ONLY
+                             including its walks down from the root) */
   int64_t wg_nodes_min;   /* fewest nodes visited by one workgroup */
   int64_t stack_pushes;   /* deferred children kept on a workgroup's own stack */
   int64_t stack_pops;
@@ -156,6 +164,11 @@ int vc_destroy(vc_ctx *ctx);
 
 /* Text of a status code. */
 const char *vc_strerror(int status);
+
+/* Nodes visited by each workgroup of the context's last traversal launch (the last kernel
+ * family of a batch): up to `max` values in `nodes_out`, *count_out = the grid size. With
+ * VC_OPT_STACK_ONLY a workgroup's count includes its walks down from the root. */
+int vc_wg_loads(vc_ctx *ctx, int64_t *nodes_out, int32_t max, int32_t *count_out);
 
 /* Description of the last failure on this context ("" if none). Valid until the next call. */
 const char *vc_last_error(const vc_ctx *ctx);

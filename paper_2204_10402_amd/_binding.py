@@ -29,6 +29,7 @@ OPT_PROFILE = 0x10
 OPT_DEGREE_ARRAYS = 0x20
 OPT_BITSETS = 0x40
 OPT_AUTOTUNE = 0x80
+OPT_STACK_ONLY = 0x100
 ACTIVITIES = ("acquire", "reduce", "branch", "donate", "other", "total",
               "reduce_deg1", "reduce_tri", "reduce_high", "reduce_apply")
 
@@ -38,7 +39,7 @@ EXPORTS = (
     "vc_mvc", "vc_pvc", "vc_mvc_device", "vc_pvc_device", "vc_greedy_device",
     "vc_reduce_device", "vc_mvc_batch", "vc_pvc_batch", "vc_mvc_batch_device",
     "vc_pvc_batch_device", "vc_server_create", "vc_server_submit", "vc_server_poll",
-    "vc_server_pending", "vc_server_destroy",
+    "vc_server_pending", "vc_server_destroy", "vc_wg_loads",
 )
 
 PROBLEM_MVC = 0
@@ -73,7 +74,8 @@ class _Options(ctypes.Structure):
     _fields_ = [("wg_size", ctypes.c_int32), ("num_wg", ctypes.c_int32),
                 ("wl_capacity", ctypes.c_int32), ("wl_threshold", ctypes.c_int32),
                 ("node_budget", ctypes.c_int64), ("flags", ctypes.c_int32),
-                ("grid_share", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("grid_share", ctypes.c_int32), ("start_depth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
 
 
 class _Stats(ctypes.Structure):
@@ -100,13 +102,14 @@ class Options:
     node_budget: int = 0
     flags: int = 0
     grid_share: int = 0
+    start_depth: int = 0
 
     def _c(self) -> _Options:
         o = _Options()
         o.wg_size, o.num_wg = self.wg_size, self.num_wg
         o.wl_capacity, o.wl_threshold = self.wl_capacity, self.wl_threshold
         o.node_budget, o.flags = self.node_budget, self.flags
-        o.grid_share = self.grid_share
+        o.grid_share, o.start_depth = self.grid_share, self.start_depth
         return o
 
 
@@ -175,6 +178,7 @@ def load_library(path: str = LIB_PATH):
         "vc_server_poll": ([vp, ctypes.POINTER(_Served), i32, i32, i32p], ctypes.c_int),
         "vc_server_pending": ([vp, i32p, i32p], ctypes.c_int),
         "vc_server_destroy": ([vp], ctypes.c_int),
+        "vc_wg_loads": ([vp, vp, i32, i32p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -405,6 +409,15 @@ class Solver:
                                            nodes.ctypes.data, ctypes.byref(st))
         self._check(rc, "vc_pvc_batch_device")
         return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, True)
+
+    def wg_loads(self) -> np.ndarray:
+        """Nodes visited by each workgroup of the last traversal launch."""
+        count = ctypes.c_int32()
+        self._check(self._lib.vc_wg_loads(self._ctx, None, 0, ctypes.byref(count)), "vc_wg_loads")
+        out = np.zeros(max(count.value, 1), np.int64)
+        self._check(self._lib.vc_wg_loads(self._ctx, out.ctypes.data, count.value,
+                                          ctypes.byref(count)), "vc_wg_loads")
+        return out[:count.value]
 
     def greedy_device(self, row_ptr, col_idx, cover=None) -> int:
         cg = _device_graph(row_ptr, col_idx)

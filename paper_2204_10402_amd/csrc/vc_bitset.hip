@@ -505,6 +505,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   int64_t unreported = 0;
   int max_depth = 0;
   uint32_t headers = 0;  // node headers read so far
+  uint32_t so_path = 0;  // StackOnly: the current path index
   Live<W> L;
 
   for (;;) {
@@ -515,6 +516,71 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         bits_load<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, pending, inst);
         ++pops;
         clk.charge(kActAcquire);
+      } else if (p.start_depth > 0) {
+        // StackOnly (the comparison method of §V-A): no worklist. This workgroup's sub-trees
+        // are the paths wg, wg + num_wg, ... < 2^start_depth (bit d: which child at depth d);
+        // it walks each path down from the root, then walks the sub-tree with its stack. A node
+        // above the start depth counts for the instance only on the path whose remaining bits
+        // are zero, so the instance's node count is the tree's.
+        if (cur < 0) {
+          cur_n = load_adjacency<W>(p, 0, adj_lds, r);
+          const Instance in = p.inst[0];
+          cur = 0;
+          cur_k = in.k;
+          cur_vtx = in.vtx_off;
+          ++insts;
+          so_path = static_cast<uint32_t>(wg);
+        } else {
+          so_path += static_cast<uint32_t>(p.num_wg);
+        }
+        const int rejected =
+            __builtin_amdgcn_readfirstlane(load_relaxed(&p.ist[0].err_row) != kNoRow);
+        if (so_path >= (1u << p.start_depth) || rejected) {
+          clk.charge(kActAcquire);
+          break;
+        }
+        root_bits<W>(L, cur_n);
+        pending = -1;
+        bool reached = true;
+        for (int d = 0; d < p.start_depth && reached; ++d) {
+          const bool owner = (so_path >> d) == 0;
+          const uint64_t h = uniform64(inst_header(p, cur));
+          const int32_t state = static_cast<int32_t>(h >> 32);
+          if ((state & kInstOutOfBudget) || (PVC && (state & kInstFound))) {
+            reached = false;
+            break;
+          }
+          const int64_t bound = PVC ? static_cast<int64_t>(cur_k)
+                                    : static_cast<int64_t>(static_cast<int32_t>(h)) - 1;
+          ++nodes;
+          if (owner) ++unreported;
+          reduce_bits<W>(r, L, adj_lds, bound, p.rules);
+          const int64_t rr = bound - L.s;
+          int vmax = 0;
+          int32_t degsum = 0;
+          if (rr >= 0) bits_max_degree<W>(r, L, vmax, degsum);
+          const int64_t edges = degsum / 2;
+          if (rr < 0 || ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > rr * rr)) {
+            reached = false;
+          } else if (edges == 0) {  // a cover: recorded once, on the owning path
+            if (owner) {
+              int won = 0;
+              if (tid == 0) won = bits_claim<PVC>(p, cur, L.s);
+              if (__builtin_amdgcn_readfirstlane(won)) {
+                write_cover<W>(p.covers + cur_vtx, L, cur_n);
+                __threadfence();
+                if (tid == 0) bits_publish<PVC>(p, cur, L.s);
+              }
+            }
+            reached = false;
+          } else if ((so_path >> d) & 1u) {
+            remove_neighbourhood_bits<W>(L, vmax, adj_lds);
+          } else {
+            remove_vertex_bits<W>(L, vmax);
+          }
+        }
+        clk.charge(kActAcquire);
+        if (!reached) continue;
       } else {
         if (holding) {
           if (tid == 0) release_work(p, cur);

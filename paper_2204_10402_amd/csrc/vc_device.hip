@@ -707,6 +707,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0, insts = 0;
   int64_t unreported = 0;  // nodes on `cur` not yet added to its counter
   int max_depth = 0;
+  uint32_t so_path = 0;    // StackOnly: the current path index
 
   for (;;) {
     if (!have) {
@@ -717,6 +718,75 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         ++pops;
         __syncthreads();
         clk.charge(kActAcquire);
+      } else if (p.start_depth > 0) {
+        // StackOnly (the comparison method of §V-A), as in bitset_traverse_kernel: walk this
+        // workgroup's next path down from the root, then take the node at the start depth.
+        if (cur < 0) {
+          nd = load_instance(p, 0, st, heads);
+          const Instance in = p.inst[0];
+          cur = 0;
+          cur_k = in.k;
+          cur_vtx = in.vtx_off;
+          ++insts;
+          so_path = static_cast<uint32_t>(wg);
+        } else {
+          so_path += static_cast<uint32_t>(p.num_wg);
+        }
+        if (tid == 0) c.err = load_relaxed(&p.ist[0].err_row) != kNoRow;
+        __syncthreads();
+        if (so_path >= (1u << p.start_depth) || c.err) {
+          clk.charge(kActAcquire);
+          break;
+        }
+        build_root(p, nd, 0);
+        bool reached = true;
+        for (int d = 0; d < p.start_depth && reached; ++d) {
+          const bool owner = (so_path >> d) == 0;
+          if (tid == 0) {
+            const uint64_t h = inst_header(p, cur);
+            const int32_t state = static_cast<int32_t>(h >> 32);
+            c.drop = (state & kInstOutOfBudget) | (PVC ? (state & kInstFound) : 0);
+            c.best = static_cast<int32_t>(static_cast<uint32_t>(h));
+          }
+          __syncthreads();
+          if (c.drop) {
+            reached = false;
+            break;
+          }
+          const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(c.best) - 1;
+          ++nodes;
+          if (owner) ++unreported;
+          reduce_node(nd, c, bound, p.rules, epoch, clk);
+          const int32_t s = st[nd.n];
+          const int64_t r = bound - s;
+          int vmax = 0, dmax = 0;
+          int32_t degsum = 0;
+          if (r >= 0) max_degree_and_sum(nd, c, vmax, dmax, degsum);
+          const int64_t edges = degsum / 2;
+          if (r < 0 || ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > r * r)) {
+            reached = false;
+          } else if (edges == 0) {  // a cover: recorded once, on the owning path
+            if (owner) {
+              if (tid == 0) c.status = claim_solution<PVC>(p, cur, s);
+              __syncthreads();
+              if (c.status) {
+                uint8_t* cov = p.covers + cur_vtx;
+                for (int v = tid; v < nd.n; v += blockDim.x) cov[v] = st[v] == kSent;
+                __threadfence();
+                __syncthreads();
+                if (tid == 0) publish_solution<PVC>(p, cur, s);
+              }
+            }
+            reached = false;
+          } else if ((so_path >> d) & 1u) {
+            remove_neighbourhood(nd, vmax);
+          } else {
+            remove_vertex(nd, vmax);
+          }
+          __syncthreads();  // every thread has read c.* before thread 0 writes it again
+        }
+        clk.charge(kActAcquire);
+        if (!reached) continue;
       } else {
         if (holding) {
           if (tid == 0) release_work(p, cur);

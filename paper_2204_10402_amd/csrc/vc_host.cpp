@@ -40,6 +40,7 @@ struct vc_ctx {
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   std::vector<hipEvent_t> ev;  // two per launch group
+  int32_t last_num_wg = 0;     // grid of the last traversal launch (its WgStats are kept)
   std::string last_error;
   // occupancy-API answers: (kernel family, pvc, profiled, workgroup size, words, LDS bytes)
   std::map<std::tuple<int, int, int, int, int, size_t>, int> occupancy;
@@ -177,7 +178,11 @@ int check_options(vc_ctx* ctx, const vc_options* o) {
     return fail(ctx, VC_ERR_INVALID_ARG, "negative option value");
   const int32_t known = VC_OPT_NO_DEGREE_ONE | VC_OPT_NO_TRIANGLE | VC_OPT_NO_HIGH_DEGREE |
                         VC_OPT_NO_EDGE_PRUNE | VC_OPT_PROFILE | VC_OPT_DEGREE_ARRAYS |
-                        VC_OPT_BITSETS | VC_OPT_AUTOTUNE;
+                        VC_OPT_BITSETS | VC_OPT_AUTOTUNE | VC_OPT_STACK_ONLY;
+  if (o->start_depth < 0 || o->start_depth > 24)
+    return fail(ctx, VC_ERR_INVALID_ARG, "start_depth must be in [0, 24]");
+  if (o->start_depth && !(o->flags & VC_OPT_STACK_ONLY))
+    return fail(ctx, VC_ERR_INVALID_ARG, "start_depth needs VC_OPT_STACK_ONLY");
   if (o->flags & ~known) return fail(ctx, VC_ERR_INVALID_ARG, "unknown option flag");
   if ((o->flags & VC_OPT_DEGREE_ARRAYS) && (o->flags & VC_OPT_BITSETS))
     return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_DEGREE_ARRAYS and VC_OPT_BITSETS exclude each other");
@@ -402,6 +407,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   if (rc) return rc;
   const int32_t flags = o ? o->flags : 0;
   const bool prof = flags & VC_OPT_PROFILE;
+  const bool stack_only = flags & VC_OPT_STACK_ONLY;
 
   // instance table, sorted by kernel family; graphs without vertices are answered here
   std::vector<int32_t> words(b.count, 0), order;
@@ -541,8 +547,13 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.words = g.words;
     p.rp_lds = pl.rp_lds;
     p.pvc = pvc ? 1 : 0;
+    if (stack_only) {
+      p.start_depth = o->start_depth ? o->start_depth : 12;
+      p.q_threshold = 0;  // no worklist
+    }
     DevResult* dres = d_res + gi;
     p.res = dres;
+    ctx->last_num_wg = pl.num_wg;
 
     VC_HIP(ctx, vc::launch_init(p, dres, st));
     VC_HIP(ctx, vc::launch_prepare(p, g.vertices, g.entries, st));
@@ -569,6 +580,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.stacks = static_cast<int32_t*>(ctx->stacks.ptr);
     p.depth_cap = g.depth_cap;
     p.num_wg = pl.num_wg;
+    ctx->last_num_wg = pl.num_wg;
     VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi], st));
     if (g.words) VC_HIP(ctx, vc::launch_bitset_traverse(pvc, prof, p, st));
     else VC_HIP(ctx, vc::launch_traverse(pvc, prof, p, pl.wg_size, st));
@@ -588,8 +600,10 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     return VC_OK;
   };
 
+  if (stack_only && m > 1)
+    return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_STACK_ONLY takes one graph per call");
   const bool explicit_knobs = o && (o->wg_size || o->num_wg || o->wl_capacity || o->wl_threshold);
-  const bool autotune = (flags & VC_OPT_AUTOTUNE) && !explicit_knobs;
+  const bool autotune = (flags & VC_OPT_AUTOTUNE) && !explicit_knobs && !stack_only;
   for (int32_t gi = 0; gi < ng; ++gi) {
     Group& g = groups[gi];
     vc_options go = o ? *o : vc_options{};
@@ -721,10 +735,10 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     vc_stats* sp = out.stats;
     std::memset(sp, 0, sizeof *sp);
     sp->wg_nodes_min = ng ? INT64_MAX : 0;
+    for (int32_t s = 0; s < m; ++s) sp->nodes += h_ist[s].nodes;  // each tree node once
     for (int32_t gi = 0; gi < ng; ++gi) {
       const DevResult& r = h_res[gi];
       const Group& g = groups[gi];
-      sp->nodes += r.nodes;
       sp->wg_nodes_max = std::max(sp->wg_nodes_max, r.wg_nodes_max);
       // idle workgroups do not report: any idle one makes the minimum zero
       sp->wg_nodes_min = std::min<int64_t>(
@@ -930,6 +944,24 @@ const char* vc_strerror(int status) {
 }
 
 const char* vc_last_error(const vc_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int vc_wg_loads(vc_ctx* ctx, int64_t* nodes_out, int32_t max, int32_t* count_out) {
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if (!count_out || max < 0 || (max > 0 && !nodes_out))
+    return fail(ctx, VC_ERR_INVALID_ARG, "NULL argument");
+  const int32_t cnt = ctx->wg_stats.ptr ? ctx->last_num_wg : 0;
+  *count_out = cnt;
+  const int32_t take = std::min(cnt, max);
+  if (take > 0) {
+    std::vector<vc::WgStats> w(static_cast<size_t>(take));
+    VC_HIP(ctx, hipMemcpyAsync(w.data(), ctx->wg_stats.ptr, w.size() * sizeof(vc::WgStats),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    VC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int32_t i = 0; i < take; ++i) nodes_out[i] = w[static_cast<size_t>(i)].nodes;
+  }
+  return VC_OK;
+}
 
 int vc_create(vc_ctx** ctx_out, int device, void* hip_stream) {
   if (!ctx_out) return VC_ERR_INVALID_ARG;

@@ -136,7 +136,7 @@ struct Params {
   int32_t words;        // bitset kernels: words per row of this launch; 0 = degree arrays
   int32_t rp_lds;       // degree-array kernels: copy the instance's row_ptr into LDS
   int32_t pvc;          // 1: PVC (instances stop once answered), 0: MVC
-  int32_t pad;
+  int32_t start_depth;  // > 0: StackOnly traversal of instance 0 from this depth; 0: hybrid
 };
 
 // Degree-array node, stored and in LDS: deg[0..n_i), s at n_i, pending vertex at n_i + 1, the

@@ -364,7 +364,7 @@ def test_node_budget(solver, oracle_lib):
 
 def test_bad_options(solver):
     import paper_2204_10402_amd as vc
-    for o in (vc.Options(wg_size=100), vc.Options(num_wg=-1), vc.Options(flags=0x100),
+    for o in (vc.Options(wg_size=100), vc.Options(num_wg=-1), vc.Options(flags=0x1000),
               vc.Options(wl_threshold=-2), vc.Options(flags=0x60), vc.Options(wg_size=128)):
         with pytest.raises(vc.VCError) as ei:
             solver.mvc(G.path(4), o)
@@ -429,3 +429,50 @@ def test_profiled_kernel_same_answers(solver, oracle_lib):
     assert arr.stats["nodes"] == o.nodes and arr.stats["cycles"]["reduce"] > 0
     plain = solver.mvc(g)
     assert all(v == 0 for v in plain.stats["cycles"].values())
+
+
+# ---- StackOnly ablation (the comparison method of §V-A) ------------------------------------
+
+@pytest.mark.parametrize("kernel", sorted(KERNELS))
+@pytest.mark.parametrize("depth", [1, 4, 8, 12])
+def test_stack_only_answers(solver, oracle_lib, kernel, depth):
+    """Static sub-tree partition at a start depth: same answers as the oracle; a PVC-no tree is
+    counted node for node (nodes above the start depth count once, on their owning path)."""
+    import paper_2204_10402_amd as vc
+    for seed in range(3):
+        g = G.erdos_renyi(40 + 10 * seed, 0.12, 900 + seed)
+        o = oracle.mvc(g)
+        opt = vc.Options(flags=vc.OPT_STACK_ONLY | KERNELS[kernel], start_depth=depth)
+        r = solver.mvc(g, opt)
+        assert r.size == o.size
+        check_cover(g, r.cover, o.size)
+        loads = solver.wg_loads()
+        assert loads.size == r.stats["num_wg"] and loads.sum() >= 1
+        for k in (o.size - 1, o.size):
+            want = oracle.pvc(g, k)
+            p = solver.pvc(g, k, opt)
+            assert p.yes == want.yes
+            if not want.yes:
+                assert p.stats["nodes"] == want.nodes
+            else:
+                check_cover(g, p.cover, p.size)
+
+
+def test_stack_only_larger_tree_and_limits(solver, oracle_lib):
+    """G(100, 0.1), seed 1: a 30,000-node tree (oracle); StackOnly at depths 8 and 16."""
+    import paper_2204_10402_amd as vc
+    g = G.erdos_renyi(100, 0.1, 1)
+    o = oracle.mvc(g)
+    for depth in (8, 16):
+        r = solver.mvc(g, vc.Options(flags=vc.OPT_STACK_ONLY, start_depth=depth))
+        assert r.size == o.size
+        check_cover(g, r.cover, o.size)
+        p = solver.pvc(g, o.size - 1, vc.Options(flags=vc.OPT_STACK_ONLY, start_depth=depth))
+        assert not p.yes and p.stats["nodes"] == oracle.pvc(g, o.size - 1).nodes
+    with pytest.raises(vc.VCError) as ei:
+        solver.mvc_batch([G.path(5), G.path(6)], vc.Options(flags=vc.OPT_STACK_ONLY))
+    assert ei.value.code == vc.ERR_INVALID_ARG
+    for bad in (vc.Options(flags=vc.OPT_STACK_ONLY, start_depth=25), vc.Options(start_depth=4)):
+        with pytest.raises(vc.VCError) as ei:
+            solver.mvc(G.path(5), bad)
+        assert ei.value.code == vc.ERR_INVALID_ARG
