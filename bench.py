@@ -23,6 +23,12 @@ Workloads (seeded, synthetic):
                  (one worker, one request per launch, in arrival order)
 Prints one JSON line on stdout; progress goes to stderr.
 
+Ablation (--ablation, hard instances): the hybrid traversal against StackOnly, the method the
+paper compares with (static sub-trees at start depth 8, 12 or 16, no worklist), on 5-regular
+n=120 and G(150, 0.08), seeds 0-1: time per solve, per-workgroup load distribution (load =
+nodes visited by a workgroup / mean over workgroups) and the activity breakdown of the
+instrumented kernels (each workgroup's cycles per activity / its total, mean over workgroups).
+
 HBM traffic of the traversal kernel (roofline "traffic"): two rocprofv3 counter runs of
     python bench.py --workload W --traffic-probe
 one with --pmc FETCH_SIZE and one with --pmc WRITE_SIZE, each writing CSV under a directory;
@@ -128,6 +134,74 @@ def serving_summary(res, wall, reqs):
             "nodes": int(sum(r["nodes"] for r in res)), "wall_s": round(wall, 3),
             "mean_batch": statistics.mean(r["batch_size"] for r in res),
             "span_ms": last - first}
+
+
+def load_distribution(loads):
+    import numpy as np
+    m = loads.mean() if loads.size and loads.mean() > 0 else 1.0
+    q = lambda x: float(np.percentile(loads, x) / m)
+    return {"min": float(loads.min() / m), "p25": q(25), "median": q(50), "p75": q(75),
+            "max": float(loads.max() / m), "workgroups": int(loads.size)}
+
+
+def activity_breakdown(cycles):
+    """Mean over workgroups of each activity's share of the workgroup's own total."""
+    import numpy as np
+    import paper_2204_10402_amd as vc
+    names = vc.ACTIVITIES
+    tot = cycles[:, names.index("total")].astype(float)
+    keep = tot > 0
+    out = {}
+    for i, name in enumerate(names):
+        if name != "total":
+            out[name] = float(np.mean(cycles[keep, i] / tot[keep])) if keep.any() else 0.0
+    return out
+
+
+def ablation_main(a):
+    import graphs as G
+    import paper_2204_10402_amd as vc
+    insts = [("5-regular n=120 seed 0", G.random_regular(120, 5, 0)),
+             ("5-regular n=120 seed 1", G.random_regular(120, 5, 1)),
+             ("G(150,0.08) seed 0", G.erdos_renyi(150, 0.08, 0)),
+             ("G(150,0.08) seed 1", G.erdos_renyi(150, 0.08, 1))]
+    solver = vc.Solver(0)
+    modes = [("hybrid", vc.Options())] + [
+        (f"stack_only_d{d}", vc.Options(flags=vc.OPT_STACK_ONLY, start_depth=d)) for d in (8, 12, 16)]
+    rows = []
+    for name, g in insts:
+        row = {"instance": name}
+        for mode, o in modes:
+            solver.mvc(g, o)  # warm
+            t = time.perf_counter()
+            r = solver.mvc(g, o)
+            dt = time.perf_counter() - t
+            row[mode] = {"ms": 1000 * dt, "kernel_ms": r.stats["kernel_ms"], "size": r.size,
+                         "nodes": r.stats["nodes"], "load": load_distribution(solver.wg_loads())}
+            log(f"{name} {mode}: {1000 * dt:.1f} ms")
+        best = min((m for m, _ in modes[1:]), key=lambda m: row[m]["ms"])
+        row["best_stack_only"] = best
+        row["hybrid_speedup_over_best_stack_only"] = row[best]["ms"] / row["hybrid"]["ms"]
+        prof = {}
+        for mode, o in (("hybrid", modes[0][1]), (best, dict(modes)[best])):
+            po = vc.Options(flags=o.flags | vc.OPT_PROFILE, start_depth=o.start_depth)
+            solver.mvc(g, po)
+            _, cyc = solver.wg_loads(cycles=True)
+            prof[mode] = activity_breakdown(cyc)
+        row["activity_breakdown"] = prof
+        if len({row[m]["size"] for m, _ in modes}) != 1:
+            raise SystemExit(f"{name}: answers differ between methods")
+        rows.append(row)
+    sp = [r["hybrid_speedup_over_best_stack_only"] for r in rows]
+    out = {"metric": METRIC, "value": statistics.geometric_mean(sp),
+           "unit": "x (hybrid over best StackOnly, geometric mean)", "n_gpus": 1,
+           "steps": 1, "warmup": 1, "ms_per_step": sum(r["hybrid"]["ms"] for r in rows),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+           "data": "synthetic", "config": {"workload": "ablation: hybrid vs StackOnly",
+                                           "instances": [r["instance"] for r in rows]},
+           "ablation": rows}
+    solver.close()
+    print(json.dumps(out), flush=True)
 
 
 def serving_main(a):
@@ -323,6 +397,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run 2 steps and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--ablation", action="store_true",
+                    help="hybrid against StackOnly on hard MVC instances (one JSON line)")
     a = ap.parse_args()
     if a.gpus != 1:
         log("bench.py measures one GPU: the traversal runs on a single MI355X and no multi-GPU "
@@ -333,6 +409,9 @@ def main():
         return
     if a.workload == "serving":
         serving_main(a)
+        return
+    if a.ablation:
+        ablation_main(a)
         return
     mode = a.mode
 

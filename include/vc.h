@@ -165,10 +165,13 @@ int vc_destroy(vc_ctx *ctx);
 /* Text of a status code. */
 const char *vc_strerror(int status);
 
-/* Nodes visited by each workgroup of the context's last traversal launch (the last kernel
- * family of a batch): up to `max` values in `nodes_out`, *count_out = the grid size. With
- * VC_OPT_STACK_ONLY a workgroup's count includes its walks down from the root. */
-int vc_wg_loads(vc_ctx *ctx, int64_t *nodes_out, int32_t max, int32_t *count_out);
+/* Per-workgroup statistics of the context's last traversal launch (the last kernel family of
+ * a batch), for up to `max` workgroups; *count_out = the grid size. `nodes_out` (may be NULL):
+ * nodes visited by each workgroup (with VC_OPT_STACK_ONLY including its walks down from the
+ * root). `cycles_out` (may be NULL; 10 per workgroup, in the order of vc_stats.cycles):
+ * its activity clocks, zero unless the launch ran with VC_OPT_PROFILE. */
+int vc_wg_loads(vc_ctx *ctx, int64_t *nodes_out, int64_t *cycles_out, int32_t max,
+                int32_t *count_out);
 
 /* Description of the last failure on this context ("" if none). Valid until the next call. */
 const char *vc_last_error(const vc_ctx *ctx);

@@ -178,7 +178,7 @@ def load_library(path: str = LIB_PATH):
         "vc_server_poll": ([vp, ctypes.POINTER(_Served), i32, i32, i32p], ctypes.c_int),
         "vc_server_pending": ([vp, i32p, i32p], ctypes.c_int),
         "vc_server_destroy": ([vp], ctypes.c_int),
-        "vc_wg_loads": ([vp, vp, i32, i32p], ctypes.c_int),
+        "vc_wg_loads": ([vp, vp, vp, i32, i32p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -410,14 +410,19 @@ class Solver:
         self._check(rc, "vc_pvc_batch_device")
         return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, True)
 
-    def wg_loads(self) -> np.ndarray:
-        """Nodes visited by each workgroup of the last traversal launch."""
+    def wg_loads(self, cycles: bool = False):
+        """Nodes visited by each workgroup of the last traversal launch; with cycles=True also
+        its activity clocks, an int64 array [workgroups, 10] (see ACTIVITIES)."""
         count = ctypes.c_int32()
-        self._check(self._lib.vc_wg_loads(self._ctx, None, 0, ctypes.byref(count)), "vc_wg_loads")
-        out = np.zeros(max(count.value, 1), np.int64)
-        self._check(self._lib.vc_wg_loads(self._ctx, out.ctypes.data, count.value,
+        self._check(self._lib.vc_wg_loads(self._ctx, None, None, 0, ctypes.byref(count)),
+                    "vc_wg_loads")
+        c = count.value
+        out = np.zeros(max(c, 1), np.int64)
+        cyc = np.zeros((max(c, 1), len(ACTIVITIES)), np.int64)
+        self._check(self._lib.vc_wg_loads(self._ctx, out.ctypes.data,
+                                          cyc.ctypes.data if cycles else None, c,
                                           ctypes.byref(count)), "vc_wg_loads")
-        return out[:count.value]
+        return (out[:c], cyc[:c]) if cycles else out[:c]
 
     def greedy_device(self, row_ptr, col_idx, cover=None) -> int:
         cg = _device_graph(row_ptr, col_idx)

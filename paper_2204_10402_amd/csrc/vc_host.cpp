@@ -945,11 +945,11 @@ const char* vc_strerror(int status) {
 
 const char* vc_last_error(const vc_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
 
-int vc_wg_loads(vc_ctx* ctx, int64_t* nodes_out, int32_t max, int32_t* count_out) {
+int vc_wg_loads(vc_ctx* ctx, int64_t* nodes_out, int64_t* cycles_out, int32_t max,
+                int32_t* count_out) {
   int rc = enter(ctx);
   if (rc) return rc;
-  if (!count_out || max < 0 || (max > 0 && !nodes_out))
-    return fail(ctx, VC_ERR_INVALID_ARG, "NULL argument");
+  if (!count_out || max < 0) return fail(ctx, VC_ERR_INVALID_ARG, "NULL argument");
   const int32_t cnt = ctx->wg_stats.ptr ? ctx->last_num_wg : 0;
   *count_out = cnt;
   const int32_t take = std::min(cnt, max);
@@ -958,7 +958,12 @@ int vc_wg_loads(vc_ctx* ctx, int64_t* nodes_out, int32_t max, int32_t* count_out
     VC_HIP(ctx, hipMemcpyAsync(w.data(), ctx->wg_stats.ptr, w.size() * sizeof(vc::WgStats),
                                hipMemcpyDeviceToHost, ctx->stream));
     VC_HIP(ctx, hipStreamSynchronize(ctx->stream));
-    for (int32_t i = 0; i < take; ++i) nodes_out[i] = w[static_cast<size_t>(i)].nodes;
+    for (int32_t i = 0; i < take; ++i) {
+      const vc::WgStats& x = w[static_cast<size_t>(i)];
+      if (nodes_out) nodes_out[i] = x.nodes;
+      if (cycles_out)
+        for (int a = 0; a < vc::kNumActivities; ++a) cycles_out[i * vc::kNumActivities + a] = x.cycles[a];
+    }
   }
   return VC_OK;
 }
