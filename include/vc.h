@@ -71,6 +71,9 @@ extern "C" {
                                      depth start_depth numbered w, w + grid, ..., walks down
                                      to each from the root and walks it with its own stack.
                                      One graph per call (a batch of one). */
+#define VC_OPT_GLOBAL_NODES 0x200 /* keep the degree-array node in device memory instead of LDS
+                                     (implies the degree-array kernels). Chosen automatically
+                                     when a node does not fit in LDS (n above about 39,000) */
 #define VC_OPT_AUTOTUNE 0x80      /* pick workgroup size, grid size and donation threshold of
                                      each launch by timing trial launches the first time this
                                      context sees its kernel family, problem, options and size

@@ -482,7 +482,7 @@ __device__ __forceinline__ void bits_report_nodes(const Params& p, int j, int64_
 
 // The hybrid traversal (§IV-A, Fig. 4; termination §IV-C) on bitset nodes, over every instance
 // of the launch (as traverse_kernel).
-template <int W, bool PVC, bool PROF>
+template <int W, bool PVC, bool PROF, bool SO>
 __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   extern __shared__ uint64_t adj_lds[];
   __shared__ Ctrl c;
@@ -516,7 +516,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         bits_load<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, pending, inst);
         ++pops;
         clk.charge(kActAcquire);
-      } else if (p.start_depth > 0) {
+      } else if constexpr (SO) {
         // StackOnly (the comparison method of §V-A): no worklist. This workgroup's sub-trees
         // are the paths wg, wg + num_wg, ... < 2^start_depth (bit d: which child at depth d);
         // it walks each path down from the root, then walks the sub-tree with its stack. A node
@@ -759,20 +759,22 @@ __global__ void __launch_bounds__(64) bitset_reduce_kernel(Params p, int32_t* de
 
 // ---- launchers ---------------------------------------------------------------------------------
 
-template <int W>
+template <int W, bool SO>
 static const void* bitset_traverse_fn(bool pvc, bool prof) {
-  if (pvc) return prof ? reinterpret_cast<const void*>(&bitset_traverse_kernel<W, true, true>)
-                       : reinterpret_cast<const void*>(&bitset_traverse_kernel<W, true, false>);
-  return prof ? reinterpret_cast<const void*>(&bitset_traverse_kernel<W, false, true>)
-              : reinterpret_cast<const void*>(&bitset_traverse_kernel<W, false, false>);
+  if (pvc) return prof ? reinterpret_cast<const void*>(&bitset_traverse_kernel<W, true, true, SO>)
+                       : reinterpret_cast<const void*>(&bitset_traverse_kernel<W, true, false, SO>);
+  return prof ? reinterpret_cast<const void*>(&bitset_traverse_kernel<W, false, true, SO>)
+              : reinterpret_cast<const void*>(&bitset_traverse_kernel<W, false, false, SO>);
 }
 
-static const void* bitset_fn(int words, bool pvc, bool prof) {
+// The StackOnly walk-down is a separate instantiation, so the hybrid kernels carry none of its
+// registers.
+static const void* bitset_fn(int words, bool pvc, bool prof, bool stack_only = false) {
   switch (words) {
-    case 1: return bitset_traverse_fn<1>(pvc, prof);
-    case 2: return bitset_traverse_fn<2>(pvc, prof);
-    case 3: return bitset_traverse_fn<3>(pvc, prof);
-    default: return bitset_traverse_fn<4>(pvc, prof);
+    case 1: return stack_only ? bitset_traverse_fn<1, true>(pvc, prof) : bitset_traverse_fn<1, false>(pvc, prof);
+    case 2: return stack_only ? bitset_traverse_fn<2, true>(pvc, prof) : bitset_traverse_fn<2, false>(pvc, prof);
+    case 3: return stack_only ? bitset_traverse_fn<3, true>(pvc, prof) : bitset_traverse_fn<3, false>(pvc, prof);
+    default: return stack_only ? bitset_traverse_fn<4, true>(pvc, prof) : bitset_traverse_fn<4, false>(pvc, prof);
   }
 }
 
@@ -796,8 +798,8 @@ hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStrea
   Params args = p;
   void* kargs[] = {&args};
   // plain launch; see launch_traverse for why co-residency is not required
-  return hipLaunchKernel(bitset_fn(p.words, pvc, prof), dim3(p.num_wg), dim3(64), kargs,
-                         bitset_lds_bytes(p.n_max, p.words), stream);
+  return hipLaunchKernel(bitset_fn(p.words, pvc, prof, p.start_depth > 0), dim3(p.num_wg),
+                         dim3(64), kargs, bitset_lds_bytes(p.n_max, p.words), stream);
 }
 
 hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,

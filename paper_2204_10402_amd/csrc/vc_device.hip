@@ -450,6 +450,21 @@ __device__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stri
   for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
 }
 
+// The node a workgroup works on: in LDS (dynamic shared memory, followed by the staged row
+// pointers), or, for graphs whose node does not fit there, in slot `slot` of the device-memory
+// node array. The node operations take a plain pointer, so one body serves both; in device
+// memory their reads, writes and atomics are global-memory accesses, ordered inside the
+// workgroup by the same barriers.
+template <bool GLOBAL>
+__device__ __forceinline__ int32_t* node_base(const Params& p, int slot) {
+  if constexpr (GLOBAL) {
+    return p.gnodes + static_cast<size_t>(slot) * p.stride;
+  } else {
+    extern __shared__ int4 lds4[];
+    return reinterpret_cast<int32_t*>(lds4);
+  }
+}
+
 // ---- instances -------------------------------------------------------------------------------
 
 // Whole workgroup: make instance j the one the node operations work on. Its row pointers are
@@ -601,11 +616,11 @@ __global__ void prepare_kernel(Params p, int64_t vertices, int64_t entries) {
 // §IV-E): degree-one and degree-two-triangle rules, then a maximum-degree vertex into the
 // cover, until no edge is left. One workgroup per instance (a grid-stride loop over the
 // launch's instances); the cover goes to the instance's cover output.
+template <bool GLOBAL>
 __global__ void __launch_bounds__(1024) greedy_kernel(Params p) {
-  extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
   __shared__ int32_t heads[kMaxWaves * 64];
-  int32_t* st = reinterpret_cast<int32_t*>(lds4);
+  int32_t* st = node_base<GLOBAL>(p, blockIdx.x);
   if (threadIdx.x == 0) c.flag_epoch = -1;
   int epoch = 0;
   for (int j = blockIdx.x; j < p.num_inst; j += gridDim.x) {
@@ -677,12 +692,11 @@ __device__ __forceinline__ void report_nodes(const Params& p, int j, int64_t cou
 // instance of the launch. A workgroup takes the root of an unstarted instance or a node from
 // the worklist, walks that node's sub-tree depth first with its stack, and loads an instance
 // (row pointers) only when the node it takes belongs to another one than the last.
-template <bool PVC, bool PROF>
+template <bool PVC, bool PROF, bool GLOBAL, bool SO>
 __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
-  extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
   __shared__ int32_t heads[kMaxWaves * 64];
-  int32_t* st = reinterpret_cast<int32_t*>(lds4);
+  int32_t* st = node_base<GLOBAL>(p, blockIdx.x);
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
   if (tid == 0) {
@@ -718,7 +732,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         ++pops;
         __syncthreads();
         clk.charge(kActAcquire);
-      } else if (p.start_depth > 0) {
+      } else if constexpr (SO) {
         // StackOnly (the comparison method of §V-A), as in bitset_traverse_kernel: walk this
         // workgroup's next path down from the root, then take the node at the start depth.
         if (cur < 0) {
@@ -1027,12 +1041,12 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertice
 
 // The reduction rules of one node, alone, on a degree array in device memory (instance 0 of
 // the launch, one workgroup). A rejected input leaves the degree array alone.
+template <bool GLOBAL>
 __global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, int32_t* s,
                                                       int64_t bound) {
-  extern __shared__ int4 lds4[];
   __shared__ Ctrl c;
   __shared__ int32_t heads[kMaxWaves * 64];
-  int32_t* st = reinterpret_cast<int32_t*>(lds4);
+  int32_t* st = node_base<GLOBAL>(p, 0);
   if (threadIdx.x == 0) {
     c.err = load_relaxed(&p.ist[0].err_row) != kNoRow;
     c.flag_epoch = -1;
@@ -1090,18 +1104,34 @@ hipError_t launch_prepare(const Params& p, int64_t vertices, int64_t entries,
   return hipGetLastError();
 }
 
+// Grid of the greedy launch (one workgroup per instance, at most 65,535); the device-memory
+// node array needs this many slots.
+int greedy_grid(const Params& p) { return p.num_inst < 65535 ? p.num_inst : 65535; }
+
 hipError_t launch_greedy(const Params& p, int32_t wg_size, hipStream_t stream) {
-  const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
-  hipLaunchKernelGGL(greedy_kernel, dim3(p.num_inst < 65535 ? p.num_inst : 65535), dim3(wg_size),
-                     lds, stream, p);
+  if (p.gnodes) {
+    hipLaunchKernelGGL(greedy_kernel<true>, dim3(greedy_grid(p)), dim3(wg_size), 0, stream, p);
+  } else {
+    const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
+    hipLaunchKernelGGL(greedy_kernel<false>, dim3(greedy_grid(p)), dim3(wg_size), lds, stream, p);
+  }
   return hipGetLastError();
 }
 
-static const void* traverse_fn(bool pvc, bool prof) {
-  if (pvc) return prof ? reinterpret_cast<const void*>(&traverse_kernel<true, true>)
-                       : reinterpret_cast<const void*>(&traverse_kernel<true, false>);
-  return prof ? reinterpret_cast<const void*>(&traverse_kernel<false, true>)
-              : reinterpret_cast<const void*>(&traverse_kernel<false, false>);
+template <bool GLOBAL, bool SO>
+static const void* traverse_fn_g(bool pvc, bool prof) {
+  if (pvc) return prof ? reinterpret_cast<const void*>(&traverse_kernel<true, true, GLOBAL, SO>)
+                       : reinterpret_cast<const void*>(&traverse_kernel<true, false, GLOBAL, SO>);
+  return prof ? reinterpret_cast<const void*>(&traverse_kernel<false, true, GLOBAL, SO>)
+              : reinterpret_cast<const void*>(&traverse_kernel<false, false, GLOBAL, SO>);
+}
+
+// The StackOnly walk-down is a separate instantiation, so the hybrid kernels carry none of its
+// registers.
+static const void* traverse_fn(bool pvc, bool prof, bool global_node, bool stack_only = false) {
+  if (stack_only)
+    return global_node ? traverse_fn_g<true, true>(pvc, prof) : traverse_fn_g<false, true>(pvc, prof);
+  return global_node ? traverse_fn_g<true, false>(pvc, prof) : traverse_fn_g<false, false>(pvc, prof);
 }
 
 // A plain launch: the grid is sized by the occupancy API so that all workgroups are normally
@@ -1111,10 +1141,12 @@ static const void* traverse_fn(bool pvc, bool prof) {
 // counter.
 hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size,
                            hipStream_t stream) {
-  const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
+  const bool global_node = p.gnodes != nullptr;
+  const size_t lds = global_node ? 0 : node_lds_bytes(p.stride, p.n_max, p.rp_lds);
   Params args = p;
   void* kargs[] = {&args};
-  return hipLaunchKernel(traverse_fn(pvc, prof), dim3(p.num_wg), dim3(wg_size), kargs, lds, stream);
+  return hipLaunchKernel(traverse_fn(pvc, prof, global_node, p.start_depth > 0), dim3(p.num_wg),
+                         dim3(wg_size), kargs, lds, stream);
 }
 
 hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, DevResult* res,
@@ -1127,8 +1159,12 @@ hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, D
 
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
                          int64_t bound, hipStream_t stream) {
-  const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(wg_size), lds, stream, p, deg, s, bound);
+  if (p.gnodes) {
+    hipLaunchKernelGGL(reduce_kernel<true>, dim3(1), dim3(wg_size), 0, stream, p, deg, s, bound);
+  } else {
+    const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
+    hipLaunchKernelGGL(reduce_kernel<false>, dim3(1), dim3(wg_size), lds, stream, p, deg, s, bound);
+  }
   return hipGetLastError();
 }
 
@@ -1137,17 +1173,19 @@ hipError_t launch_max_greedy(const Params& p, int32_t* out, hipStream_t stream) 
   return hipGetLastError();
 }
 
-hipError_t traverse_occupancy(bool pvc, bool prof, int32_t wg_size, size_t lds_bytes,
-                              int* blocks_per_cu) {
-  const void* fn = traverse_fn(pvc, prof);
+hipError_t traverse_occupancy(bool pvc, bool prof, bool global_node, int32_t wg_size,
+                              size_t lds_bytes, int* blocks_per_cu) {
+  const void* fn = traverse_fn(pvc, prof, global_node);
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, wg_size, lds_bytes);
 }
 
 hipError_t set_lds_limit(size_t lds_bytes) {
-  const void* fns[] = {traverse_fn(true, false), traverse_fn(false, false),
-                       traverse_fn(true, true), traverse_fn(false, true),
-                       reinterpret_cast<const void*>(&greedy_kernel),
-                       reinterpret_cast<const void*>(&reduce_kernel)};
+  const void* fns[] = {traverse_fn(true, false, false), traverse_fn(false, false, false),
+                       traverse_fn(true, true, false), traverse_fn(false, true, false),
+                       traverse_fn(true, false, false, true), traverse_fn(false, false, false, true),
+                       traverse_fn(true, true, false, true), traverse_fn(false, true, false, true),
+                       reinterpret_cast<const void*>(&greedy_kernel<false>),
+                       reinterpret_cast<const void*>(&reduce_kernel<false>)};
   for (const void* fn : fns) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds_bytes));

@@ -36,7 +36,7 @@ struct vc_ctx {
   size_t lds_limit_set = 0;
   // meta: the instance table, per-instance state, work counters and result blocks of a call,
   // mirrored in pinned host memory so that each call makes one copy in and one copy out
-  DevBuf rp, ci, meta, payload, seq, ctr, stacks, covers, wg_stats, scratch, bits;
+  DevBuf rp, ci, meta, payload, seq, ctr, stacks, covers, wg_stats, scratch, bits, gnodes;
   void* pinned = nullptr;
   size_t pinned_bytes = 0;
   std::vector<hipEvent_t> ev;  // two per launch group
@@ -178,7 +178,10 @@ int check_options(vc_ctx* ctx, const vc_options* o) {
     return fail(ctx, VC_ERR_INVALID_ARG, "negative option value");
   const int32_t known = VC_OPT_NO_DEGREE_ONE | VC_OPT_NO_TRIANGLE | VC_OPT_NO_HIGH_DEGREE |
                         VC_OPT_NO_EDGE_PRUNE | VC_OPT_PROFILE | VC_OPT_DEGREE_ARRAYS |
-                        VC_OPT_BITSETS | VC_OPT_AUTOTUNE | VC_OPT_STACK_ONLY;
+                        VC_OPT_BITSETS | VC_OPT_AUTOTUNE | VC_OPT_STACK_ONLY |
+                        VC_OPT_GLOBAL_NODES;
+  if ((o->flags & VC_OPT_GLOBAL_NODES) && (o->flags & VC_OPT_BITSETS))
+    return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_GLOBAL_NODES and VC_OPT_BITSETS exclude each other");
   if (o->start_depth < 0 || o->start_depth > 24)
     return fail(ctx, VC_ERR_INVALID_ARG, "start_depth must be in [0, 24]");
   if (o->start_depth && !(o->flags & VC_OPT_STACK_ONLY))
@@ -205,20 +208,22 @@ struct Plan {
   uint32_t cap = 0;
   uint32_t threshold = 0;
   size_t lds = 0;
-  int32_t rp_lds = 0;  // degree-array kernels: row_ptr staged in LDS
+  int32_t rp_lds = 0;       // degree-array kernels: row_ptr staged in LDS
+  int32_t global_node = 0;  // degree-array kernels: the node lives in device memory
 };
 
 // Resident workgroups per CU, from the occupancy API, remembered per context.
 int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, int n_max,
-              int* out) {
-  const auto key = std::make_tuple(words ? 1 : 0, pvc ? 1 : 0, prof ? 1 : 0, ws, words, lds);
+              int* out, bool global_node = false) {
+  const int family = words ? 1 : (global_node ? 2 : 0);
+  const auto key = std::make_tuple(family, pvc ? 1 : 0, prof ? 1 : 0, ws, words, lds);
   const auto it = ctx->occupancy.find(key);
   if (it != ctx->occupancy.end()) {
     *out = it->second;
     return VC_OK;
   }
   if (words) VC_HIP(ctx, vc::bitset_occupancy(words, pvc, prof, n_max, out));
-  else VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, ws, lds, out));
+  else VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, global_node, ws, lds, out));
   ctx->occupancy[key] = *out;
   return VC_OK;
 }
@@ -227,7 +232,7 @@ int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, i
 // the caller asks for degree arrays (0).
 int choose_words(vc_ctx* ctx, int32_t n, int32_t flags, int32_t* words) {
   const bool force_bits = flags & VC_OPT_BITSETS;
-  const bool force_arrays = flags & VC_OPT_DEGREE_ARRAYS;
+  const bool force_arrays = flags & (VC_OPT_DEGREE_ARRAYS | VC_OPT_GLOBAL_NODES);
   if (force_bits && n > vc::kMaxBitsetN)
     return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_BITSETS needs n <= 256");
   *words = (!force_arrays && n <= vc::kMaxBitsetN) ? (std::max(n, 1) + 63) / 64 : 0;
@@ -254,11 +259,12 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int32_t words, const vc_op
     pl.stride = vc::array_stride(n_max);
     pl.lds = vc::node_lds_bytes(pl.stride, n_max, false);
     const size_t lds_cap = static_cast<size_t>(ctx->prop.maxSharedMemoryPerMultiProcessor);
-    if (pl.lds + 1024 > lds_cap)
-      return fail(ctx, VC_ERR_INVALID_ARG,
-                  "graph too large for the LDS-resident node (n = " + std::to_string(n_max) + ")");
+    // Selection rule (§IV-E, adapted): the node stays in LDS while it fits there with room
+    // to spare; larger graphs (or VC_OPT_GLOBAL_NODES) keep it in device memory.
+    pl.global_node = ((o && (o->flags & VC_OPT_GLOBAL_NODES)) || pl.lds + 1024 > lds_cap) ? 1 : 0;
+    if (pl.global_node) pl.lds = 0;
     const size_t lds_rp = vc::node_lds_bytes(pl.stride, n_max, true);
-    const size_t lds_max = lds_rp + 1024 <= lds_cap ? lds_rp : pl.lds;
+    const size_t lds_max = pl.global_node ? 0 : (lds_rp + 1024 <= lds_cap ? lds_rp : pl.lds);
     if (lds_max > 65536 && ctx->lds_limit_set < lds_max) {
       VC_HIP(ctx, vc::set_lds_limit(lds_max));
       ctx->lds_limit_set = lds_max;
@@ -274,9 +280,11 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int32_t words, const vc_op
       while (ws < 1024 && ws * 2 <= std::max(n_max, 1) / 4) ws *= 2;
       best_ws = ws;
     }
-    if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, pl.lds, n_max, &best_occ))) return rc;
+    if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, pl.lds, n_max, &best_occ,
+                        pl.global_node != 0)))
+      return rc;
     // Keep row_ptr in LDS too when that costs no resident workgroup.
-    if (lds_rp + 1024 <= lds_cap) {
+    if (!pl.global_node && lds_rp + 1024 <= lds_cap) {
       int occ_rp = 0;
       if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_rp, n_max, &occ_rp))) return rc;
       if (occ_rp == best_occ) {
@@ -547,6 +555,12 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.words = g.words;
     p.rp_lds = pl.rp_lds;
     p.pvc = pvc ? 1 : 0;
+    if (pl.global_node) {
+      // one node slot per traversal workgroup and per greedy workgroup
+      const int64_t slots = std::max<int64_t>(pl.num_wg, std::min<int64_t>(g.end - g.begin, 65535));
+      if ((rc2 = ensure(ctx, ctx->gnodes, static_cast<size_t>(slots) * stride_b))) return rc2;
+      p.gnodes = static_cast<int32_t*>(ctx->gnodes.ptr);
+    }
     if (stack_only) {
       p.start_depth = o->start_depth ? o->start_depth : 12;
       p.q_threshold = 0;  // no worklist
@@ -879,6 +893,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   if (rc) return rc;
   Plan pl;
   vc_options o{};
+  o.flags = flags & VC_OPT_GLOBAL_NODES;
   if ((rc = plan_launch(ctx, false, g->n, words, &o, pl))) return rc;
   const MetaLayout L = meta_layout(1, 1, 0);
   if ((rc = ensure(ctx, ctx->meta, L.dev_end))) return rc;
@@ -916,6 +931,10 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   p.bits = words ? static_cast<uint64_t*>(ctx->bits.ptr) : nullptr;
   p.words = words;
   p.rp_lds = pl.rp_lds;
+  if (pl.global_node) {
+    if ((rc = ensure(ctx, ctx->gnodes, static_cast<size_t>(pl.stride) * sizeof(int32_t)))) return rc;
+    p.gnodes = static_cast<int32_t*>(ctx->gnodes.ptr);
+  }
   *wg_size = words ? 64 : static_cast<int32_t>(std::min<int64_t>(1024, round_up(g->n, 64)));
   DevResult* dres = reinterpret_cast<DevResult*>(dev + L.res);
   p.res = dres;
@@ -1001,7 +1020,7 @@ int vc_destroy(vc_ctx* ctx) {
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,       &ctx->meta,     &ctx->payload, &ctx->seq,
                     &ctx->ctr,    &ctx->stacks,   &ctx->covers,   &ctx->wg_stats, &ctx->scratch,
-                    &ctx->bits};
+                    &ctx->bits,   &ctx->gnodes};
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);

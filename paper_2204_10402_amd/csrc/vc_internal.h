@@ -135,6 +135,8 @@ struct Params {
   uint64_t* bits;       // bitset kernels: adjacency rows, words per launch-local vertex
   int32_t words;        // bitset kernels: words per row of this launch; 0 = degree arrays
   int32_t rp_lds;       // degree-array kernels: copy the instance's row_ptr into LDS
+  int32_t* gnodes;      // degree-array kernels with the node in device memory: one stride-word
+                        // slot per workgroup (nullptr: the node lives in LDS)
   int32_t pvc;          // 1: PVC (instances stop once answered), 0: MVC
   int32_t start_depth;  // > 0: StackOnly traversal of instance 0 from this depth; 0: hybrid
 };
@@ -178,14 +180,15 @@ hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream);
 hipError_t launch_prepare(const Params& p, int64_t vertices, int64_t entries,
                           hipStream_t stream);
 hipError_t launch_greedy(const Params& p, int32_t wg_size, hipStream_t stream);
+int greedy_grid(const Params& p);
 hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size,
                            hipStream_t stream);
 hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, DevResult* res,
                            hipStream_t stream);
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
                          int64_t bound, hipStream_t stream);
-hipError_t traverse_occupancy(bool pvc, bool prof, int32_t wg_size, size_t lds_bytes,
-                              int* blocks_per_cu);
+hipError_t traverse_occupancy(bool pvc, bool prof, bool global_node, int32_t wg_size,
+                              size_t lds_bytes, int* blocks_per_cu);
 hipError_t set_lds_limit(size_t lds_bytes);
 hipError_t launch_max_greedy(const Params& p, int32_t* out, hipStream_t stream);
 

@@ -36,7 +36,9 @@ def solver(torch_cuda):
     s.close()
 
 
-KERNELS = {"bitsets": 0x40, "degree_arrays": 0x20}
+# kernel families: bitsets (n <= 256), degree arrays with the node in LDS, and degree arrays
+# with the node in device memory (chosen automatically only when the node does not fit in LDS)
+KERNELS = {"bitsets": 0x40, "degree_arrays": 0x20, "global_nodes": 0x200}
 
 
 def single_wg(flags=0):
@@ -476,3 +478,24 @@ def test_stack_only_larger_tree_and_limits(solver, oracle_lib):
         with pytest.raises(vc.VCError) as ei:
             solver.mvc(G.path(5), bad)
         assert ei.value.code == vc.ERR_INVALID_ARG
+
+
+def test_graph_beyond_lds(solver, oracle_lib):
+    """n = 50,040 (a degree array of 200 KB: more than a CU's LDS), so the node lives in device
+    memory: 20 stars of 2,500 leaves and 2 Petersen graphs; tau = 20 + 2 * 6 = 32 (textbook
+    values of the components); the PVC-no tree is the oracle's node for node."""
+    import paper_2204_10402_amd as vc
+    g = G.disjoint_union(*([G.star(2500)] * 20 + [G.petersen()] * 2))
+    assert g.n == 50040
+    r = solver.mvc(g)
+    assert r.size == 32
+    check_cover(g, r.cover, 32)
+    assert r.stats["bitset_words"] == 0
+    p = solver.pvc(g, 31)
+    assert not p.yes and p.stats["nodes"] == oracle.pvc(g, 31, node_cap=100000).nodes
+    q = solver.pvc(g, 32)
+    assert q.yes and q.size <= 32
+    check_cover(g, q.cover, q.size)
+    with pytest.raises(vc.VCError) as ei:
+        solver.mvc(g, vc.Options(flags=vc.OPT_GLOBAL_NODES | vc.OPT_BITSETS))
+    assert ei.value.code == vc.ERR_INVALID_ARG
