@@ -397,6 +397,8 @@ def main():
     ap.add_argument("--traffic-probe", action="store_true",
                     help="run 2 steps and a calibration copy, for rocprofv3 --pmc")
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--no-single-pass", action="store_true",
+                    help="skip the untimed pass of single calls (for profiles of the batched call)")
     ap.add_argument("--ablation", action="store_true",
                     help="hybrid against StackOnly on hard MVC instances (one JSON line)")
     a = ap.parse_args()
@@ -529,6 +531,12 @@ def main():
                      + (" (all launches of a call)" if mode == "batch" else ""),
                      "algorithmic_bytes_per_launch": alg_bytes / calls},
     }
+    if a.no_single_pass:
+        if not a.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(a.workload, insts)
+        solver.close()
+        print(json.dumps(out), flush=True)
+        return
     # one untimed pass of single calls: per-instance time-to-solve, and the plain form's rate
     log("one pass of single calls (time-to-solve per instance)")
     if not a.no_autotune:

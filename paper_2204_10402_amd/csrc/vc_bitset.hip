@@ -181,18 +181,32 @@ __device__ __forceinline__ int pass_high_degree(const Rows<W>& r, Live<W>& L, in
 template <int W>
 __device__ __forceinline__ void reduce_bits(const Rows<W>& r, Live<W>& L, const uint64_t* adj_lds,
                             int64_t bound, int rules) {
+  // A pass is skipped when nothing has been removed since it last found nothing (its inputs
+  // are unchanged), as in the degree-array kernels.
+  int changes = 0, quiet1 = -1, quiet2 = -1, quiet3 = -1;
   for (;;) {
     const int32_t s0 = L.s;
     if (s0 > bound) return;
-    if (rules & kRuleDeg1) {
-      pass_degree_one(r, L);
-      if (L.s > bound) return;
+    if ((rules & kRuleDeg1) && quiet1 != changes) {
+      if (pass_degree_one(r, L)) {
+        ++changes;
+        if (L.s > bound) return;
+      } else {
+        quiet1 = changes;
+      }
     }
-    if (rules & kRuleTri) {
-      pass_triangle(r, L, adj_lds);
-      if (L.s > bound) return;
+    if ((rules & kRuleTri) && quiet2 != changes) {
+      if (pass_triangle(r, L, adj_lds)) {
+        ++changes;
+        if (L.s > bound) return;
+      } else {
+        quiet2 = changes;
+      }
     }
-    if (rules & kRuleHigh) pass_high_degree(r, L, bound - L.s);
+    if ((rules & kRuleHigh) && quiet3 != changes) {
+      if (pass_high_degree(r, L, bound - L.s)) ++changes;
+      else quiet3 = changes;
+    }
     if (L.s == s0) return;
   }
 }

@@ -314,39 +314,53 @@ __device__ void reduce_node(const Node nd, Ctrl& c, int64_t bound, int rules, in
                             Clock& clk) {
   const int n = nd.n;
   int32_t* st = nd.st;
+  // A rule pass is skipped when nothing has been removed since it last found nothing: its
+  // inputs (the graph, and |S| for the high-degree rule) are then unchanged, so it would find
+  // nothing again. This drops the empty passes of the final round, not any decision.
+  int changes = 0;                             // removal steps applied in this call
+  int quiet1 = -1, quiet2 = -1, quiet3 = -1;   // `changes` when each rule last found nothing
   for (;;) {
     const int32_t s0 = st[n];
     if (s0 > bound) return;
-    if (rules & kRuleDeg1) {
+    if ((rules & kRuleDeg1) && quiet1 != changes) {
       ++epoch;
       decide_degree_one(nd, c, epoch);
       __syncthreads();
       clk.charge(kActDeg1);
       if (c.flag_epoch == epoch) {
         apply_marks(nd);
+        ++changes;
         clk.charge(kActApply);
         if (st[n] > bound) return;
+      } else {
+        quiet1 = changes;
       }
     }
-    if (rules & kRuleTri) {
+    if ((rules & kRuleTri) && quiet2 != changes) {
       ++epoch;
       decide_triangle(nd, c, epoch);
       __syncthreads();
       clk.charge(kActTri);
       if (c.flag_epoch == epoch) {
         apply_marks(nd);
+        ++changes;
         clk.charge(kActApply);
         if (st[n] > bound) return;
+      } else {
+        quiet2 = changes;
       }
     }
-    if (rules & kRuleHigh) {
+    if ((rules & kRuleHigh) && quiet3 != changes) {
       ++epoch;
       decide_high_degree(nd, c, epoch, bound - st[n]);
       __syncthreads();
       clk.charge(kActHigh);
       if (c.flag_epoch == epoch) {
         apply_marks(nd);
+        ++changes;
         clk.charge(kActApply);
+      } else {
+        quiet3 = changes;
       }
     }
     if (st[n] == s0) return;
