@@ -429,7 +429,7 @@ def main():
     ks = [k for _, _, k, _ in insts]
     dev = torch.device("cuda:0")
     resident = []
-    for _, g, k, name in insts:
+    for _, g, k, name in insts if (mode == "single" or not a.no_single_pass) else []:
         rp = torch.from_numpy(g.row_ptr).to(dev)
         ci = torch.from_numpy(g.col_idx).to(dev)
         cover = torch.zeros(max(g.n, 1), dtype=torch.uint8, device=dev)
