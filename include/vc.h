@@ -74,6 +74,11 @@ extern "C" {
 #define VC_OPT_GLOBAL_NODES 0x200 /* keep the degree-array node in device memory instead of LDS
                                      (implies the degree-array kernels). Chosen automatically
                                      when a node does not fit in LDS (n above about 39,000) */
+#define VC_OPT_CSR_GLOBAL 0x400  /* degree-array kernels: read the graph's column indices from
+                                     device memory on every row walk. Without it a launch copies
+                                     each instance's CSR into LDS beside the node when that keeps
+                                     at least half of its resident workgroups; answers and node
+                                     counts are the same either way */
 #define VC_OPT_AUTOTUNE 0x80      /* pick workgroup size, grid size and donation threshold of
                                      each launch by timing trial launches the first time this
                                      context sees its kernel family, problem, options and size

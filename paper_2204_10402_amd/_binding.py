@@ -31,6 +31,7 @@ OPT_BITSETS = 0x40
 OPT_AUTOTUNE = 0x80
 OPT_STACK_ONLY = 0x100
 OPT_GLOBAL_NODES = 0x200
+OPT_CSR_GLOBAL = 0x400
 ACTIVITIES = ("acquire", "reduce", "branch", "donate", "other", "total",
               "reduce_deg1", "reduce_tri", "reduce_high", "reduce_apply")
 

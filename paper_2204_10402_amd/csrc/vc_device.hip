@@ -483,17 +483,26 @@ __device__ __forceinline__ int32_t* node_base(const Params& p, int slot) {
 
 // Whole workgroup: make instance j the one the node operations work on. Its row pointers are
 // copied into LDS right after the node when the launch has room for them (one LDS access
-// instead of an L2 round trip at the head of every row walk); the copy ends with a barrier.
+// instead of an L2 round trip at the head of every row walk), and its column indices after
+// them when the launch has room for those too (every row walk of a rule pass is then a chain
+// of LDS accesses); the copy ends with a barrier. The copies read only the instance's own
+// n + 1 row pointers and nnz entries, so they stay in bounds whatever the graph holds.
 __device__ Node load_instance(const Params& p, int j, int32_t* st, int32_t* heads) {
   const Instance in = p.inst[j];
   const int32_t* rp = p.rp_all + in.rp_off;
+  const int32_t* ci = p.ci_all + in.ci_off;
   if (p.rp_lds) {
     int32_t* dst = st + p.stride;
     for (int i = threadIdx.x; i <= in.n; i += blockDim.x) dst[i] = rp[i];
+    if (p.rp_lds == 2) {
+      int32_t* dci = dst + rp_lds_words(p.n_max);
+      for (int i = threadIdx.x; i < in.nnz; i += blockDim.x) dci[i] = ci[i];
+      ci = dci;
+    }
     __syncthreads();
     rp = dst;
   }
-  return Node{st, in.n, rp, p.ci_all + in.ci_off, heads};
+  return Node{st, in.n, rp, ci, heads};
 }
 
 // Whole workgroup: the root of instance j in LDS -- the input's degree array, s = 0, nothing
@@ -1126,7 +1135,7 @@ hipError_t launch_greedy(const Params& p, int32_t wg_size, hipStream_t stream) {
   if (p.gnodes) {
     hipLaunchKernelGGL(greedy_kernel<true>, dim3(greedy_grid(p)), dim3(wg_size), 0, stream, p);
   } else {
-    const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
+    const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds, p.nnz_max);
     hipLaunchKernelGGL(greedy_kernel<false>, dim3(greedy_grid(p)), dim3(wg_size), lds, stream, p);
   }
   return hipGetLastError();
@@ -1156,7 +1165,7 @@ static const void* traverse_fn(bool pvc, bool prof, bool global_node, bool stack
 hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size,
                            hipStream_t stream) {
   const bool global_node = p.gnodes != nullptr;
-  const size_t lds = global_node ? 0 : node_lds_bytes(p.stride, p.n_max, p.rp_lds);
+  const size_t lds = global_node ? 0 : node_lds_bytes(p.stride, p.n_max, p.rp_lds, p.nnz_max);
   Params args = p;
   void* kargs[] = {&args};
   return hipLaunchKernel(traverse_fn(pvc, prof, global_node, p.start_depth > 0), dim3(p.num_wg),
@@ -1176,7 +1185,7 @@ hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t
   if (p.gnodes) {
     hipLaunchKernelGGL(reduce_kernel<true>, dim3(1), dim3(wg_size), 0, stream, p, deg, s, bound);
   } else {
-    const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds);
+    const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds, p.nnz_max);
     hipLaunchKernelGGL(reduce_kernel<false>, dim3(1), dim3(wg_size), lds, stream, p, deg, s, bound);
   }
   return hipGetLastError();

@@ -179,7 +179,7 @@ int check_options(vc_ctx* ctx, const vc_options* o) {
   const int32_t known = VC_OPT_NO_DEGREE_ONE | VC_OPT_NO_TRIANGLE | VC_OPT_NO_HIGH_DEGREE |
                         VC_OPT_NO_EDGE_PRUNE | VC_OPT_PROFILE | VC_OPT_DEGREE_ARRAYS |
                         VC_OPT_BITSETS | VC_OPT_AUTOTUNE | VC_OPT_STACK_ONLY |
-                        VC_OPT_GLOBAL_NODES;
+                        VC_OPT_GLOBAL_NODES | VC_OPT_CSR_GLOBAL;
   if ((o->flags & VC_OPT_GLOBAL_NODES) && (o->flags & VC_OPT_BITSETS))
     return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_GLOBAL_NODES and VC_OPT_BITSETS exclude each other");
   if (o->start_depth < 0 || o->start_depth > 24)
@@ -208,7 +208,7 @@ struct Plan {
   uint32_t cap = 0;
   uint32_t threshold = 0;
   size_t lds = 0;
-  int32_t rp_lds = 0;       // degree-array kernels: row_ptr staged in LDS
+  int32_t rp_lds = 0;       // degree-array kernels: 1 = row_ptr staged in LDS, 2 = the CSR
   int32_t global_node = 0;  // degree-array kernels: the node lives in device memory
 };
 
@@ -242,8 +242,8 @@ int choose_words(vc_ctx* ctx, int32_t n, int32_t flags, int32_t* words) {
 // Workgroup size and count for one launch (paper §IV-E, adapted): a power-of-two workgroup of
 // about n_max/4 threads; as many workgroups as can be resident at once, fewer if their stacks
 // do not fit in device memory (size_stacks).
-int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int32_t words, const vc_options* o,
-                Plan& pl) {
+int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int64_t nnz_max, int32_t words,
+                const vc_options* o, Plan& pl) {
   const bool prof = o && (o->flags & VC_OPT_PROFILE);
   const int cus = ctx->prop.multiProcessorCount;
   int best_ws = 0, best_occ = 0, rc;
@@ -257,14 +257,19 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int32_t words, const vc_op
     if ((rc = occupancy(ctx, words, pvc, prof, 64, pl.lds, n_max, &best_occ))) return rc;
   } else {
     pl.stride = vc::array_stride(n_max);
-    pl.lds = vc::node_lds_bytes(pl.stride, n_max, false);
+    pl.lds = vc::node_lds_bytes(pl.stride, n_max, 0, 0);
     const size_t lds_cap = static_cast<size_t>(ctx->prop.maxSharedMemoryPerMultiProcessor);
     // Selection rule (§IV-E, adapted): the node stays in LDS while it fits there with room
     // to spare; larger graphs (or VC_OPT_GLOBAL_NODES) keep it in device memory.
     pl.global_node = ((o && (o->flags & VC_OPT_GLOBAL_NODES)) || pl.lds + 1024 > lds_cap) ? 1 : 0;
     if (pl.global_node) pl.lds = 0;
-    const size_t lds_rp = vc::node_lds_bytes(pl.stride, n_max, true);
-    const size_t lds_max = pl.global_node ? 0 : (lds_rp + 1024 <= lds_cap ? lds_rp : pl.lds);
+    const size_t lds_rp = vc::node_lds_bytes(pl.stride, n_max, 1, 0);
+    const size_t lds_csr = vc::node_lds_bytes(pl.stride, n_max, 2, nnz_max);
+    const bool csr_fits = !pl.global_node && !(o && (o->flags & VC_OPT_CSR_GLOBAL)) &&
+                          lds_csr + 1024 <= lds_cap;
+    const size_t lds_max = pl.global_node ? 0
+                           : csr_fits     ? lds_csr
+                                          : (lds_rp + 1024 <= lds_cap ? lds_rp : pl.lds);
     if (lds_max > 65536 && ctx->lds_limit_set < lds_max) {
       VC_HIP(ctx, vc::set_lds_limit(lds_max));
       ctx->lds_limit_set = lds_max;
@@ -290,6 +295,17 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int32_t words, const vc_op
       if (occ_rp == best_occ) {
         pl.rp_lds = 1;
         pl.lds = lds_rp;
+      }
+    }
+    // And the column indices when that keeps at least half of the resident workgroups: a
+    // rule pass is a chain of dependent row walks, which then read LDS instead of L2 or HBM.
+    if (csr_fits) {
+      int occ_csr = 0;
+      if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_csr, n_max, &occ_csr))) return rc;
+      if (occ_csr >= 1 && 2 * occ_csr >= best_occ) {
+        pl.rp_lds = 2;
+        pl.lds = lds_csr;
+        best_occ = occ_csr;
       }
     }
   }
@@ -367,6 +383,7 @@ struct Group {
   int32_t words = 0;
   int32_t begin = 0, end = 0;
   int32_t n_max = 0;
+  int32_t nnz_max = 0;
   int32_t k_max = 0;
   int64_t vertices = 0, entries = 0;
   Plan pl;
@@ -484,6 +501,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     in.k = pvc ? b.k[i] : 0;
     g.end = s + 1;
     g.n_max = std::max(g.n_max, in.n);
+    g.nnz_max = std::max(g.nnz_max, in.nnz);
     g.k_max = std::max(g.k_max, std::min(in.k, in.n));
     g.vertices += in.n;
     g.entries += in.nnz;
@@ -517,7 +535,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   auto run_group = [&](int32_t gi, const vc_options* go, int thr_div, bool final) -> int {
     Group& g = groups[gi];
     int rc2;
-    if ((rc2 = plan_launch(ctx, pvc, g.n_max, g.words, go, g.pl))) return rc2;
+    if ((rc2 = plan_launch(ctx, pvc, g.n_max, g.nnz_max, g.words, go, g.pl))) return rc2;
     Plan& pl = g.pl;
     if (thr_div > 0)
       pl.threshold = static_cast<uint32_t>(std::min<int64_t>(
@@ -534,6 +552,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.num_inst = g.end - g.begin;
     p.stride = pl.stride;
     p.n_max = g.n_max;
+    p.nnz_max = g.nnz_max;
     p.rules = rules_from_flags(flags);
     p.inst = d_inst + g.begin;
     p.ist = d_ist + g.begin;
@@ -636,7 +655,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
             for (int div : {8, 2}) cand.emplace_back(0, mult * cus, div);
         } else {
           Plan base;
-          if ((rc = plan_launch(ctx, pvc, g.n_max, 0, &go, base))) return rc;
+          if ((rc = plan_launch(ctx, pvc, g.n_max, g.nnz_max, 0, &go, base))) return rc;
           for (int ws : {base.wg_size / 2, base.wg_size, base.wg_size * 2})
             if (ws >= 64 && ws <= 1024)
               for (int div : {8, 1}) cand.emplace_back(ws, 0, div);
@@ -893,8 +912,8 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   if (rc) return rc;
   Plan pl;
   vc_options o{};
-  o.flags = flags & VC_OPT_GLOBAL_NODES;
-  if ((rc = plan_launch(ctx, false, g->n, words, &o, pl))) return rc;
+  o.flags = flags & (VC_OPT_GLOBAL_NODES | VC_OPT_CSR_GLOBAL);
+  if ((rc = plan_launch(ctx, false, g->n, g->nnz, words, &o, pl))) return rc;
   const MetaLayout L = meta_layout(1, 1, 0);
   if ((rc = ensure(ctx, ctx->meta, L.dev_end))) return rc;
   if ((rc = ensure_pinned(ctx, L.host_end))) return rc;
@@ -918,6 +937,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   p.num_inst = 1;
   p.stride = pl.stride;
   p.n_max = g->n;
+  p.nnz_max = g->nnz;
   p.rules = rules;
   p.inst = reinterpret_cast<const Instance*>(dev + L.inst);
   p.ist = reinterpret_cast<InstState*>(dev + L.ist);

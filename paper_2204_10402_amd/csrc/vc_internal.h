@@ -134,7 +134,9 @@ struct Params {
   int32_t num_wg;
   uint64_t* bits;       // bitset kernels: adjacency rows, words per launch-local vertex
   int32_t words;        // bitset kernels: words per row of this launch; 0 = degree arrays
-  int32_t rp_lds;       // degree-array kernels: copy the instance's row_ptr into LDS
+  int32_t rp_lds;       // degree-array kernels: 1 = copy the instance's row_ptr into LDS after
+                        // the node, 2 = its col_idx too (after row_ptr); 0 = neither
+  int32_t nnz_max;      // largest nnz of this launch (sizes the LDS copy of col_idx)
   int32_t* gnodes;      // degree-array kernels with the node in device memory: one stride-word
                         // slot per workgroup (nullptr: the node lives in LDS)
   int32_t pvc;          // 1: PVC (instances stop once answered), 0: MVC
@@ -147,10 +149,16 @@ inline int32_t array_stride(int32_t n_max) {
   return static_cast<int32_t>((static_cast<int64_t>(n_max) + 3 + 63) / 64 * 64);
 }
 
-// Dynamic LDS of a degree-array kernel: the node (stride words), then row_ptr if staged.
-inline size_t node_lds_bytes(int32_t stride, int32_t n_max, bool rp_lds) {
-  const size_t node = static_cast<size_t>(stride) * 4;
-  return rp_lds ? node + ((static_cast<size_t>(n_max) + 1) * 4 + 15) / 16 * 16 : node;
+// LDS words that hold a staged row_ptr (n_max + 1 entries, padded to 16 bytes).
+__host__ __device__ inline size_t rp_lds_words(int32_t n_max) { return (static_cast<size_t>(n_max) + 1 + 3) / 4 * 4; }
+
+// Dynamic LDS of a degree-array kernel: the node (stride words), then row_ptr if staged
+// (rp_lds >= 1), then col_idx if staged (rp_lds == 2).
+inline size_t node_lds_bytes(int32_t stride, int32_t n_max, int32_t rp_lds, int64_t nnz_max) {
+  size_t words = static_cast<size_t>(stride);
+  if (rp_lds >= 1) words += rp_lds_words(n_max);
+  if (rp_lds == 2) words += (static_cast<size_t>(nnz_max) + 3) / 4 * 4;
+  return words * 4;
 }
 
 // Launch-wide result block written by the finalize kernel and copied to the host once.

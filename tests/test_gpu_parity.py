@@ -38,7 +38,8 @@ def solver(torch_cuda):
 
 # kernel families: bitsets (n <= 256), degree arrays with the node in LDS, and degree arrays
 # with the node in device memory (chosen automatically only when the node does not fit in LDS)
-KERNELS = {"bitsets": 0x40, "degree_arrays": 0x20, "global_nodes": 0x200}
+# degree_arrays stages small graphs' CSR in LDS; csr_global reads it from device memory
+KERNELS = {"bitsets": 0x40, "degree_arrays": 0x20, "csr_global": 0x420, "global_nodes": 0x200}
 
 
 def single_wg(flags=0):
