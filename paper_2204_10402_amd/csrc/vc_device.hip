@@ -487,10 +487,20 @@ __device__ __forceinline__ int32_t* node_base(const Params& p, int slot) {
 // them when the launch has room for those too (every row walk of a rule pass is then a chain
 // of LDS accesses); the copy ends with a barrier. The copies read only the instance's own
 // n + 1 row pointers and nnz entries, so they stay in bounds whatever the graph holds.
+// Graphs whose column indices stay in device memory (up to 1 MB of them) are first touched
+// once per 128-byte line, with independent loads, so that the dependent row walks of the rule
+// passes find them in this XCD's L2.
+constexpr int32_t kTouchMaxEntries = 1 << 18;
+
 __device__ Node load_instance(const Params& p, int j, int32_t* st, int32_t* heads) {
   const Instance in = p.inst[j];
   const int32_t* rp = p.rp_all + in.rp_off;
   const int32_t* ci = p.ci_all + in.ci_off;
+  if (p.rp_lds != 2 && !p.gnodes && in.nnz <= kTouchMaxEntries) {
+    int32_t acc = 0;
+    for (int i = threadIdx.x * 32; i < in.nnz; i += blockDim.x * 32) acc ^= ci[i];
+    asm volatile("" ::"v"(acc));
+  }
   if (p.rp_lds) {
     int32_t* dst = st + p.stride;
     for (int i = threadIdx.x; i <= in.n; i += blockDim.x) dst[i] = rp[i];
@@ -555,12 +565,21 @@ __device__ bool try_enqueue(const Params& p, const Node nd, Ctrl& c, int pending
 
 // ---- kernels ---------------------------------------------------------------------------------
 
-// Zero the control lines and the result block and mark every worklist slot free (the host
-// uploads the fresh per-instance state with the instance table). Every instance's root is
-// handed out by the root ticket counter, so the worklist starts empty.
-__global__ void init_kernel(Params p, DevResult* res) {
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gsize = gridDim.x * blockDim.x;
+
+// Check every graph of the launch (simple undirected, §II-A). Index i < vertices checks row
+// i's bounds (and, for the bitset kernels, packs the row into adjacency words); index i <
+// entries checks one CSR entry: in range, not a self-loop, larger than the entry before it in
+// its row, and present in reverse. Every read is bounds-checked before it is made, so a
+// malformed input cannot send a thread out of its instance's arrays. Each instance keeps the
+// smallest offending row.
+//
+// The same launch first resets the launch's control lines and result block and marks every
+// worklist slot free (the host uploads the fresh per-instance state with the instance table);
+// every instance's root is handed out by the root ticket counter, so the worklist starts empty.
+// Nothing in the validation reads what the reset writes.
+__global__ void prepare_kernel(Params p, DevResult* res, int64_t vertices, int64_t entries) {
+  const int64_t total = vertices > entries ? vertices : entries;
+  const int64_t gsize = static_cast<int64_t>(gridDim.x) * blockDim.x;
   if (blockIdx.x == 0) {
     for (int i = threadIdx.x; i < kNumCounters * kCounterStride; i += blockDim.x) p.ctr[i] = 0;
     __syncthreads();
@@ -572,18 +591,9 @@ __global__ void init_kernel(Params p, DevResult* res) {
       res->wg_nodes_min = INT64_MAX;
     }
   }
-  for (uint32_t i = gtid; i < p.q_cap; i += gsize) p.seq[i] = 0u;
-}
-
-// Check every graph of the launch (simple undirected, §II-A). Index i < vertices checks row
-// i's bounds (and, for the bitset kernels, packs the row into adjacency words); index i <
-// entries checks one CSR entry: in range, not a self-loop, larger than the entry before it in
-// its row, and present in reverse. Every read is bounds-checked before it is made, so a
-// malformed input cannot send a thread out of its instance's arrays. Each instance keeps the
-// smallest offending row.
-__global__ void prepare_kernel(Params p, int64_t vertices, int64_t entries) {
-  const int64_t total = vertices > entries ? vertices : entries;
-  const int64_t gsize = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < p.q_cap;
+       i += gsize)
+    p.seq[i] = 0u;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < total;
        i += gsize) {
     if (i < vertices) {
@@ -1114,16 +1124,12 @@ static int grid_for(int64_t items, int threads, int cap) {
   return static_cast<int>(blocks);
 }
 
-hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream) {
-  hipLaunchKernelGGL(init_kernel, dim3(grid_for(p.q_cap, 256, 1024)), dim3(256), 0, stream, p, res);
-  return hipGetLastError();
-}
-
-hipError_t launch_prepare(const Params& p, int64_t vertices, int64_t entries,
+hipError_t launch_prepare(const Params& p, DevResult* res, int64_t vertices, int64_t entries,
                           hipStream_t stream) {
   const int64_t items = vertices > entries ? vertices : entries;
-  hipLaunchKernelGGL(prepare_kernel, dim3(grid_for(items, 256, 4096)), dim3(256), 0, stream, p,
-                     vertices, entries);
+  const int blocks = std::max(grid_for(items, 256, 4096), grid_for(p.q_cap, 256, 1024));
+  hipLaunchKernelGGL(prepare_kernel, dim3(blocks), dim3(256), 0, stream, p, res, vertices,
+                     entries);
   return hipGetLastError();
 }
 

@@ -588,8 +588,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.res = dres;
     ctx->last_num_wg = pl.num_wg;
 
-    VC_HIP(ctx, vc::launch_init(p, dres, st));
-    VC_HIP(ctx, vc::launch_prepare(p, g.vertices, g.entries, st));
+    VC_HIP(ctx, vc::launch_prepare(p, dres, g.vertices, g.entries, st));
     if (!pvc) {
       const int gws = g.words ? 64 : static_cast<int>(std::min<int64_t>(1024, round_up(g.n_max, 64)));
       hipEvent_t e0 = ctx->ev[2 * ng], e1 = ctx->ev[2 * ng + 1];
@@ -958,8 +957,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
   *wg_size = words ? 64 : static_cast<int32_t>(std::min<int64_t>(1024, round_up(g->n, 64)));
   DevResult* dres = reinterpret_cast<DevResult*>(dev + L.res);
   p.res = dres;
-  VC_HIP(ctx, vc::launch_init(p, dres, ctx->stream));
-  VC_HIP(ctx, vc::launch_prepare(p, g->n, g->nnz, ctx->stream));
+  VC_HIP(ctx, vc::launch_prepare(p, dres, g->n, g->nnz, ctx->stream));
   return VC_OK;
 }
 

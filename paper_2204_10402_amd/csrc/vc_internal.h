@@ -184,8 +184,8 @@ struct DevResult {
 // `vertices` / `entries` are totals over the launch's instances (sum of n, sum of nnz).
 
 // vc_device.hip
-hipError_t launch_init(const Params& p, DevResult* res, hipStream_t stream);
-hipError_t launch_prepare(const Params& p, int64_t vertices, int64_t entries,
+// Reset the launch's control words, result block and worklist tickets, and validate every CSR.
+hipError_t launch_prepare(const Params& p, DevResult* res, int64_t vertices, int64_t entries,
                           hipStream_t stream);
 hipError_t launch_greedy(const Params& p, int32_t wg_size, hipStream_t stream);
 int greedy_grid(const Params& p);
