@@ -18,7 +18,11 @@
  *   col_idx    nnz entries; row v holds the neighbours of v, strictly ascending, no v itself,
  *              and u in row v  <=>  v in row u.
  * An input that breaks any of these rules is rejected with VC_ERR_INVALID_GRAPH; nothing is
- * repaired. Vertices of degree 0 never enter a returned cover.
+ * repaired. The message names the first offending row: the smallest v whose bounds are wrong
+ * or which holds an entry u that is out of range, equal to v, not above the entry before it,
+ * or not found in row u by a binary search (which assumes row u ascending, so an unsorted row
+ * can also make a neighbour's row the first one named). Vertices of degree 0 never enter a
+ * returned cover.
  *
  * Threading: one call at a time per context. Separate contexts may be used concurrently.
  * Ownership: every pointer argument stays owned by the caller; the library keeps no

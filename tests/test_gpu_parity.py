@@ -356,6 +356,63 @@ def test_invalid_graph_rejected(solver, name, rp, ci, first_row):
     assert solver.mvc(G.path(5)).size == 2
 
 
+def first_bad_row(n, rp, ci):
+    """The first offending row as include/vc.h defines it: its bounds, and each entry in range,
+    not a self-loop, above the one before it, and found in reverse by a binary search of the
+    neighbour's row (bisect here). The row pointers here are non-decreasing, so every entry
+    belongs to exactly one row."""
+    import bisect
+    nnz = len(ci)
+    for v in range(n):
+        b, e = int(rp[v]), int(rp[v + 1])
+        if (v == 0 and b != 0) or (v == n - 1 and e != nnz) or b < 0 or e < b or e > nnz:
+            return v
+        for j in range(b, e):
+            u = int(ci[j])
+            if u < 0 or u >= n or u == v or (j > b and int(ci[j - 1]) >= u):
+                return v
+            row = [int(x) for x in ci[rp[u]:rp[u + 1]]]
+            at = bisect.bisect_left(row, v)
+            if at >= len(row) or row[at] != v:
+                return v
+    return None
+
+
+@pytest.mark.parametrize("kind", ["out_of_range", "self_loop", "asymmetric", "unsorted"])
+def test_invalid_entry_deep_in_a_large_graph(solver, kind):
+    """A defect in one entry of G(600, 0.05) (about 18,000 entries, many validation blocks):
+    the reported row is the first offending row by the format's definition."""
+    import paper_2204_10402_amd as vc
+    g = G.erdos_renyi(600, 0.05, 77)
+    rp, ci = g.row_ptr.copy(), g.col_idx.copy()
+    v = 411
+    j = int(rp[v]) + 1
+    if kind == "out_of_range":
+        ci[j] = 600
+    elif kind == "self_loop":
+        ci[j] = v
+    elif kind == "asymmetric":
+        ci[j] = int(ci[j]) + 1 if int(ci[j]) + 1 < int(ci[j + 1]) else int(ci[j]) - 1
+    else:
+        ci[j], ci[j + 1] = ci[j + 1], ci[j]
+    want = first_bad_row(600, rp, ci)
+    assert want is not None
+
+    class Raw:
+        pass
+    bad = Raw()
+    bad.n, bad.row_ptr, bad.col_idx = 600, rp, ci
+    with pytest.raises(vc.VCError) as ei:
+        solver.mvc(bad, vc.Options(flags=vc.OPT_DEGREE_ARRAYS))
+    assert ei.value.code == vc.ERR_INVALID_GRAPH and f"row {want} " in str(ei.value)
+    # inside a batch, between two valid graphs: only its own status changes (the valid graph
+    # is sparse, G(300, 2/300): its oracle search takes a handful of nodes)
+    good = G.erdos_renyi(300, 2.0 / 300, 78)
+    r = solver.mvc_batch([good, bad, good])
+    assert list(r.status) == [0, vc.ERR_INVALID_GRAPH, 0]
+    assert r.size[0] == r.size[2] == solver.mvc(good).size
+
+
 def test_node_budget(solver, oracle_lib):
     import paper_2204_10402_amd as vc
     g = G.random_regular(120, 5, 0)
