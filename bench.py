@@ -526,8 +526,8 @@ def main():
         "kernel_ms_avg": 1000 * avg_kernel_s,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": ("traverse_kernel" if last["n"] > 256 or not last["bitset_words"]
-                                else "bitset_traverse_kernel")
+                     "kernel": ("bitset_traverse_kernel" if last["bitset_words"]
+                                else "traverse_kernel")
                      + (" (all launches of a call)" if mode == "batch" else ""),
                      "algorithmic_bytes_per_launch": alg_bytes / calls},
     }

@@ -68,8 +68,8 @@ extern "C" {
 #define VC_OPT_DEGREE_ARRAYS 0x20 /* use the degree-array kernels (the default above 256
                                      vertices): a node is an int32 degree array in LDS */
 #define VC_OPT_BITSETS 0x40       /* use the bitset kernels (the default up to 256 vertices;
-                                     VC_ERR_INVALID_ARG above): a node is the set of live
-                                     vertices, held in registers */
+                                     available up to 512, VC_ERR_INVALID_ARG above): a node is
+                                     the set of live vertices, held in registers */
 #define VC_OPT_STACK_ONLY 0x100   /* ablation: the StackOnly method the paper compares with
                                      (§V-A): no worklist; workgroup w takes the sub-trees at
                                      depth start_depth numbered w, w + grid, ..., walks down

@@ -1,4 +1,4 @@
-// vc_bitset.hip -- the vertex-cover search for graphs of at most 256 vertices, with a search
+// vc_bitset.hip -- the vertex-cover search for graphs of at most 512 vertices, with a search
 // node held as a bitset of live vertices (gfx950).
 //
 // Same method and same rules as the degree-array kernels in vc_device.hip (paper §II-B, §IV):
@@ -257,15 +257,15 @@ __device__ __forceinline__ void remove_neighbourhood_bits(Live<W>& L, int v,
 
 
 // A stored node: W words of live bits (lo/hi 32-bit halves), |S|, then one word packing the
-// pending vertex plus one (9 bits, n <= 256) with the instance (launch-local index, shifted
-// left 9), padding to a multiple of four words. Lane 0 writes and reads every stored node, so
+// pending vertex plus one (10 bits, n <= 512) with the instance (launch-local index below
+// 2^22, shifted left 10), padding to a multiple of four words. Lane 0 writes and reads every stored node, so
 // a node pushed on the workgroup's stack is read back in program order, and the worklist
 // publishes it with one release store.
 template <int W>
 constexpr int bits_stride() {
   return ((2 * W + 2) + 3) & ~3;
 }
-constexpr int kPendingBits = 9;
+constexpr int kPendingBits = 10;
 
 template <int W>
 __device__ __forceinline__ void bits_store(int32_t* dst, const Live<W>& L, int pending, int inst) {
@@ -276,7 +276,8 @@ __device__ __forceinline__ void bits_store(int32_t* dst, const Live<W>& L, int p
       dst[2 * w + 1] = static_cast<int32_t>(static_cast<uint32_t>(L.bits[w] >> 32));
     }
     dst[2 * W] = L.s;
-    dst[2 * W + 1] = (pending + 1) | (inst << kPendingBits);
+    dst[2 * W + 1] = static_cast<int32_t>(static_cast<uint32_t>(pending + 1) |
+                                          (static_cast<uint32_t>(inst) << kPendingBits));
   }
 }
 
@@ -784,12 +785,19 @@ static const void* bitset_traverse_fn(bool pvc, bool prof) {
 // The StackOnly walk-down is a separate instantiation, so the hybrid kernels carry none of its
 // registers.
 static const void* bitset_fn(int words, bool pvc, bool prof, bool stack_only = false) {
+#define VC_BITSET_CASE(WW) \
+  case WW: return stack_only ? bitset_traverse_fn<WW, true>(pvc, prof) : bitset_traverse_fn<WW, false>(pvc, prof);
   switch (words) {
-    case 1: return stack_only ? bitset_traverse_fn<1, true>(pvc, prof) : bitset_traverse_fn<1, false>(pvc, prof);
-    case 2: return stack_only ? bitset_traverse_fn<2, true>(pvc, prof) : bitset_traverse_fn<2, false>(pvc, prof);
-    case 3: return stack_only ? bitset_traverse_fn<3, true>(pvc, prof) : bitset_traverse_fn<3, false>(pvc, prof);
-    default: return stack_only ? bitset_traverse_fn<4, true>(pvc, prof) : bitset_traverse_fn<4, false>(pvc, prof);
+    VC_BITSET_CASE(1)
+    VC_BITSET_CASE(2)
+    VC_BITSET_CASE(3)
+    VC_BITSET_CASE(4)
+    VC_BITSET_CASE(5)
+    VC_BITSET_CASE(6)
+    VC_BITSET_CASE(7)
+    default: return stack_only ? bitset_traverse_fn<8, true>(pvc, prof) : bitset_traverse_fn<8, false>(pvc, prof);
   }
+#undef VC_BITSET_CASE
 }
 
 size_t bitset_lds_bytes(int n_max, int words) { return static_cast<size_t>(n_max) * words * 8; }
@@ -803,7 +811,11 @@ hipError_t launch_bitset_greedy(const Params& p, hipStream_t stream) {
     case 1: hipLaunchKernelGGL(bitset_greedy_kernel<1>, grid, dim3(64), lds, stream, p); break;
     case 2: hipLaunchKernelGGL(bitset_greedy_kernel<2>, grid, dim3(64), lds, stream, p); break;
     case 3: hipLaunchKernelGGL(bitset_greedy_kernel<3>, grid, dim3(64), lds, stream, p); break;
-    default: hipLaunchKernelGGL(bitset_greedy_kernel<4>, grid, dim3(64), lds, stream, p); break;
+    case 4: hipLaunchKernelGGL(bitset_greedy_kernel<4>, grid, dim3(64), lds, stream, p); break;
+    case 5: hipLaunchKernelGGL(bitset_greedy_kernel<5>, grid, dim3(64), lds, stream, p); break;
+    case 6: hipLaunchKernelGGL(bitset_greedy_kernel<6>, grid, dim3(64), lds, stream, p); break;
+    case 7: hipLaunchKernelGGL(bitset_greedy_kernel<7>, grid, dim3(64), lds, stream, p); break;
+    default: hipLaunchKernelGGL(bitset_greedy_kernel<8>, grid, dim3(64), lds, stream, p); break;
   }
   return hipGetLastError();
 }
@@ -823,7 +835,11 @@ hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64
     case 1: hipLaunchKernelGGL(bitset_reduce_kernel<1>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
     case 2: hipLaunchKernelGGL(bitset_reduce_kernel<2>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
     case 3: hipLaunchKernelGGL(bitset_reduce_kernel<3>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
-    default: hipLaunchKernelGGL(bitset_reduce_kernel<4>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
+    case 4: hipLaunchKernelGGL(bitset_reduce_kernel<4>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
+    case 5: hipLaunchKernelGGL(bitset_reduce_kernel<5>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
+    case 6: hipLaunchKernelGGL(bitset_reduce_kernel<6>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
+    case 7: hipLaunchKernelGGL(bitset_reduce_kernel<7>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
+    default: hipLaunchKernelGGL(bitset_reduce_kernel<8>, dim3(1), dim3(64), lds, stream, p, deg, s, bound); break;
   }
   return hipGetLastError();
 }

@@ -607,7 +607,7 @@ __global__ void prepare_kernel(Params p, DevResult* res, int64_t vertices, int64
                        end < beg || end > in.nnz;
       if (bad) atomicMin(&p.ist[j].err_row, v);
       if (p.words && !bad) {
-        uint64_t row[4] = {0, 0, 0, 0};
+        uint64_t row[kMaxBitsetWords] = {};
         for (int e = beg; e < end; ++e) {
           const int u = ci[e];
           if (u >= 0 && u < in.n) row[u >> 6] |= 1ull << (u & 63);

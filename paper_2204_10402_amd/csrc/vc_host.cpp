@@ -228,14 +228,15 @@ int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, i
   return VC_OK;
 }
 
-// Kernel family of a graph: bitset kernels with ceil(n/64) words up to 256 vertices unless
-// the caller asks for degree arrays (0).
+// Kernel family of a graph: bitset kernels with ceil(n/64) words up to kAutoBitsetN vertices
+// (up to kMaxBitsetN when the caller asks for them), else degree arrays (0).
 int choose_words(vc_ctx* ctx, int32_t n, int32_t flags, int32_t* words) {
   const bool force_bits = flags & VC_OPT_BITSETS;
   const bool force_arrays = flags & (VC_OPT_DEGREE_ARRAYS | VC_OPT_GLOBAL_NODES);
   if (force_bits && n > vc::kMaxBitsetN)
-    return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_BITSETS needs n <= 256");
-  *words = (!force_arrays && n <= vc::kMaxBitsetN) ? (std::max(n, 1) + 63) / 64 : 0;
+    return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_BITSETS needs n <= 512");
+  const bool bits = force_bits || (!force_arrays && n <= vc::kAutoBitsetN);
+  *words = bits ? (std::max(n, 1) + 63) / 64 : 0;
   return VC_OK;
 }
 

@@ -201,7 +201,13 @@ hipError_t set_lds_limit(size_t lds_bytes);
 hipError_t launch_max_greedy(const Params& p, int32_t* out, hipStream_t stream);
 
 // vc_bitset.hip: graphs of at most kMaxBitsetN vertices
-constexpr int kMaxBitsetN = 256;
+constexpr int kMaxBitsetN = 512;
+constexpr int kMaxBitsetWords = 8;  // ceil(kMaxBitsetN / 64)
+// Largest n that takes the bitset kernels by default. Wider bitsets (5 to 8 words) hold so many
+// registers that fewer wavefronts stay resident: they were up to 2.3 times faster than the
+// degree-array kernels on searches of ~20,000 nodes, slower on 10^5-10^6 nodes and on batches
+// and request streams of graphs settled near the root, so they are used only on request.
+constexpr int kAutoBitsetN = 256;
 hipError_t launch_bitset_greedy(const Params& p, hipStream_t stream);
 hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStream_t stream);
 hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,

@@ -46,7 +46,7 @@ struct Request {
 // the stored node size of its kernel family.
 int64_t footprint(int32_t n, int32_t problem, int32_t k, int32_t wg_per_request) {
   const int64_t depth = problem == VC_PROBLEM_PVC ? std::min<int64_t>(k, n) + 1 : n;
-  const int64_t node = n <= vc::kMaxBitsetN ? vc::bitset_stride((std::max(n, 1) + 63) / 64) * 4
+  const int64_t node = n <= vc::kAutoBitsetN ? vc::bitset_stride((std::max(n, 1) + 63) / 64) * 4
                                             : static_cast<int64_t>(vc::array_stride(n)) * 4;
   return std::min<int64_t>(wg_per_request, 256) * depth * node;
 }

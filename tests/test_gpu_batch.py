@@ -42,7 +42,8 @@ def check_cover(g, cover, size):
 
 
 def mixed_graphs(seed, count=24, n_hi=300):
-    """Small random graphs of every kernel family: 1..4 bitset words and degree arrays."""
+    """Small random graphs of 1..4 bitset words and degree arrays (the batch tests also run
+    them all on the degree-array kernels by flag)."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(count):
@@ -52,10 +53,12 @@ def mixed_graphs(seed, count=24, n_hi=300):
     return out
 
 
+@pytest.mark.parametrize("kernel", ["auto", "degree_arrays"])
 @pytest.mark.parametrize("seed", range(4))
-def test_mvc_batch_matches_oracle(solver, oracle_lib, seed):
+def test_mvc_batch_matches_oracle(solver, oracle_lib, seed, kernel):
+    import paper_2204_10402_amd as vc
     gs = mixed_graphs(seed)
-    res = solver.mvc_batch(gs)
+    res = solver.mvc_batch(gs, vc.Options(flags=KERNELS[kernel]))
     for i, g in enumerate(gs):
         o = oracle.mvc(g)
         assert res.status[i] == 0
@@ -77,12 +80,14 @@ def test_mvc_batch_single_workgroup_node_parity(solver, oracle_lib, kernel):
         check_cover(g, res.cover_of(i), o.size)
 
 
+@pytest.mark.parametrize("kernel", ["auto", "degree_arrays"])
 @pytest.mark.parametrize("seed", range(3))
-def test_pvc_batch_decisions_and_no_node_counts(solver, oracle_lib, seed):
+def test_pvc_batch_decisions_and_no_node_counts(solver, oracle_lib, seed, kernel):
+    import paper_2204_10402_amd as vc
     gs = mixed_graphs(100 + seed, count=20, n_hi=200)
     taus = [oracle.mvc(g).size for g in gs]
     ks = [max(t - (i % 3), 0) for i, t in enumerate(taus)]  # tau, tau-1, tau-2 in turn
-    res = solver.pvc_batch(gs, ks)
+    res = solver.pvc_batch(gs, ks, vc.Options(flags=KERNELS[kernel]))
     for i, g in enumerate(gs):
         want = ks[i] >= taus[i]
         assert res.status[i] == 0
@@ -100,11 +105,18 @@ def test_planted_batch_full_size(solver, oracle_lib):
     """4,096 planted-cover PVC instances (n uniform in [40, 400], average degree in [3, 12],
     |C| = 0.3n, k = |C| for even i and |C| - 1 for odd i) in one call: every decision equals
     the oracle's; no-instances visit exactly the oracle's nodes."""
+    import paper_2204_10402_amd as vc
     batch = G.planted_batch(4096, 0)
     gs = [g for g, _ in batch]
     ks = [k for _, k in batch]
     res = solver.pvc_batch(gs, ks)
     assert (res.status == 0).all()
+    # the instances above 256 vertices on the degree-array kernels too
+    wide = [i for i, g in enumerate(gs) if g.n > 256]
+    arr = solver.pvc_batch([gs[i] for i in wide], [ks[i] for i in wide],
+                           vc.Options(flags=vc.OPT_DEGREE_ARRAYS))
+    assert (arr.status == 0).all()
+    assert [bool(x) for x in arr.yes] == [bool(res.yes[i]) for i in wide]
     for i, (g, k) in enumerate(batch):
         o = oracle.pvc(g, k)
         assert bool(res.yes[i]) == o.yes, i
@@ -197,7 +209,7 @@ def test_empty_batch_and_bad_arguments(solver):
         solver.pvc_batch([G.path(4)], [-1])
     assert ei.value.code == vc.ERR_INVALID_ARG
     with pytest.raises(vc.VCError) as ei:
-        solver.mvc_batch([G.path(300)], vc.Options(flags=vc.OPT_BITSETS))
+        solver.mvc_batch([G.path(600)], vc.Options(flags=vc.OPT_BITSETS))
     assert ei.value.code == vc.ERR_INVALID_ARG
 
 

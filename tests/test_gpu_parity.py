@@ -36,7 +36,7 @@ def solver(torch_cuda):
     s.close()
 
 
-# kernel families: bitsets (n <= 256), degree arrays with the node in LDS, and degree arrays
+# kernel families: bitsets (n <= 512), degree arrays with the node in LDS, and degree arrays
 # with the node in device memory (chosen automatically only when the node does not fit in LDS)
 # degree_arrays stages small graphs' CSR in LDS; csr_global reads it from device memory
 KERNELS = {"bitsets": 0x40, "degree_arrays": 0x20, "csr_global": 0x420, "global_nodes": 0x200}
@@ -163,7 +163,7 @@ def test_reduce_fixpoint_parity(solver, oracle_lib, torch_cuda, seed, kernel):
     torch = torch_cuda
     rng = np.random.default_rng(900 + seed)
     n = [12, 40, 63, 64, 65, 130, 200, 256, 700][seed % 9]
-    if kernel == "bitsets" and n > 256:
+    if kernel == "bitsets" and n > 512:
         n = 193
     g = G.random_small(n, 900 + seed) if n <= 40 else G.erdos_renyi(n, float(rng.uniform(0.02, 0.1)), seed)
     deg, s = random_consistent_state(g, rng, float(rng.uniform(0.0, 0.4)))
@@ -413,6 +413,52 @@ def test_invalid_entry_deep_in_a_large_graph(solver, kind):
     assert r.size[0] == r.size[2] == solver.mvc(good).size
 
 
+@pytest.mark.parametrize("n", [257, 320, 384, 448, 511, 512])
+@pytest.mark.parametrize("family", ["planted", "er"])
+def test_wide_bitsets_match_oracle(solver, oracle_lib, n, family):
+    """Bitset nodes of 5 to 8 words (257 <= n <= 512, on request): the
+    oracle's answers; one workgroup visits the oracle's tree node for node; PVC-no visits it
+    with the full grid too; the default family gives the same answers."""
+    if family == "planted":
+        g = G.planted_cover(n, int(0.3 * n), 4 * n, 0.75, 900 + n)
+    else:
+        g = G.erdos_renyi(n, 3.0 / n, 900 + n)
+    bits = KERNELS["bitsets"]
+    o = oracle.mvc(g, node_cap=200000)
+    r = solver.mvc(g, opts(flags=bits))
+    assert r.stats["bitset_words"] == (n + 63) // 64
+    assert r.size == o.size
+    check_cover(g, r.cover, o.size)
+    one = solver.mvc(g, single_wg(bits))
+    assert one.size == o.size and one.stats["nodes"] == o.nodes
+    k = o.size - 1
+    want = oracle.pvc(g, k, node_cap=200000)
+    p = solver.pvc(g, k, opts(flags=bits))
+    assert not p.yes and p.stats["nodes"] == want.nodes
+    yes = solver.pvc(g, o.size, opts(flags=bits))
+    assert yes.yes and yes.size <= o.size
+    check_cover(g, yes.cover, yes.size)
+    auto = solver.mvc(g)
+    assert auto.size == o.size and auto.stats["bitset_words"] == 0
+
+
+@pytest.mark.parametrize("flags", [0, 0x40])
+def test_batch_across_all_bitset_widths(solver, oracle_lib, flags):
+    """One batch over 1 to 8 bitset words (by default: 1 to 4 words and degree arrays above
+    256 vertices): PVC-no node counts per graph equal the oracle's."""
+    import paper_2204_10402_amd as vc
+    sizes = [40, 100, 150, 230, 300, 350, 430, 500] + ([600] if flags == 0 else [])
+    gs = [G.erdos_renyi(n, 3.0 / n, 1700 + n) for n in sizes]
+    taus = [oracle.mvc(g, node_cap=200000).size for g in gs]
+    ks = [t - 1 for t in taus]
+    r = solver.pvc_batch(gs, ks, vc.Options(flags=flags))
+    assert list(r.status) == [0] * len(gs) and not r.yes.any()
+    for g, k, nodes in zip(gs, ks, r.nodes):
+        assert nodes == oracle.pvc(g, k, node_cap=200000).nodes
+    m = solver.mvc_batch(gs, vc.Options(flags=flags))
+    assert list(m.size) == taus
+
+
 def test_node_budget(solver, oracle_lib):
     import paper_2204_10402_amd as vc
     g = G.random_regular(120, 5, 0)
@@ -430,7 +476,7 @@ def test_bad_options(solver):
             solver.mvc(G.path(4), o)
         assert ei.value.code == vc.ERR_INVALID_ARG
     with pytest.raises(vc.VCError) as ei:
-        solver.mvc(G.path(300), vc.Options(flags=vc.OPT_BITSETS))
+        solver.mvc(G.path(600), vc.Options(flags=vc.OPT_BITSETS))
     assert ei.value.code == vc.ERR_INVALID_ARG
 
 
