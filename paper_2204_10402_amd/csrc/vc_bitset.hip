@@ -508,7 +508,10 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   clk.begin();
 
   constexpr int kStride = bits_stride<W>();
-  int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * kStride;
+  // Lane 0 alone writes and reads stack entries, in program order, so the ring needs no
+  // barrier in LDS either.
+  int32_t* stack = p.stack_lds ? reinterpret_cast<int32_t*>(adj_lds + static_cast<size_t>(p.n_max) * W)
+                               : p.stacks + static_cast<size_t>(wg) * p.depth_cap * kStride;
   // The stack is a ring of depth_cap entries holding [bot, top): pops take the top, donations
   // take the bottom (the oldest deferred child, nearest its sub-tree root). Every entry belongs
   // to the instance of the sub-tree being walked.
@@ -804,6 +807,11 @@ size_t bitset_lds_bytes(int n_max, int words) { return static_cast<size_t>(n_max
 
 int bitset_stride(int words) { return ((2 * words + 2) + 3) & ~3; }
 
+size_t bitset_traverse_lds_bytes(const Params& p) {
+  const size_t stack = p.stack_lds ? static_cast<size_t>(p.depth_cap) * bitset_stride(p.words) * 4 : 0;
+  return bitset_lds_bytes(p.n_max, p.words) + stack;
+}
+
 hipError_t launch_bitset_greedy(const Params& p, hipStream_t stream) {
   const size_t lds = bitset_lds_bytes(p.n_max, p.words);
   const dim3 grid(p.num_inst < 65535 ? p.num_inst : 65535);
@@ -825,7 +833,7 @@ hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStrea
   void* kargs[] = {&args};
   // plain launch; see launch_traverse for why co-residency is not required
   return hipLaunchKernel(bitset_fn(p.words, pvc, prof, p.start_depth > 0), dim3(p.num_wg),
-                         dim3(64), kargs, bitset_lds_bytes(p.n_max, p.words), stream);
+                         dim3(64), kargs, bitset_traverse_lds_bytes(p), stream);
 }
 
 hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,
@@ -844,9 +852,9 @@ hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64
   return hipGetLastError();
 }
 
-hipError_t bitset_occupancy(int words, bool pvc, bool prof, int n_max, int* blocks_per_cu) {
+hipError_t bitset_occupancy(int words, bool pvc, bool prof, size_t lds, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bitset_fn(words, pvc, prof),
-                                                      64, bitset_lds_bytes(n_max, words));
+                                                      64, lds);
 }
 
 }  // namespace vc

@@ -222,7 +222,7 @@ int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, i
     *out = it->second;
     return VC_OK;
   }
-  if (words) VC_HIP(ctx, vc::bitset_occupancy(words, pvc, prof, n_max, out));
+  if (words) VC_HIP(ctx, vc::bitset_occupancy(words, pvc, prof, lds, out));
   else VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, global_node, ws, lds, out));
   ctx->occupancy[key] = *out;
   return VC_OK;
@@ -613,6 +613,18 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.stacks = static_cast<int32_t*>(ctx->stacks.ptr);
     p.depth_cap = g.depth_cap;
     p.num_wg = pl.num_wg;
+    p.stack_lds = 0;
+    if (g.words) {
+      // A bitset node is a few dozen bytes: keep the stack ring in LDS when it fits there
+      // (within the default 64 KB) without lowering the launch's residency, so a pop is an LDS
+      // read instead of a dependent device-memory load.
+      p.stack_lds = 1;
+      const size_t lds = vc::bitset_traverse_lds_bytes(p);
+      int occ = 0;
+      if (lds <= 65536 && (rc2 = occupancy(ctx, g.words, pvc, prof, 64, lds, g.n_max, &occ)))
+        return rc2;
+      if (static_cast<int64_t>(occ) * ctx->prop.multiProcessorCount < pl.num_wg) p.stack_lds = 0;
+    }
     ctx->last_num_wg = pl.num_wg;
     VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi], st));
     if (g.words) VC_HIP(ctx, vc::launch_bitset_traverse(pvc, prof, p, st));

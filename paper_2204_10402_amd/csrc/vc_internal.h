@@ -139,6 +139,8 @@ struct Params {
   int32_t nnz_max;      // largest nnz of this launch (sizes the LDS copy of col_idx)
   int32_t* gnodes;      // degree-array kernels with the node in device memory: one stride-word
                         // slot per workgroup (nullptr: the node lives in LDS)
+  int32_t stack_lds;    // bitset kernels: 1 = each workgroup's stack ring lives in LDS after the
+                        // adjacency matrix (depth_cap nodes), 0 = in `stacks`
   int32_t pvc;          // 1: PVC (instances stop once answered), 0: MVC
   int32_t start_depth;  // > 0: StackOnly traversal of instance 0 from this depth; 0: hybrid
 };
@@ -212,8 +214,12 @@ hipError_t launch_bitset_greedy(const Params& p, hipStream_t stream);
 hipError_t launch_bitset_traverse(bool pvc, bool prof, const Params& p, hipStream_t stream);
 hipError_t launch_bitset_reduce(const Params& p, int32_t* deg, int32_t* s, int64_t bound,
                                 hipStream_t stream);
-hipError_t bitset_occupancy(int words, bool pvc, bool prof, int n_max, int* blocks_per_cu);
+// Resident workgroups per CU of a bitset traversal launch with `lds` bytes of dynamic LDS.
+hipError_t bitset_occupancy(int words, bool pvc, bool prof, size_t lds, int* blocks_per_cu);
+// Dynamic LDS of the bitset kernels: the adjacency matrix (and, for a traversal launch with
+// stack_lds, the stack ring after it).
 size_t bitset_lds_bytes(int n_max, int words);
+size_t bitset_traverse_lds_bytes(const Params& p);
 int bitset_stride(int words);
 
 }  // namespace vc
