@@ -524,6 +524,8 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   int max_depth = 0;
   uint32_t headers = 0;  // node headers read so far
   uint32_t so_path = 0;  // StackOnly: the current path index
+  int seen_inst = -1;    // MVC: the instance whose best was last read, and that best
+  int32_t seen_best = 0;
   Live<W> L;
 
   for (;;) {
@@ -647,14 +649,32 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     }
 
     // node header: the instance's flags and current best (one load), and every 16 nodes the
-    // launch-wide stop (idle workgroups also look at it while they wait for work)
-    const uint64_t h = uniform64(inst_header(p, cur));
+    // launch-wide stop (idle workgroups also look at it while they wait for work). The loads
+    // are issued here and waited for after the reduction, which runs meanwhile with the bound
+    // known before them: k (PVC), or the best this instance's header showed at this
+    // workgroup's previous node, lowered by the covers this workgroup has found since (MVC).
+    // An older best is only a weaker bound: once the header arrives, the reduction continues
+    // under the current one, and the stop test uses it. After a switch of instance the first
+    // header is waited for before the reduction. With one workgroup the two bounds always
+    // agree.
+    const uint64_t hraw = inst_header(p, cur);
+    const bool poll = (headers++ & 15) == 0;
+    const int32_t abort_raw = poll ? load_relaxed(ctr_i32(p, kAbort)) : 0;
+    const int32_t open_raw = (PVC && poll) ? load_relaxed(ctr_i32(p, kOpen)) : 1;
+    if (!PVC && seen_inst != cur) {
+      seen_best = static_cast<int32_t>(static_cast<uint32_t>(uniform64(hraw)));
+      seen_inst = cur;
+    }
+    const int64_t early = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(seen_best) - 1;
+    reduce_bits<W>(r, L, adj_lds, early, p.rules);
+
+    const uint64_t h = uniform64(hraw);
     const int32_t state = static_cast<int32_t>(h >> 32);
-    const int stop = (headers++ & 15) == 0
-                         ? __builtin_amdgcn_readfirstlane(search_stopped(p) ? 1 : 0) : 0;
+    const int stop = __builtin_amdgcn_readfirstlane((abort_raw != 0 || open_raw == 0) ? 1 : 0);
     const int drop = (state & kInstOutOfBudget) | (PVC ? (state & kInstFound) : 0);
     const int32_t best = static_cast<int32_t>(static_cast<uint32_t>(h));
-    clk.charge(kActOther);
+    if (!PVC) seen_best = best;
+    clk.charge(kActReduce);
     if (stop) break;
     if (drop) {  // answered or out of budget: drop this node and the rest of the sub-tree
       have = false;
@@ -670,8 +690,10 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     }
 
     const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(best) - 1;
-    reduce_bits<W>(r, L, adj_lds, bound, p.rules);
-    clk.charge(kActReduce);
+    if (!PVC && bound < early) {
+      reduce_bits<W>(r, L, adj_lds, bound, p.rules);
+      clk.charge(kActReduce);
+    }
 
     const int64_t rr = bound - L.s;
     if (rr < 0) {
@@ -688,6 +710,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
       continue;
     }
     if (edges == 0) {  // a vertex cover of size |S|
+      if (!PVC && L.s < seen_best) seen_best = L.s;
       int won = 0;
       if (tid == 0) won = bits_claim<PVC>(p, cur, L.s);
       if (__builtin_amdgcn_readfirstlane(won)) {
