@@ -46,6 +46,10 @@ struct vc_ctx {
   std::map<std::tuple<int, int, int, int, int, size_t>, int> occupancy;
   // autotuner choices: (bitset words, pvc, flags, log2 n_max, log2 instances) -> knobs
   std::map<std::tuple<int, int, int, int, int>, std::tuple<int, int, int>> tuned;
+  // A second context (own stream, worklist, counters, stacks) on which a batch's degree-array
+  // launch runs while its bitset launches run on this one; created on first use.
+  vc_ctx* aux = nullptr;
+  vc_ctx* stats_src = nullptr;  // the context holding the last traversal's per-workgroup stats
 };
 
 namespace {
@@ -508,12 +512,40 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     g.entries += in.nnz;
   }
   hipStream_t st = ctx->stream;
+  // A batch with both kernel families runs its degree-array launch on the auxiliary context
+  // (first, as the longest) while the bitset launches follow on this one: the two persistent
+  // launches share the device instead of queueing behind each other. Not when the caller
+  // already runs launches side by side on shares of the grid (vc_options.grid_share).
+  const bool use_aux = !stack_only && ng >= 2 && groups.back().words == 0 &&
+                       !(o && o->grid_share > 0);
+  if (use_aux && !ctx->aux) {
+    vc_ctx* a = nullptr;
+    if ((rc = vc_create(&a, ctx->device, nullptr)) != VC_OK)
+      return fail(ctx, rc, "could not create the auxiliary launch context");
+    ctx->aux = a;
+  }
+  auto lane = [&](int32_t gi) -> vc_ctx* {
+    return use_aux && groups[gi].words == 0 ? ctx->aux : ctx;
+  };
 
   if (m > 0) {
     if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
-    if ((rc = ensure_events(ctx, 2 * static_cast<size_t>(ng) + 2))) return rc;
+    if ((rc = ensure_events(ctx, 2 * static_cast<size_t>(ng) + 4))) return rc;
+    if (ctx->aux) {
+      // whatever an earlier call left on the auxiliary stream (an error return does not wait
+      // for it) finishes before this call's table overwrites the meta buffer
+      VC_HIP(ctx, hipEventRecord(ctx->ev[2 * ng + 3], ctx->aux->stream));
+      VC_HIP(ctx, hipStreamWaitEvent(st, ctx->ev[2 * ng + 3], 0));
+    }
+    if (use_aux &&
+        (rc = ensure(ctx, ctx->aux->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t))))
+      return rc;
     // one copy in: instance table, fresh per-instance state and work counters
     VC_HIP(ctx, hipMemcpyAsync(dev, host, L.res, hipMemcpyHostToDevice, st));
+    if (use_aux) {
+      VC_HIP(ctx, hipEventRecord(ctx->ev[2 * ng + 2], st));
+      VC_HIP(ctx, hipStreamWaitEvent(ctx->aux->stream, ctx->ev[2 * ng + 2], 0));
+    }
   }
   uint8_t* covers = out.cover_dev;
   if (!covers && total_n > 0) {
@@ -535,18 +567,29 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   // the knobs of `go` and, if thr_div > 0, a donation threshold of num_wg / thr_div.
   auto run_group = [&](int32_t gi, const vc_options* go, int thr_div, bool final) -> int {
     Group& g = groups[gi];
+    vc_ctx* lc = lane(gi);
+    const hipStream_t gst = lc->stream;
     int rc2;
+    vc_options shared = go ? *go : vc_options{};
+    if (use_aux) {
+      // Two launches side by side, each on a share of the co-resident grid; the rest stays free
+      // for the short validation and check kernels of the other stream. Full grids starved them
+      // (the degree-array launch holds its CUs to the end); a third for the degree-array launch,
+      // which waits for work much of the time, and half for the bitset launches measured best.
+      shared.grid_share = std::max(shared.grid_share, 1) * (g.words ? 2 : 3);
+      go = &shared;
+    }
     if ((rc2 = plan_launch(ctx, pvc, g.n_max, g.nnz_max, g.words, go, g.pl))) return rc2;
     Plan& pl = g.pl;
     if (thr_div > 0)
       pl.threshold = static_cast<uint32_t>(std::min<int64_t>(
           std::max<int64_t>(16, pl.num_wg / thr_div), static_cast<int64_t>(pl.cap) - 2 * pl.num_wg));
     const size_t stride_b = static_cast<size_t>(pl.stride) * sizeof(int32_t);
-    if ((rc2 = ensure(ctx, ctx->payload, static_cast<size_t>(pl.cap) * stride_b))) return rc2;
-    if ((rc2 = ensure(ctx, ctx->seq, static_cast<size_t>(pl.cap) * sizeof(uint32_t)))) return rc2;
-    if ((rc2 = ensure(ctx, ctx->wg_stats, static_cast<size_t>(pl.num_wg) * sizeof(vc::WgStats)))) return rc2;
+    if ((rc2 = ensure(ctx, lc->payload, static_cast<size_t>(pl.cap) * stride_b))) return rc2;
+    if ((rc2 = ensure(ctx, lc->seq, static_cast<size_t>(pl.cap) * sizeof(uint32_t)))) return rc2;
+    if ((rc2 = ensure(ctx, lc->wg_stats, static_cast<size_t>(pl.num_wg) * sizeof(vc::WgStats)))) return rc2;
     if (g.words &&
-        (rc2 = ensure(ctx, ctx->bits, static_cast<size_t>(g.vertices) * g.words * sizeof(uint64_t))))
+        (rc2 = ensure(ctx, lc->bits, static_cast<size_t>(g.vertices) * g.words * sizeof(uint64_t))))
       return rc2;
     Params& p = params[gi];
     p = Params{};
@@ -560,26 +603,26 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     p.work = d_work + g.begin;
     p.rp_all = b.rp;
     p.ci_all = b.ci;
-    p.payload = static_cast<int32_t*>(ctx->payload.ptr);
-    p.seq = static_cast<uint32_t*>(ctx->seq.ptr);
-    p.ctr = static_cast<int32_t*>(ctx->ctr.ptr);
+    p.payload = static_cast<int32_t*>(lc->payload.ptr);
+    p.seq = static_cast<uint32_t*>(lc->seq.ptr);
+    p.ctr = static_cast<int32_t*>(lc->ctr.ptr);
     p.covers = covers;
-    p.wg_stats = static_cast<vc::WgStats*>(ctx->wg_stats.ptr);
+    p.wg_stats = static_cast<vc::WgStats*>(lc->wg_stats.ptr);
     p.node_budget = o ? o->node_budget : 0;
     // report often enough that the whole grid overshoots a budget by at most about half
     p.budget_chunk = std::max<int64_t>(1, std::min<int64_t>(1024, p.node_budget / (2 * pl.num_wg)));
     p.q_cap = pl.cap;
     p.q_threshold = pl.threshold;
     p.num_wg = pl.num_wg;
-    p.bits = g.words ? static_cast<uint64_t*>(ctx->bits.ptr) : nullptr;
+    p.bits = g.words ? static_cast<uint64_t*>(lc->bits.ptr) : nullptr;
     p.words = g.words;
     p.rp_lds = pl.rp_lds;
     p.pvc = pvc ? 1 : 0;
     if (pl.global_node) {
       // one node slot per traversal workgroup and per greedy workgroup
       const int64_t slots = std::max<int64_t>(pl.num_wg, std::min<int64_t>(g.end - g.begin, 65535));
-      if ((rc2 = ensure(ctx, ctx->gnodes, static_cast<size_t>(slots) * stride_b))) return rc2;
-      p.gnodes = static_cast<int32_t*>(ctx->gnodes.ptr);
+      if ((rc2 = ensure(ctx, lc->gnodes, static_cast<size_t>(slots) * stride_b))) return rc2;
+      p.gnodes = static_cast<int32_t*>(lc->gnodes.ptr);
     }
     if (stack_only) {
       p.start_depth = o->start_depth ? o->start_depth : 12;
@@ -587,19 +630,18 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     }
     DevResult* dres = d_res + gi;
     p.res = dres;
-    ctx->last_num_wg = pl.num_wg;
 
-    VC_HIP(ctx, vc::launch_prepare(p, dres, g.vertices, g.entries, st));
+    VC_HIP(ctx, vc::launch_prepare(p, dres, g.vertices, g.entries, gst));
     if (!pvc) {
       const int gws = g.words ? 64 : static_cast<int>(std::min<int64_t>(1024, round_up(g.n_max, 64)));
       hipEvent_t e0 = ctx->ev[2 * ng], e1 = ctx->ev[2 * ng + 1];
-      VC_HIP(ctx, hipEventRecord(e0, st));
-      if (g.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, st));
-      else VC_HIP(ctx, vc::launch_greedy(p, gws, st));
-      VC_HIP(ctx, hipEventRecord(e1, st));
-      VC_HIP(ctx, vc::launch_max_greedy(p, d_greedy + gi, st));
-      VC_HIP(ctx, hipMemcpyAsync(h_gmax + gi, d_greedy + gi, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-      VC_HIP(ctx, hipStreamSynchronize(st));
+      VC_HIP(ctx, hipEventRecord(e0, gst));
+      if (g.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, gst));
+      else VC_HIP(ctx, vc::launch_greedy(p, gws, gst));
+      VC_HIP(ctx, hipEventRecord(e1, gst));
+      VC_HIP(ctx, vc::launch_max_greedy(p, d_greedy + gi, gst));
+      VC_HIP(ctx, hipMemcpyAsync(h_gmax + gi, d_greedy + gi, sizeof(int32_t), hipMemcpyDeviceToHost, gst));
+      VC_HIP(ctx, hipStreamSynchronize(gst));
       const int32_t gmax = h_gmax[gi];
       float ms = 0.f;
       VC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
@@ -609,8 +651,11 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     } else {
       g.depth_cap = g.k_max + 1;
     }
-    if ((rc2 = size_stacks(ctx, pl, g.depth_cap))) return rc2;
-    p.stacks = static_cast<int32_t*>(ctx->stacks.ptr);
+    if ((rc2 = size_stacks(lc, pl, g.depth_cap))) {
+      if (lc != ctx) ctx->last_error = lc->last_error;
+      return rc2;
+    }
+    p.stacks = static_cast<int32_t*>(lc->stacks.ptr);
     p.depth_cap = g.depth_cap;
     p.num_wg = pl.num_wg;
     p.stack_lds = 0;
@@ -625,12 +670,13 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
         return rc2;
       if (static_cast<int64_t>(occ) * ctx->prop.multiProcessorCount < pl.num_wg) p.stack_lds = 0;
     }
-    ctx->last_num_wg = pl.num_wg;
-    VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi], st));
-    if (g.words) VC_HIP(ctx, vc::launch_bitset_traverse(pvc, prof, p, st));
-    else VC_HIP(ctx, vc::launch_traverse(pvc, prof, p, pl.wg_size, st));
-    VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi + 1], st));
-    if (final) VC_HIP(ctx, vc::launch_finalize(p, g.vertices, g.entries, dres, st));
+    lc->last_num_wg = pl.num_wg;
+    ctx->stats_src = lc;
+    VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi], gst));
+    if (g.words) VC_HIP(ctx, vc::launch_bitset_traverse(pvc, prof, p, gst));
+    else VC_HIP(ctx, vc::launch_traverse(pvc, prof, p, pl.wg_size, gst));
+    VC_HIP(ctx, hipEventRecord(ctx->ev[2 * gi + 1], gst));
+    if (final) VC_HIP(ctx, vc::launch_finalize(p, g.vertices, g.entries, dres, gst));
     return VC_OK;
   };
 
@@ -638,10 +684,11 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   auto reset_group = [&](int32_t gi) -> int {
     const Group& g = groups[gi];
     const size_t cnt = static_cast<size_t>(g.end - g.begin);
+    const hipStream_t gst = lane(gi)->stream;
     VC_HIP(ctx, hipMemcpyAsync(d_ist + g.begin, h_ist + g.begin, cnt * sizeof(InstState),
-                               hipMemcpyHostToDevice, st));
+                               hipMemcpyHostToDevice, gst));
     VC_HIP(ctx, hipMemcpyAsync(d_work + g.begin, reinterpret_cast<int32_t*>(host + L.work) + g.begin,
-                               cnt * sizeof(int32_t), hipMemcpyHostToDevice, st));
+                               cnt * sizeof(int32_t), hipMemcpyHostToDevice, gst));
     return VC_OK;
   };
 
@@ -649,7 +696,9 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_STACK_ONLY takes one graph per call");
   const bool explicit_knobs = o && (o->wg_size || o->num_wg || o->wl_capacity || o->wl_threshold);
   const bool autotune = (flags & VC_OPT_AUTOTUNE) && !explicit_knobs && !stack_only;
-  for (int32_t gi = 0; gi < ng; ++gi) {
+  for (int32_t step = 0; step < ng; ++step) {
+    // with the auxiliary context, the degree-array group (the last) goes first
+    const int32_t gi = use_aux ? (step == 0 ? ng - 1 : step - 1) : step;
     Group& g = groups[gi];
     vc_options go = o ? *o : vc_options{};
     int thr_div = 0;
@@ -682,7 +731,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
           rc = run_group(gi, &t, std::get<2>(c), false);
           if (rc == VC_ERR_INVALID_ARG || rc == VC_ERR_NO_MEMORY) continue;  // does not fit
           if (rc) return rc;
-          VC_HIP(ctx, hipStreamSynchronize(st));
+          VC_HIP(ctx, hipStreamSynchronize(lane(gi)->stream));
           float ms = 0.f;
           VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * gi], ctx->ev[2 * gi + 1]));
           if (best_ms == 0.f || ms < best_ms) {
@@ -700,6 +749,10 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     }
     if ((rc = run_group(gi, &go, thr_div, true))) return rc;
   }
+  if (use_aux) {  // the degree-array launch and its cover check end before the copy out
+    VC_HIP(ctx, hipEventRecord(ctx->ev[2 * ng + 3], ctx->aux->stream));
+    VC_HIP(ctx, hipStreamWaitEvent(st, ctx->ev[2 * ng + 3], 0));
+  }
 
   // one copy out: per-instance state, work counters and result blocks
   if (m > 0)
@@ -708,11 +761,18 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   if (out.cover_host && total_n > 0)
     VC_HIP(ctx, hipMemcpyAsync(h_cover, covers, static_cast<size_t>(total_n), hipMemcpyDeviceToHost, st));
   VC_HIP(ctx, hipStreamSynchronize(st));
+  // traversal time: the launches' durations added up, or with the auxiliary context (whose
+  // degree-array launch starts first) the span until the last traversal ends
   double kernel_ms = 0.0;
   for (int32_t gi = 0; gi < ng; ++gi) {
     float ms = 0.f;
-    VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * gi], ctx->ev[2 * gi + 1]));
-    kernel_ms += ms;
+    if (use_aux) {
+      VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * (ng - 1)], ctx->ev[2 * gi + 1]));
+      kernel_ms = std::max(kernel_ms, static_cast<double>(ms));
+    } else {
+      VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * gi], ctx->ev[2 * gi + 1]));
+      kernel_ms += ms;
+    }
   }
 
   // launch-wide failures end the whole call
@@ -1000,14 +1060,15 @@ int vc_wg_loads(vc_ctx* ctx, int64_t* nodes_out, int64_t* cycles_out, int32_t ma
   int rc = enter(ctx);
   if (rc) return rc;
   if (!count_out || max < 0) return fail(ctx, VC_ERR_INVALID_ARG, "NULL argument");
-  const int32_t cnt = ctx->wg_stats.ptr ? ctx->last_num_wg : 0;
+  const vc_ctx* src = ctx->stats_src ? ctx->stats_src : ctx;
+  const int32_t cnt = src->wg_stats.ptr ? src->last_num_wg : 0;
   *count_out = cnt;
   const int32_t take = std::min(cnt, max);
   if (take > 0) {
     std::vector<vc::WgStats> w(static_cast<size_t>(take));
-    VC_HIP(ctx, hipMemcpyAsync(w.data(), ctx->wg_stats.ptr, w.size() * sizeof(vc::WgStats),
-                               hipMemcpyDeviceToHost, ctx->stream));
-    VC_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    VC_HIP(ctx, hipMemcpyAsync(w.data(), src->wg_stats.ptr, w.size() * sizeof(vc::WgStats),
+                               hipMemcpyDeviceToHost, src->stream));
+    VC_HIP(ctx, hipStreamSynchronize(src->stream));
     for (int32_t i = 0; i < take; ++i) {
       const vc::WgStats& x = w[static_cast<size_t>(i)];
       if (nodes_out) nodes_out[i] = x.nodes;
@@ -1048,6 +1109,7 @@ int vc_create(vc_ctx** ctx_out, int device, void* hip_stream) {
 int vc_destroy(vc_ctx* ctx) {
   if (!ctx) return VC_OK;
   (void)hipSetDevice(ctx->device);
+  if (ctx->aux) vc_destroy(ctx->aux);  // first: its launches read this context's buffers
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
   DevBuf* bufs[] = {&ctx->rp,     &ctx->ci,       &ctx->meta,     &ctx->payload, &ctx->seq,
                     &ctx->ctr,    &ctx->stacks,   &ctx->covers,   &ctx->wg_stats, &ctx->scratch,
