@@ -153,8 +153,9 @@ typedef struct {
   int32_t bitset_words;   /* 64-bit words per node with the bitset kernels; 0 = degree arrays
                              (batches: the largest used) */
   int32_t node_bytes;     /* bytes of one search node's state (batches: the largest) */
-  double kernel_ms;       /* traversal kernel time (HIP events on the context stream; batches:
-                             summed over the launches) */
+  double kernel_ms;       /* traversal kernel time (HIP events; batches: summed over the
+                             launches, or, when a batch's degree-array launch runs beside its
+                             bitset launches, the span from its start to the last one's end) */
   double greedy_ms;       /* greedy kernel time (MVC) */
   double total_ms;        /* wall clock of the whole call */
   /* With VC_OPT_PROFILE, shader-clock cycles summed over the workgroups (paper §V-D):
@@ -168,7 +169,10 @@ typedef struct {
 } vc_stats;
 
 /* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to run on, or NULL
- * for a stream owned by the context. */
+ * for a stream owned by the context. A batch holding graphs of both kernel families (unless
+ * vc_options.grid_share is set) also runs on a second stream and workspace that the context
+ * creates on first use and owns; the call still returns only when all of its work is done,
+ * ordered after earlier work on `hip_stream` and before later work there. */
 int vc_create(vc_ctx **ctx_out, int device, void *hip_stream);
 
 /* Release the context, its workspace and its own stream. NULL is accepted. */
@@ -178,7 +182,7 @@ int vc_destroy(vc_ctx *ctx);
 const char *vc_strerror(int status);
 
 /* Per-workgroup statistics of the context's last traversal launch (the last kernel family of
- * a batch), for up to `max` workgroups; *count_out = the grid size. `nodes_out` (may be NULL):
+ * a batch launched), for up to `max` workgroups; *count_out = the grid size. `nodes_out` (may be NULL):
  * nodes visited by each workgroup (with VC_OPT_STACK_ONLY including its walks down from the
  * root). `cycles_out` (may be NULL; 10 per workgroup, in the order of vc_stats.cycles):
  * its activity clocks, zero unless the launch ran with VC_OPT_PROFILE. */

@@ -258,9 +258,9 @@ __device__ __forceinline__ void remove_neighbourhood_bits(Live<W>& L, int v,
 
 // A stored node: W words of live bits (lo/hi 32-bit halves), |S|, then one word packing the
 // pending vertex plus one (10 bits, n <= 512) with the instance (launch-local index below
-// 2^22, shifted left 10), padding to a multiple of four words. Lane 0 writes and reads every stored node, so
-// a node pushed on the workgroup's stack is read back in program order, and the worklist
-// publishes it with one release store.
+// 2^22, shifted left 10), padding to a multiple of four words. Lane 0 writes and reads every
+// stored node, so a node pushed on the workgroup's stack is read back in program order, and
+// the worklist publishes it with one release store.
 template <int W>
 constexpr int bits_stride() {
   return ((2 * W + 2) + 3) & ~3;
