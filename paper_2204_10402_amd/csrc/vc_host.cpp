@@ -530,7 +530,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
 
   if (m > 0) {
     if ((rc = ensure(ctx, ctx->ctr, vc::kNumCounters * vc::kCounterStride * sizeof(int32_t)))) return rc;
-    if ((rc = ensure_events(ctx, 2 * static_cast<size_t>(ng) + 4))) return rc;
+    if ((rc = ensure_events(ctx, 4 * static_cast<size_t>(ng) + 4))) return rc;
     if (ctx->aux) {
       // whatever an earlier call left on the auxiliary stream (an error return does not wait
       // for it) finishes before this call's table overwrites the meta buffer
@@ -634,20 +634,24 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     VC_HIP(ctx, vc::launch_prepare(p, dres, g.vertices, g.entries, gst));
     if (!pvc) {
       const int gws = g.words ? 64 : static_cast<int>(std::min<int64_t>(1024, round_up(g.n_max, 64)));
-      hipEvent_t e0 = ctx->ev[2 * ng], e1 = ctx->ev[2 * ng + 1];
+      hipEvent_t e0 = ctx->ev[2 * ng + 4 + 2 * gi], e1 = ctx->ev[2 * ng + 5 + 2 * gi];
       VC_HIP(ctx, hipEventRecord(e0, gst));
       if (g.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, gst));
       else VC_HIP(ctx, vc::launch_greedy(p, gws, gst));
       VC_HIP(ctx, hipEventRecord(e1, gst));
-      VC_HIP(ctx, vc::launch_max_greedy(p, d_greedy + gi, gst));
-      VC_HIP(ctx, hipMemcpyAsync(h_gmax + gi, d_greedy + gi, sizeof(int32_t), hipMemcpyDeviceToHost, gst));
-      VC_HIP(ctx, hipStreamSynchronize(gst));
-      const int32_t gmax = h_gmax[gi];
-      float ms = 0.f;
-      VC_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
-      if (final) greedy_ms += ms;
-      // bound = best - 1: a path branches at most best - 1 times (each branching adds to s)
-      g.depth_cap = std::max(gmax, 1);
+      if (g.words) {
+        // A path branches at most best - 1 <= n - 1 times. Bitset nodes are a few dozen bytes,
+        // so their stacks are provisioned for that bound straight away instead of waiting on
+        // the host for the largest greedy size (the traversal reads each instance's greedy
+        // size from its state as the first best).
+        g.depth_cap = std::max(g.n_max, 1);
+      } else {
+        VC_HIP(ctx, vc::launch_max_greedy(p, d_greedy + gi, gst));
+        VC_HIP(ctx, hipMemcpyAsync(h_gmax + gi, d_greedy + gi, sizeof(int32_t), hipMemcpyDeviceToHost, gst));
+        VC_HIP(ctx, hipStreamSynchronize(gst));
+        // bound = best - 1: a path branches at most best - 1 times (each branching adds to s)
+        g.depth_cap = std::max(h_gmax[gi], 1);
+      }
     } else {
       g.depth_cap = g.k_max + 1;
     }
@@ -761,6 +765,12 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   if (out.cover_host && total_n > 0)
     VC_HIP(ctx, hipMemcpyAsync(h_cover, covers, static_cast<size_t>(total_n), hipMemcpyDeviceToHost, st));
   VC_HIP(ctx, hipStreamSynchronize(st));
+  if (!pvc)
+    for (int32_t gi = 0; gi < ng; ++gi) {
+      float ms = 0.f;
+      VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * ng + 4 + 2 * gi], ctx->ev[2 * ng + 5 + 2 * gi]));
+      greedy_ms += ms;
+    }
   // traversal time: the launches' durations added up, or with the auxiliary context (whose
   // degree-array launch starts first) the span until the last traversal ends
   double kernel_ms = 0.0;
