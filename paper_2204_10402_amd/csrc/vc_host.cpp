@@ -723,9 +723,15 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
         } else {
           Plan base;
           if ((rc = plan_launch(ctx, pvc, g.n_max, g.nnz_max, 0, &go, base))) return rc;
+          // and, for fewer instances than the grid holds, one workgroup per instance (no idle
+          // workgroups polling the worklist; donations then have no takers but for finished
+          // instances' workgroups)
+          const int64_t count = g.end - g.begin;
           for (int ws : {base.wg_size / 2, base.wg_size, base.wg_size * 2})
-            if (ws >= 64 && ws <= 1024)
+            if (ws >= 64 && ws <= 1024) {
               for (int div : {8, 1}) cand.emplace_back(ws, 0, div);
+              if (count < base.num_wg) cand.emplace_back(ws, static_cast<int>(count), 8);
+            }
         }
         float best_ms = 0.f;
         std::tuple<int, int, int> best = cand[0];
@@ -733,15 +739,26 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
           vc_options t = go;
           t.wg_size = std::get<0>(c);
           t.num_wg = std::get<1>(c);
-          if ((rc = reset_group(gi))) return rc;
-          rc = run_group(gi, &t, std::get<2>(c), false);
-          if (rc == VC_ERR_INVALID_ARG || rc == VC_ERR_NO_MEMORY) continue;  // does not fit
-          if (rc) return rc;
-          VC_HIP(ctx, hipStreamSynchronize(lane(gi)->stream));
-          float ms = 0.f;
-          VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * gi], ctx->ev[2 * gi + 1]));
-          if (best_ms == 0.f || ms < best_ms) {
-            best_ms = ms;
+          // two trial launches per candidate, the faster one counts (one launch's noise is as
+          // large as the differences that matter)
+          float cand_ms = 0.f;
+          bool fits = true;
+          for (int trial = 0; trial < 2 && fits; ++trial) {
+            if ((rc = reset_group(gi))) return rc;
+            rc = run_group(gi, &t, std::get<2>(c), false);
+            if (rc == VC_ERR_INVALID_ARG || rc == VC_ERR_NO_MEMORY) {  // does not fit
+              fits = false;
+              break;
+            }
+            if (rc) return rc;
+            VC_HIP(ctx, hipStreamSynchronize(lane(gi)->stream));
+            float ms = 0.f;
+            VC_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev[2 * gi], ctx->ev[2 * gi + 1]));
+            if (trial == 0 || ms < cand_ms) cand_ms = ms;
+          }
+          if (!fits) continue;
+          if (best_ms == 0.f || cand_ms < best_ms) {
+            best_ms = cand_ms;
             best = c;
           }
         }
