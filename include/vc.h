@@ -166,6 +166,18 @@ typedef struct {
    * [6] degree-one decisions, [7] degree-two-triangle decisions, [8] high-degree decisions,
    * [9] removing the decided vertices. Zero without VC_OPT_PROFILE. */
   int64_t cycles[10];
+  /* Where the search moved its nodes (paper §IV-A, §IV-E: stacks and worklist), in bytes of
+   * node state (the degree array or live-vertex bitset, |S|, pending vertex, instance):
+   * hbm_node_bytes counts worklist enqueues and dequeues and the pushes and pops of stacks in
+   * device memory; lds_node_bytes the pushes and pops of stacks held in LDS. graph_bytes
+   * estimates the graph data workgroups copied from device memory into LDS or registers on
+   * taking an instance (bitset adjacency rows, or the staged CSR of the degree-array kernels),
+   * from each launch's mean graph size. */
+  int64_t hbm_node_bytes;
+  int64_t lds_node_bytes;
+  int64_t graph_bytes;
+  int32_t stack_lds;      /* 1 if a traversal launch kept its stacks in LDS */
+  int32_t launches;       /* traversal launches of the call (one per kernel family) */
 } vc_stats;
 
 /* Create a context on HIP device `device`. `hip_stream` is a hipStream_t to run on, or NULL

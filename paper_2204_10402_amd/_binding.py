@@ -91,7 +91,9 @@ class _Stats(ctypes.Structure):
                 ("n", ctypes.c_int32), ("bitset_words", ctypes.c_int32),
                 ("node_bytes", ctypes.c_int32), ("kernel_ms", ctypes.c_double),
                 ("greedy_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
-                ("cycles", ctypes.c_int64 * 10)]
+                ("cycles", ctypes.c_int64 * 10), ("hbm_node_bytes", ctypes.c_int64),
+                ("lds_node_bytes", ctypes.c_int64), ("graph_bytes", ctypes.c_int64),
+                ("stack_lds", ctypes.c_int32), ("launches", ctypes.c_int32)]
 
 
 @dataclass

@@ -12,6 +12,7 @@ import os
 import shutil
 import subprocess
 import sys
+import tempfile
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -29,24 +30,41 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libvc.so)")
 
 
-def command(out: str) -> list[str]:
-    return [
-        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
-        # no packed-FP32 instructions anywhere (the library has no float arithmetic anyway)
-        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-        "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
-        f"-I{INCLUDE}", f"-I{CSRC}",
-        *[os.path.join(CSRC, s) for s in SOURCES],
-        "-o", out,
-    ]
+FLAGS = [
+    f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-pthread",
+    # no packed-FP32 instructions anywhere (the library has no float arithmetic anyway)
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-result", "-Wno-unused-command-line-argument",
+    f"-I{INCLUDE}", f"-I{CSRC}",
+]
+
+
+def compile_command(src: str, obj: str) -> list[str]:
+    return [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+
+
+def link_command(objs: list[str], out: str) -> list[str]:
+    return [hipcc(), *FLAGS, "-shared", *objs, "-o", out]
 
 
 def build(verbose: bool = False) -> str:
+    """Compile every source to an object file (in parallel, one process per source), then
+    link libvc.so. Objects go to a temporary directory; only the library stays in-tree."""
+    from concurrent.futures import ThreadPoolExecutor
     tmp = LIB + ".tmp"
-    cmd = command(tmp)
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd, cwd=ROOT)
+    with tempfile.TemporaryDirectory(prefix="vc_build_") as work:
+        objs = [os.path.join(work, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+        cmds = [compile_command(s, o) for s, o in zip(SOURCES, objs)]
+        if verbose:
+            for c in cmds:
+                print(" ".join(c), flush=True)
+        with ThreadPoolExecutor(len(cmds)) as ex:
+            for f in [ex.submit(subprocess.check_call, c, cwd=ROOT) for c in cmds]:
+                f.result()
+        cmd = link_command(objs, tmp)
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd, cwd=ROOT)
     os.replace(tmp, LIB)
     return LIB
 

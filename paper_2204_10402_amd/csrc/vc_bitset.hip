@@ -41,10 +41,14 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
   return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+// Lane mask test: bit `lane` of a wavefront-uniform 64-bit mask, used directly as the lane's
+// condition (the mask becomes the lane mask of one v_cndmask; no shift per lane).
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
 // Is this lane's vertex of word wv live?
 template <int W>
 __device__ __forceinline__ bool held_live(const Live<W>& L, int wv) {
-  return (L.bits[wv] >> lane_id()) & 1ull;
+  return lane_in(L.bits[wv]);
 }
 
 // Bit x of a W-word mask (x < 64 W), without indexing the register array at run time.
@@ -56,84 +60,185 @@ __device__ __forceinline__ bool bit_of(const uint64_t (&M)[W], int x) {
   return (word >> (x & 63)) & 1ull;
 }
 
+// Per-lane cached degrees of the held vertices, and a wavefront-uniform cache of degree-two
+// vertices already known to lie in no triangle. Invariant at every rule pass: for each live
+// held vertex v, deg = |N(v) ∩ L| (entries of removed vertices are stale; every use masks them
+// with L). Along one root-to-leaf path vertices are only ever removed, so a vertex that still
+// has degree two still has the same two neighbours, and if they were not adjacent they still
+// are not: no_tri stays valid down a path and is cleared whenever the node is replaced by one
+// that is not its descendant (a pop, a dequeue, a root).
 template <int W>
-__device__ __forceinline__ void held_degrees(const Rows<W>& r, const Live<W>& L, int (&deg)[W]) {
+struct Degrees {
+  int32_t deg[W];
+  uint64_t no_tri[W];
+};
+
+// All degrees from scratch: deg(v) = popcount(adj(v) & L) over W words.
+template <int W>
+__device__ __forceinline__ void degrees_full(const Rows<W>& r, const Live<W>& L, Degrees<W>& D) {
 #pragma unroll
   for (int wv = 0; wv < W; ++wv) {
     int d = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) d += __popcll(r.adj[wv][w] & L.bits[w]);
-    deg[wv] = d;
+    D.deg[wv] = d;
   }
 }
 
-// Remove the marked set F: |S| grows by its size (§IV-B, with the |S| counter).
+// The held vertices adjacent to vertex w*64 + b lose one degree. W is a compile-time word of
+// the caller's unrolled loop; b is uniform, so the half select is a scalar condition.
 template <int W>
-__device__ __forceinline__ int remove_set(Live<W>& L, const uint64_t (&F)[W]) {
+__device__ __forceinline__ void drop_neighbour(const Rows<W>& r, int w, int b, Degrees<W>& D) {
+#pragma unroll
+  for (int wv = 0; wv < W; ++wv) {
+    const uint64_t a = r.adj[wv][w];
+    const uint32_t half = (b & 32) ? static_cast<uint32_t>(a >> 32) : static_cast<uint32_t>(a);
+    D.deg[wv] -= static_cast<int32_t>(__builtin_amdgcn_ubfe(half, static_cast<uint32_t>(b & 31), 1u));
+  }
+}
+
+// Remove the set F from the node: |S| grows by the number of live vertices in F (§IV-B, with
+// the |S| counter) and the degrees follow, one neighbour at a time for a few removed vertices,
+// from scratch for more.
+template <int W>
+__device__ __forceinline__ int remove_set(const Rows<W>& r, Live<W>& L, const uint64_t (&F)[W],
+                                          Degrees<W>& D) {
+  uint64_t R[W];
   int removed = 0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    removed += __popcll(F[w] & L.bits[w]);
-    L.bits[w] &= ~F[w];
+    R[w] = F[w] & L.bits[w];
+    removed += __popcll(R[w]);
+    L.bits[w] &= ~R[w];
   }
   L.s += removed;
+  if (removed > 2 * W) {
+    degrees_full(r, L, D);
+  } else if (removed > 0) {
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      uint64_t m = R[w];
+      while (m) {
+        const int b = __ffsll(static_cast<long long>(m)) - 1;
+        m &= m - 1;
+        drop_neighbour(r, w, b, D);
+      }
+    }
+  }
   return removed;
 }
 
 // Degree-one rule (§II-B, tie-breaks §IV-D). A live u is removed if it has a degree-one live
 // neighbour c and either deg(u) != 1 or u < c (for deg(u) = 1, c is its only neighbour).
+// With H the live vertices next to a degree-one vertex: every u in H of degree other than
+// one goes; a u in H of degree one forms a mutual pair with its only neighbour, and only the
+// smaller of the two goes.
 template <int W>
-__device__ __forceinline__ int pass_degree_one(const Rows<W>& r, Live<W>& L) {
-  int deg[W];
-  held_degrees(r, L, deg);
+__device__ __forceinline__ int pass_degree_one(const Rows<W>& r, Live<W>& L, Degrees<W>& D) {
   uint64_t D1[W];
   uint64_t any = 0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    D1[w] = ballot(held_live(L, w) && deg[w] == 1);
+    D1[w] = ballot(D.deg[w] == 1) & L.bits[w];
     any |= D1[w];
   }
   if (!any) return 0;
-  const int lane = lane_id();
-  uint64_t F[W];
+  uint64_t F[W], M[W];
+  uint64_t mutual = 0;
 #pragma unroll
   for (int wv = 0; wv < W; ++wv) {
-    bool has = false, bigger = false;
+    uint32_t near = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
-      const uint64_t m = r.adj[wv][w] & L.bits[w] & D1[w];
-      has |= m != 0;
-      if (w > wv) bigger |= m != 0;
-      if (w == wv) bigger |= ((m >> lane) >> 1) != 0;  // a neighbour with a larger id
+      const uint64_t m = r.adj[wv][w] & D1[w];
+      near |= static_cast<uint32_t>(m) | static_cast<uint32_t>(m >> 32);
     }
-    F[wv] = ballot(held_live(L, wv) && has && (deg[wv] != 1 || bigger));
+    const uint64_t H = ballot(near != 0) & L.bits[wv];
+    F[wv] = H & ~D1[wv];
+    M[wv] = H & D1[wv];
+    mutual |= M[wv];
   }
-  return remove_set(L, F);
+  if (mutual) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int wv = 0; wv < W; ++wv) {
+      bool bigger = false;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const uint64_t m = r.adj[wv][w] & D1[w];
+        if (w > wv) bigger |= m != 0;
+        if (w == wv) bigger |= ((m >> lane) >> 1) != 0;  // a neighbour with a larger id
+      }
+      F[wv] |= ballot(lane_in(M[wv]) && bigger);
+    }
+  }
+  return remove_set(r, L, F, D);
+}
+
+// Lowest set bit of a W-word mask (the mask is not empty): the minimum over its 32-bit halves
+// of (first set bit | 32 * half index), where an empty half gives 0xFFFFFFFF.
+template <int W>
+__device__ __forceinline__ int lowest_bit(const uint64_t (&N)[W]) {
+  uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    const uint32_t lo = static_cast<uint32_t>(N[w]), hi = static_cast<uint32_t>(N[w] >> 32);
+    const uint32_t flo = lo ? (static_cast<uint32_t>(__builtin_ctz(lo)) | (64u * w)) : 0xFFFFFFFFu;
+    const uint32_t fhi = hi ? (static_cast<uint32_t>(__builtin_ctz(hi)) | (64u * w + 32u)) : 0xFFFFFFFFu;
+    best = min(best, min(flo, fhi));
+  }
+  return static_cast<int>(best);
 }
 
 // Degree-two-triangle rule (§II-B, tie-break §IV-D). A live v of degree two whose neighbours
 // a < b are adjacent fires unless a or b is a degree-two vertex with a smaller id; the live
-// neighbours of firing vertices (exactly their a and b) are removed.
+// neighbours of firing vertices (exactly their a and b) are removed. Degree-two vertices not
+// yet in D.no_tri are checked (row a of the adjacency matrix against {a, b}); the pass ends
+// there unless one of them lies in a triangle.
 template <int W>
-__device__ __forceinline__ int pass_triangle(const Rows<W>& r, Live<W>& L,
+__device__ __forceinline__ int pass_triangle(const Rows<W>& r, Live<W>& L, Degrees<W>& D,
                                              const uint64_t* __restrict__ adj_lds) {
-  int deg[W];
-  held_degrees(r, L, deg);
-  uint64_t D2[W];
+  uint64_t D2[W], A[W];
   uint64_t any = 0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    D2[w] = ballot(held_live(L, w) && deg[w] == 2);
-    any |= D2[w];
+    D2[w] = ballot(D.deg[w] == 2) & L.bits[w];
+    any |= D2[w] & ~D.no_tri[w];
   }
   if (!any) return 0;
+  uint64_t anytri = 0;
+#pragma unroll
+  for (int wv = 0; wv < W; ++wv) {
+    const uint64_t check = D2[wv] & ~D.no_tri[wv];
+    A[wv] = 0;
+    if (check) {
+      bool adjacent = false;
+      if (lane_in(check)) {
+        uint64_t N[W];
+#pragma unroll
+        for (int w = 0; w < W; ++w) N[w] = r.adj[wv][w] & L.bits[w];
+        const int a = min(lowest_bit<W>(N), 64 * W - 1);  // N holds exactly two bits
+        uint32_t hit = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          const uint64_t x = adj_lds[a * W + w] & N[w];
+          hit |= static_cast<uint32_t>(x) | static_cast<uint32_t>(x >> 32);
+        }
+        adjacent = hit != 0;
+      }
+      A[wv] = ballot(adjacent) & check;
+      D.no_tri[wv] |= check & ~A[wv];
+      anytri |= A[wv];
+    }
+  }
+  if (!anytri) return 0;
+  // A degree-two vertex lies in a triangle: the firing decisions with their tie-breaks.
   const int lane = lane_id();
   uint64_t Fire[W];
-  uint64_t anyfire = 0;
 #pragma unroll
   for (int wv = 0; wv < W; ++wv) {
     bool fires = false;
-    if ((D2[wv] >> lane) & 1ull) {
+    if (lane_in(A[wv])) {
       const int v = wv * 64 + lane;
       int a = -1, b = -1;
 #pragma unroll
@@ -145,42 +250,39 @@ __device__ __forceinline__ int pass_triangle(const Rows<W>& r, Live<W>& L,
           if (a < 0) a = x; else b = x;
         }
       }
-      const bool adjacent = (adj_lds[a * W + (b >> 6)] >> (b & 63)) & 1ull;
       const bool a2 = bit_of<W>(D2, a);
       const bool b2 = bit_of<W>(D2, b);
-      fires = adjacent && !((a2 && a < v) || (b2 && b < v));
+      fires = !((a2 && a < v) || (b2 && b < v));
     }
     Fire[wv] = ballot(fires);
-    anyfire |= Fire[wv];
   }
-  if (!anyfire) return 0;
   uint64_t F[W];
 #pragma unroll
   for (int wu = 0; wu < W; ++wu) {
     bool near = false;
 #pragma unroll
     for (int w = 0; w < W; ++w) near |= (r.adj[wu][w] & L.bits[w] & Fire[w]) != 0;
-    F[wu] = ballot(held_live(L, wu) && near);
+    F[wu] = ballot(near) & L.bits[wu];
   }
-  return remove_set(L, F);
+  return remove_set(r, L, F, D);
 }
 
-// High-degree rule (§II-B): degree above r = bound - |S|.
+// High-degree rule (§II-B): degree above r = bound - |S| (r >= 0 here).
 template <int W>
-__device__ __forceinline__ int pass_high_degree(const Rows<W>& r, Live<W>& L, int64_t rr) {
-  int deg[W];
-  held_degrees(r, L, deg);
+__device__ __forceinline__ int pass_high_degree(const Rows<W>& r, Live<W>& L, Degrees<W>& D,
+                                                int64_t rr) {
+  const int32_t r32 = rr > 0x7FFFFFFF ? 0x7FFFFFFF : static_cast<int32_t>(rr);
   uint64_t F[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) F[w] = ballot(held_live(L, w) && static_cast<int64_t>(deg[w]) > rr);
-  return remove_set(L, F);
+  for (int w = 0; w < W; ++w) F[w] = ballot(D.deg[w] > r32) & L.bits[w];
+  return remove_set(r, L, F, D);
 }
 
 // The rules until the graph stops changing or |S| exceeds bound (same order as the
 // degree-array kernels).
 template <int W>
-__device__ __forceinline__ void reduce_bits(const Rows<W>& r, Live<W>& L, const uint64_t* adj_lds,
-                            int64_t bound, int rules) {
+__device__ __forceinline__ void reduce_bits(const Rows<W>& r, Live<W>& L, Degrees<W>& D,
+                                            const uint64_t* adj_lds, int64_t bound, int rules) {
   // A pass is skipped when nothing has been removed since it last found nothing (its inputs
   // are unchanged), as in the degree-array kernels.
   int changes = 0, quiet1 = -1, quiet2 = -1, quiet3 = -1;
@@ -188,7 +290,7 @@ __device__ __forceinline__ void reduce_bits(const Rows<W>& r, Live<W>& L, const 
     const int32_t s0 = L.s;
     if (s0 > bound) return;
     if ((rules & kRuleDeg1) && quiet1 != changes) {
-      if (pass_degree_one(r, L)) {
+      if (pass_degree_one(r, L, D)) {
         ++changes;
         if (L.s > bound) return;
       } else {
@@ -196,7 +298,7 @@ __device__ __forceinline__ void reduce_bits(const Rows<W>& r, Live<W>& L, const 
       }
     }
     if ((rules & kRuleTri) && quiet2 != changes) {
-      if (pass_triangle(r, L, adj_lds)) {
+      if (pass_triangle(r, L, D, adj_lds)) {
         ++changes;
         if (L.s > bound) return;
       } else {
@@ -204,55 +306,78 @@ __device__ __forceinline__ void reduce_bits(const Rows<W>& r, Live<W>& L, const 
       }
     }
     if ((rules & kRuleHigh) && quiet3 != changes) {
-      if (pass_high_degree(r, L, bound - L.s)) ++changes;
+      if (pass_high_degree(r, L, D, bound - L.s)) ++changes;
       else quiet3 = changes;
     }
     if (L.s == s0) return;
   }
 }
 
-// Live vertex of maximum degree (smallest id on ties) and the sum of live degrees.
+// Live vertex of maximum degree (smallest id on ties) and the sum of live degrees, from the
+// cached degrees: one 32-bit key (degree << 16 | 0xFFFF - id) per vertex, reduced with DPP.
 template <int W>
-__device__ __forceinline__ void bits_max_degree(const Rows<W>& r, const Live<W>& L, int& vmax,
+__device__ __forceinline__ void bits_max_degree(const Live<W>& L, const Degrees<W>& D, int& vmax,
                                                 int32_t& degsum) {
-  int deg[W];
-  held_degrees(r, L, deg);
-  uint64_t key = 0;
+  uint32_t key = 0;
   int32_t sum = 0;
   const int lane = lane_id();
 #pragma unroll
   for (int wv = 0; wv < W; ++wv) {
-    if (held_live(L, wv)) {
-      sum += deg[wv];
-      const uint64_t k = (static_cast<uint64_t>(deg[wv]) << 32) |
-                         static_cast<uint32_t>(~static_cast<uint32_t>(wv * 64 + lane));
-      key = key > k ? key : k;
-    }
+    const bool live = held_live(L, wv);
+    const uint32_t k = (static_cast<uint32_t>(D.deg[wv]) << 16) |
+                       (0xFFFFu - static_cast<uint32_t>(wv * 64 + lane));
+    key = max(key, live ? k : 0u);
+    sum += live ? D.deg[wv] : 0;
   }
-  key = wave_max(key);
+  key = wave_max32(key);
   degsum = wave_sum(sum);
-  vmax = static_cast<int>(~static_cast<uint32_t>(key));
+  vmax = static_cast<int>(0xFFFFu - (key & 0xFFFFu));
 }
 
+// The v_max child: v joins the cover.
 template <int W>
-__device__ __forceinline__ void remove_vertex_bits(Live<W>& L, int v) {
-  const uint64_t bit = 1ull << (v & 63);
-  const int wv = v >> 6;
+__device__ __forceinline__ void remove_vertex_bits(const Rows<W>& r, Live<W>& L, Degrees<W>& D,
+                                                   int v) {
+  const int wv = v >> 6, b = v & 63;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    const uint64_t keep = ~(bit & (0ull - static_cast<uint64_t>(wv == w)));  // all ones but v
-    L.bits[w] &= keep;
+    if (w == wv) {
+      L.bits[w] &= ~(1ull << b);
+      drop_neighbour(r, w, b, D);
+    }
   }
   L.s += 1;
 }
 
+// The N(v) child: every live neighbour of v joins the cover.
 template <int W>
-__device__ __forceinline__ void remove_neighbourhood_bits(Live<W>& L, int v,
+__device__ __forceinline__ void remove_neighbourhood_bits(const Rows<W>& r, Live<W>& L,
+                                                          Degrees<W>& D, int v,
                                                           const uint64_t* adj_lds) {
   uint64_t F[W];
 #pragma unroll
   for (int w = 0; w < W; ++w) F[w] = uniform64(adj_lds[v * W + w]);
-  remove_set(L, F);
+  remove_set(r, L, F, D);
+}
+
+// A node taken from a stack or the worklist (or a root): its removal of N(pending) goes to
+// the live set first, then the degrees are computed once.
+template <int W>
+__device__ __forceinline__ void enter_node(const Rows<W>& r, Live<W>& L, Degrees<W>& D,
+                                           int pending, const uint64_t* adj_lds) {
+  if (pending >= 0) {
+    int removed = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const uint64_t f = uniform64(adj_lds[pending * W + w]) & L.bits[w];
+      removed += __popcll(f);
+      L.bits[w] &= ~f;
+    }
+    L.s += removed;
+  }
+  degrees_full(r, L, D);
+#pragma unroll
+  for (int w = 0; w < W; ++w) D.no_tri[w] = 0;
 }
 
 
@@ -445,15 +570,17 @@ __global__ void __launch_bounds__(64) bitset_greedy_kernel(Params p) {
     Rows<W> r;
     const int n = load_adjacency<W>(p, j, adj_lds, r);
     Live<W> L;
+    Degrees<W> D;
     root_bits<W>(L, n);
+    enter_node<W>(r, L, D, -1, adj_lds);
     const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
     for (;;) {
-      reduce_bits<W>(r, L, adj_lds, unbounded, kRuleDeg1 | kRuleTri);
+      reduce_bits<W>(r, L, D, adj_lds, unbounded, kRuleDeg1 | kRuleTri);
       int vmax;
       int32_t degsum;
-      bits_max_degree<W>(r, L, vmax, degsum);
+      bits_max_degree<W>(L, D, vmax, degsum);
       if (degsum == 0) break;
-      remove_vertex_bits<W>(L, vmax);
+      remove_vertex_bits<W>(r, L, D, vmax);
     }
     write_cover<W>(p.covers + p.inst[j].vtx_off, L, n);
     if (threadIdx.x == 0) {
@@ -487,13 +614,20 @@ __device__ __forceinline__ void bits_publish(const Params& p, int j, int32_t s) 
   }
 }
 
-__device__ __forceinline__ void bits_report_nodes(const Params& p, int j, int64_t count) {
-  if (count <= 0) return;
+// Lane 0: add `count` nodes to instance j; returns 1 if that used up the instance's budget.
+__device__ __forceinline__ int bits_report_nodes(const Params& p, int j, int64_t count) {
+  if (count <= 0) return 0;
   unsigned long long* total = reinterpret_cast<unsigned long long*>(&p.ist[j].nodes);
   const unsigned long long before = fetch_add(total, static_cast<unsigned long long>(count));
-  if (p.node_budget > 0 && static_cast<int64_t>(before) + count >= p.node_budget)
+  if (p.node_budget > 0 && static_cast<int64_t>(before) + count >= p.node_budget) {
     atomicOr(&p.ist[j].state, kInstOutOfBudget);
+    return 1;
+  }
+  return 0;
 }
+
+// Nodes between two reads of the node header (a power of two).
+constexpr uint32_t kPollNodes = 8;
 
 // The hybrid traversal (§IV-A, Fig. 4; termination §IV-C) on bitset nodes, over every instance
 // of the launch (as traverse_kernel).
@@ -516,6 +650,9 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   // take the bottom (the oldest deferred child, nearest its sub-tree root). Every entry belongs
   // to the instance of the sub-tree being walked.
   int top = 0, bot = 0;
+  // ring slots of top and bot, kept reduced modulo depth_cap (no division per push or pop)
+  int top_slot = 0, bot_slot = 0;
+  const int cap = p.depth_cap;
   bool have = false, holding = false;
   int cur = -1, cur_n = 0;
   int32_t cur_k = 0, cur_vtx = 0;
@@ -524,16 +661,21 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   int max_depth = 0;
   uint32_t headers = 0;  // node headers read so far
   uint32_t so_path = 0;  // StackOnly: the current path index
-  int seen_inst = -1;    // MVC: the instance whose best was last read, and that best
-  int32_t seen_best = 0;
+  int seen_inst = -1;    // the instance whose header was last read, and what it showed:
+  int32_t seen_best = 0; // MVC: its best (lowered by this workgroup's own covers)
+  bool inst_done = false;  // it is answered (PVC) or out of budget
+  int32_t seen_count = 0;  // worklist count at the last header
+  int stop = 0;            // the launch is being stopped
   Live<W> L;
+  Degrees<W> D;
 
   for (;;) {
     if (!have) {
       int pending, inst;
       if (top > bot) {
         --top;
-        bits_load<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, pending, inst);
+        top_slot = top_slot == 0 ? cap - 1 : top_slot - 1;
+        bits_load<W>(stack + static_cast<size_t>(top_slot) * kStride, L, pending, inst);
         ++pops;
         clk.charge(kActAcquire);
       } else if constexpr (SO) {
@@ -560,6 +702,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           break;
         }
         root_bits<W>(L, cur_n);
+        enter_node<W>(r, L, D, -1, adj_lds);
         pending = -1;
         bool reached = true;
         for (int d = 0; d < p.start_depth && reached; ++d) {
@@ -574,11 +717,11 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
                                     : static_cast<int64_t>(static_cast<int32_t>(h)) - 1;
           ++nodes;
           if (owner) ++unreported;
-          reduce_bits<W>(r, L, adj_lds, bound, p.rules);
+          reduce_bits<W>(r, L, D, adj_lds, bound, p.rules);
           const int64_t rr = bound - L.s;
           int vmax = 0;
           int32_t degsum = 0;
-          if (rr >= 0) bits_max_degree<W>(r, L, vmax, degsum);
+          if (rr >= 0) bits_max_degree<W>(L, D, vmax, degsum);
           const int64_t edges = degsum / 2;
           if (rr < 0 || ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > rr * rr)) {
             reached = false;
@@ -594,9 +737,9 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
             }
             reached = false;
           } else if ((so_path >> d) & 1u) {
-            remove_neighbourhood_bits<W>(L, vmax, adj_lds);
+            remove_neighbourhood_bits<W>(r, L, D, vmax, adj_lds);
           } else {
-            remove_vertex_bits<W>(L, vmax);
+            remove_vertex_bits<W>(r, L, D, vmax);
           }
         }
         clk.charge(kActAcquire);
@@ -643,55 +786,68 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         }
         clk.charge(kActOther);
       }
-      if (pending >= 0) remove_neighbourhood_bits<W>(L, pending, adj_lds);
+      enter_node<W>(r, L, D, pending, adj_lds);
       clk.charge(kActBranch);
       have = true;
     }
 
-    // node header: the instance's flags and current best (one load), and every 16 nodes the
-    // launch-wide stop (idle workgroups also look at it while they wait for work). The loads
+    // Node header, read every kPollNodes nodes (and at the first node after a switch of
+    // instance): the instance's flags and current best (one load), the worklist count for the
+    // donation test, and the launch-wide stop. These are agent-scope loads of lines every
+    // workgroup reads, so they are kept off most nodes: a stale best is only a weaker bound
+    // (MVC), a stale count only a stale filter (the reservation re-reads it), and a workgroup
+    // that answers its instance or exhausts its budget knows it at once (inst_done). The loads
     // are issued here and waited for after the reduction, which runs meanwhile with the bound
-    // known before them: k (PVC), or the best this instance's header showed at this
-    // workgroup's previous node, lowered by the covers this workgroup has found since (MVC).
-    // An older best is only a weaker bound: once the header arrives, the reduction continues
-    // under the current one, and the stop test uses it. After a switch of instance the first
-    // header is waited for before the reduction. With one workgroup the two bounds always
-    // agree.
-    const uint64_t hraw = inst_header(p, cur);
-    const bool poll = (headers++ & 15) == 0;
-    const int32_t abort_raw = poll ? load_relaxed(ctr_i32(p, kAbort)) : 0;
-    const int32_t open_raw = (PVC && poll) ? load_relaxed(ctr_i32(p, kOpen)) : 1;
-    if (!PVC && seen_inst != cur) {
+    // known before them: k (PVC), or the best this workgroup saw last, lowered by the covers it
+    // found since (MVC); it then continues under the fresh best. With one workgroup the two
+    // bounds always agree.
+    const bool poll = (headers++ & (kPollNodes - 1)) == 0 || seen_inst != cur;
+    uint64_t hraw = 0;
+    int32_t qraw = 0, abort_raw = 0, open_raw = 1;
+    if (poll) {
+      hraw = inst_header(p, cur);
+      if (p.q_threshold > 0) qraw = load_relaxed(ctr_i32(p, kQCount));
+      abort_raw = load_relaxed(ctr_i32(p, kAbort));
+      if (PVC) open_raw = load_relaxed(ctr_i32(p, kOpen));
+    }
+    if (seen_inst != cur) {
+      // a new instance: wait for its header before the reduction
       seen_best = static_cast<int32_t>(static_cast<uint32_t>(uniform64(hraw)));
       seen_inst = cur;
+      inst_done = false;
     }
     const int64_t early = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(seen_best) - 1;
-    reduce_bits<W>(r, L, adj_lds, early, p.rules);
+    reduce_bits<W>(r, L, D, adj_lds, early, p.rules);
 
-    const uint64_t h = uniform64(hraw);
-    const int32_t state = static_cast<int32_t>(h >> 32);
-    const int stop = __builtin_amdgcn_readfirstlane((abort_raw != 0 || open_raw == 0) ? 1 : 0);
-    const int drop = (state & kInstOutOfBudget) | (PVC ? (state & kInstFound) : 0);
-    const int32_t best = static_cast<int32_t>(static_cast<uint32_t>(h));
-    if (!PVC) seen_best = best;
+    if (poll) {
+      const uint64_t h = uniform64(hraw);
+      const int32_t state = static_cast<int32_t>(h >> 32);
+      if ((state & kInstOutOfBudget) || (PVC && (state & kInstFound))) inst_done = true;
+      if (!PVC) seen_best = min(seen_best, static_cast<int32_t>(static_cast<uint32_t>(h)));
+      seen_count = __builtin_amdgcn_readfirstlane(qraw);
+      stop = __builtin_amdgcn_readfirstlane((abort_raw != 0 || open_raw == 0) ? 1 : 0);
+    }
     clk.charge(kActReduce);
     if (stop) break;
-    if (drop) {  // answered or out of budget: drop this node and the rest of the sub-tree
+    if (inst_done) {  // answered or out of budget: drop this node and the rest of the sub-tree
       have = false;
       top = bot;
+      top_slot = bot_slot;
       continue;
     }
 
     ++nodes;
     ++unreported;
     if (p.node_budget > 0 && unreported >= p.budget_chunk) {
-      if (tid == 0) bits_report_nodes(p, cur, unreported);
+      int spent = 0;
+      if (tid == 0) spent = bits_report_nodes(p, cur, unreported);
       unreported = 0;
+      if (__builtin_amdgcn_readfirstlane(spent)) inst_done = true;
     }
 
-    const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(best) - 1;
+    const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(seen_best) - 1;
     if (!PVC && bound < early) {
-      reduce_bits<W>(r, L, adj_lds, bound, p.rules);
+      reduce_bits<W>(r, L, D, adj_lds, bound, p.rules);
       clk.charge(kActReduce);
     }
 
@@ -702,7 +858,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     }
     int vmax;
     int32_t degsum;
-    bits_max_degree<W>(r, L, vmax, degsum);
+    bits_max_degree<W>(L, D, vmax, degsum);
     clk.charge(kActBranch);
     const int64_t edges = degsum / 2;
     if ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > rr * rr) {
@@ -718,6 +874,8 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         __threadfence();
         if (tid == 0) bits_publish<PVC>(p, cur, L.s);
       }
+      // PVC: a cover of size <= k is recorded now, by this workgroup or another one
+      if (PVC) inst_done = true;
       clk.charge(kActOther);
       have = false;
       continue;
@@ -727,13 +885,16 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     // worklist is below its threshold a deferred child is donated: the oldest one on this
     // workgroup's stack if there is one (the largest sub-tree it holds), else this one.
     bool kept_local = true;
-    if (p.q_threshold > 0) {
+    if (p.q_threshold > 0 && seen_count < static_cast<int32_t>(p.q_threshold)) {
       const bool from_stack = top > bot;
       const int32_t* oldest =
-          from_stack ? stack + static_cast<size_t>(bot % p.depth_cap) * kStride : nullptr;
+          from_stack ? stack + static_cast<size_t>(bot_slot) * kStride : nullptr;
       if (bits_enqueue<W>(p, c, L, vmax, oldest, cur)) {
         ++enqueues;
-        if (from_stack) ++bot;
+        if (from_stack) {
+          ++bot;
+          bot_slot = bot_slot + 1 == cap ? 0 : bot_slot + 1;
+        }
         else kept_local = false;
       }
     }
@@ -745,13 +906,14 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         }
         break;
       }
-      bits_store<W>(stack + static_cast<size_t>(top % p.depth_cap) * kStride, L, vmax, cur);
+      bits_store<W>(stack + static_cast<size_t>(top_slot) * kStride, L, vmax, cur);
       ++top;
+      top_slot = top_slot + 1 == cap ? 0 : top_slot + 1;
       ++pushes;
       if (top - bot > max_depth) max_depth = top - bot;
     }
     clk.charge(kActDonate);
-    remove_vertex_bits<W>(L, vmax);
+    remove_vertex_bits<W>(r, L, D, vmax);
     clk.charge(kActBranch);
   }
   clk.end();
@@ -787,13 +949,13 @@ __global__ void __launch_bounds__(64) bitset_reduce_kernel(Params p, int32_t* de
     L.bits[w] = ballot(v < n && deg[v] >= 0);
   }
   L.s = __builtin_amdgcn_readfirstlane(*s);
-  reduce_bits<W>(r, L, adj_lds, bound, p.rules);
-  int d[W];
-  held_degrees(r, L, d);
+  Degrees<W> D;
+  enter_node<W>(r, L, D, -1, adj_lds);
+  reduce_bits<W>(r, L, D, adj_lds, bound, p.rules);
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const int v = w * 64 + lane_id();
-    if (v < n) deg[v] = held_live(L, w) ? d[w] : -1;
+    if (v < n) deg[v] = held_live(L, w) ? D.deg[w] : -1;
   }
   if (threadIdx.x == 0) *s = L.s;
 }

@@ -98,6 +98,18 @@ __device__ __forceinline__ uint64_t wave_max(uint64_t x) {
                 umax64(readlane64(x, 32), readlane64(x, 48)));
 }
 
+__device__ __forceinline__ uint32_t wave_max32(uint32_t x) {
+  x = max(x, dpp<kDppQuadSwap1>(x));
+  x = max(x, dpp<kDppQuadSwap2>(x));
+  x = max(x, dpp<kDppHalfMirror>(x));
+  x = max(x, dpp<kDppMirror>(x));
+  const uint32_t a = max(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 0)),
+                         static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 16)));
+  const uint32_t b = max(static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 32)),
+                         static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(x), 48)));
+  return max(a, b);
+}
+
 __device__ __forceinline__ int lane_id() { return static_cast<int>(threadIdx.x) & 63; }
 __device__ __forceinline__ int wave_id() { return static_cast<int>(threadIdx.x) >> 6; }
 __device__ __forceinline__ int first_lane(uint64_t m) { return __ffsll(static_cast<long long>(m)) - 1; }

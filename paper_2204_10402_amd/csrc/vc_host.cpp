@@ -717,7 +717,8 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
         std::vector<std::tuple<int, int, int>> cand;  // (wg_size, num_wg, threshold divisor)
         cand.emplace_back(0, 0, 0);
         if (g.words) {
-          // up to 16 one-wavefront workgroups per CU (the default plan stops at 8)
+          // up to 16 one-wavefront workgroups per CU (the default plan stops at 8; 20 to 28 per
+          // CU measured slower on the hard MVC batch: more workgroups polling the worklist)
           for (int mult : {1, 2, 4, 8, 12, 16})
             for (int div : {8, 2}) cand.emplace_back(0, mult * cus, div);
         } else {
@@ -889,8 +890,24 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
       sp->depth_cap = std::max(sp->depth_cap, g.depth_cap);
       sp->n = std::max(sp->n, g.n_max);
       sp->bitset_words = std::max(sp->bitset_words, g.words);
-      sp->node_bytes = std::max(sp->node_bytes, g.words ? 8 * g.words + 8 : 4 * (g.n_max + 3));
+      const int32_t nb = g.words ? 8 * g.words + 8 : 4 * (g.n_max + 3);
+      sp->node_bytes = std::max(sp->node_bytes, nb);
       for (int a = 0; a < vc::kNumActivities; ++a) sp->cycles[a] += r.cycles[a];
+      // node copies by where they went: the worklist is in device memory; a stack is in LDS
+      // only for a bitset launch with stack_lds
+      const int64_t stack_copies = r.pushes + r.pops;
+      sp->hbm_node_bytes += static_cast<int64_t>(nb) *
+                            (r.enqueues + r.dequeues + (params[gi].stack_lds ? 0 : stack_copies));
+      if (params[gi].stack_lds) sp->lds_node_bytes += static_cast<int64_t>(nb) * stack_copies;
+      sp->stack_lds |= params[gi].stack_lds;
+      sp->launches += 1;
+      // graph data copied per instance taken, at the launch's mean graph size
+      const double count = static_cast<double>(std::max(g.end - g.begin, 1));
+      const double per_inst =
+          g.words ? 8.0 * g.words * (static_cast<double>(g.vertices) / count)
+                  : (g.pl.rp_lds >= 1 ? 4.0 * (static_cast<double>(g.vertices) / count + 1.0) : 0.0) +
+                        (g.pl.rp_lds == 2 ? 4.0 * static_cast<double>(g.entries) / count : 0.0);
+      sp->graph_bytes += static_cast<int64_t>(per_inst * static_cast<double>(r.instances));
     }
     sp->greedy_size = (!pvc && out.single && m == 1) ? h_ist[0].greedy : -1;
     sp->kernel_ms = kernel_ms;
@@ -1067,7 +1084,7 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
 
 extern "C" {
 
-const char* vc_version(void) { return "0.2.0"; }
+const char* vc_version(void) { return "0.3.0"; }
 
 const char* vc_strerror(int status) {
   switch (status) {

@@ -52,7 +52,7 @@ def test_struct_layouts_match_header():
     from paper_2204_10402_amd import _binding as b
     assert ctypes.sizeof(b._Graph) == 24
     assert ctypes.sizeof(b._Options) == 48
-    assert ctypes.sizeof(b._Stats) == 7 * 8 + 10 * 4 + 3 * 8 + 10 * 8
+    assert ctypes.sizeof(b._Stats) == 7 * 8 + 10 * 4 + 3 * 8 + 10 * 8 + 3 * 8 + 2 * 4
     assert ctypes.sizeof(b._Batch) == 8 + 4 * 8
     assert ctypes.sizeof(b._ServerOptions) == 4 + 4 + 8 + 4 + 3 * 4
     assert ctypes.sizeof(b._Served) == 8 + 6 * 4 + 8 + 3 * 8
