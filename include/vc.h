@@ -52,7 +52,8 @@ extern "C" {
 #define VC_ERR_INVALID_GRAPH (-1) /* CSR breaks the format above (first offending row named) */
 #define VC_ERR_INVALID_ARG (-2)   /* NULL pointer, k < 0, bad option, graph too large for LDS */
 #define VC_ERR_NO_MEMORY (-3)     /* stacks + worklist do not fit in free device memory */
-#define VC_ERR_BUDGET (-4)        /* node budget exhausted before the search ended */
+#define VC_ERR_BUDGET (-4)        /* node budget exhausted, time limit reached or vc_abort
+                                     called before the search ended */
 #define VC_ERR_DEVICE (-5)        /* a HIP runtime call failed, or no usable device */
 #define VC_ERR_INTERNAL (-6)      /* a device-side invariant failed (stack overflow, or a
                                      returned cover failed edge-by-edge verification) */
@@ -117,7 +118,14 @@ typedef struct {
                            run several launches side by side); 0 = all of it */
   int32_t start_depth;  /* with VC_OPT_STACK_ONLY: depth of the sub-trees handed out, 1..24;
                            0 = 12 */
-  int32_t reserved[3];  /* must be zero */
+  int32_t stack_depth;  /* stack entries per workgroup; 0 = the depth bound of §IV-E (enough
+                           for any search). A smaller value is the caller's promise: a
+                           workgroup that would need more stops the call with
+                           VC_ERR_INTERNAL ("stack overflow") */
+  int32_t timeout_ms;   /* > 0: stop each traversal launch after about this many milliseconds
+                           of the device clock (measured from the launch's start, checked every
+                           few nodes and while idle); the call returns VC_ERR_BUDGET. 0: none */
+  int32_t reserved;     /* must be zero */
 } vc_options;
 
 /* A batch of independent graphs, each in the format above, packed one after the other. */
@@ -201,6 +209,14 @@ const char *vc_strerror(int status);
 int vc_wg_loads(vc_ctx *ctx, int64_t *nodes_out, int64_t *cycles_out, int32_t max,
                 int32_t *count_out);
 
+/* Stop the call running on this context, from any thread (the one function that may run while
+ * another call on the context is in progress). The traversal kernels see the request within
+ * about 50 microseconds of the device clock (workgroup 0 reads a host-pinned word; every
+ * workgroup then sees the launch-wide stop at its next look at the control words), every
+ * workgroup exits normally, and the call returns VC_ERR_BUDGET. Calling it when no call runs
+ * has no effect on later calls. */
+int vc_abort(vc_ctx *ctx);
+
 /* Description of the last failure on this context ("" if none). Valid until the next call. */
 const char *vc_last_error(const vc_ctx *ctx);
 
@@ -255,6 +271,52 @@ int vc_pvc_batch_device(vc_ctx *ctx, const vc_batch *batch, const int32_t *k,
                         const vc_options *opts, int32_t *status_out, int32_t *yes_out,
                         int32_t *size_out, uint8_t *cover_dev, int64_t *nodes_out,
                         vc_stats *stats);
+
+/* ---- caller-owned workspace (device memory from the caller, e.g. a torch tensor) ----------
+ * The *_ws forms are the device forms above with every piece of device memory a call needs --
+ * instance table and per-instance state, worklist ring and tickets (§IV-A), per-workgroup
+ * stacks (§IV-E), control words, covers when cover_dev is NULL -- carved from one caller buffer
+ * instead of the context's own allocations, on the context's stream (pass the caller's stream
+ * to vc_create). They allocate no device memory and create no stream; host staging uses the
+ * context's pinned buffer, or ordinary host memory for a batch larger than it. They do not
+ * autotune (vc_options.flags' VC_OPT_AUTOTUNE is ignored: a trial grid need not fit the
+ * workspace), and a batch mixing kernel families runs its launches one after another.
+ * Ownership: the workspace stays the caller's; the library keeps no pointer into it after the
+ * call returns (vc_wg_loads then reports no workgroups). Two calls must not share a workspace
+ * at the same time.
+ *
+ * vc_workspace_bytes: bytes that a *_ws call on one graph of n vertices and nnz CSR entries
+ * needs with the launch knobs of `opts` (the same options the call will take; NULL = automatic)
+ * and `depth` stack entries per workgroup (0: n + 1, enough for MVC and every k). It takes the
+ * larger of the MVC and PVC needs. A smaller workspace still works while the worklist and one
+ * workgroup's stack fit: the grid then shrinks until the stacks fit (the memory bound on
+ * parallelism of §IV-E); else the call fails with VC_ERR_NO_MEMORY.
+ * vc_batch_workspace_bytes: the same for a batch (its count, n and nnz; pointers may be NULL). */
+int vc_workspace_bytes(vc_ctx *ctx, int32_t n, int32_t nnz, int32_t depth,
+                       const vc_options *opts, size_t *bytes_out);
+int vc_batch_workspace_bytes(vc_ctx *ctx, const vc_batch *batch, int32_t depth,
+                             const vc_options *opts, size_t *bytes_out);
+
+/* MVC / PVC (paper §II-A) as vc_mvc_device / vc_pvc_device, in the caller's workspace
+ * (`workspace`: device memory on the context's device, 256-byte aligned, `workspace_bytes`
+ * long). */
+int vc_mvc_device_ws(vc_ctx *ctx, const vc_graph *g, const vc_options *opts, void *workspace,
+                     size_t workspace_bytes, int32_t *size_out, uint8_t *cover_dev,
+                     vc_stats *stats);
+int vc_pvc_device_ws(vc_ctx *ctx, const vc_graph *g, int32_t k, const vc_options *opts,
+                     void *workspace, size_t workspace_bytes, int32_t *yes_out,
+                     int32_t *size_out, uint8_t *cover_dev, vc_stats *stats);
+
+/* Batched MVC / PVC (paper §II-A) as vc_mvc_batch_device / vc_pvc_batch_device, in the caller's
+ * workspace. */
+int vc_mvc_batch_device_ws(vc_ctx *ctx, const vc_batch *batch, const vc_options *opts,
+                           void *workspace, size_t workspace_bytes, int32_t *status_out,
+                           int32_t *size_out, uint8_t *cover_dev, int64_t *nodes_out,
+                           vc_stats *stats);
+int vc_pvc_batch_device_ws(vc_ctx *ctx, const vc_batch *batch, const int32_t *k,
+                           const vc_options *opts, void *workspace, size_t workspace_bytes,
+                           int32_t *status_out, int32_t *yes_out, int32_t *size_out,
+                           uint8_t *cover_dev, int64_t *nodes_out, vc_stats *stats);
 
 /* ---- serving: continuous batching of a request stream ----------------------------------
  * A server owns `workers` threads, each with its own context (device workspace and stream).

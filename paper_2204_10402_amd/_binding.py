@@ -41,7 +41,9 @@ EXPORTS = (
     "vc_mvc", "vc_pvc", "vc_mvc_device", "vc_pvc_device", "vc_greedy_device",
     "vc_reduce_device", "vc_mvc_batch", "vc_pvc_batch", "vc_mvc_batch_device",
     "vc_pvc_batch_device", "vc_server_create", "vc_server_submit", "vc_server_poll",
-    "vc_server_pending", "vc_server_destroy", "vc_wg_loads",
+    "vc_server_pending", "vc_server_destroy", "vc_wg_loads", "vc_abort", "vc_workspace_bytes",
+    "vc_batch_workspace_bytes", "vc_mvc_device_ws", "vc_pvc_device_ws",
+    "vc_mvc_batch_device_ws", "vc_pvc_batch_device_ws",
 )
 
 PROBLEM_MVC = 0
@@ -77,7 +79,8 @@ class _Options(ctypes.Structure):
                 ("wl_capacity", ctypes.c_int32), ("wl_threshold", ctypes.c_int32),
                 ("node_budget", ctypes.c_int64), ("flags", ctypes.c_int32),
                 ("grid_share", ctypes.c_int32), ("start_depth", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("stack_depth", ctypes.c_int32), ("timeout_ms", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class _Stats(ctypes.Structure):
@@ -107,6 +110,8 @@ class Options:
     flags: int = 0
     grid_share: int = 0
     start_depth: int = 0
+    stack_depth: int = 0
+    timeout_ms: int = 0
 
     def _c(self) -> _Options:
         o = _Options()
@@ -114,6 +119,7 @@ class Options:
         o.wl_capacity, o.wl_threshold = self.wl_capacity, self.wl_threshold
         o.node_budget, o.flags = self.node_budget, self.flags
         o.grid_share, o.start_depth = self.grid_share, self.start_depth
+        o.stack_depth, o.timeout_ms = self.stack_depth, self.timeout_ms
         return o
 
 
@@ -183,6 +189,18 @@ def load_library(path: str = LIB_PATH):
         "vc_server_pending": ([vp, i32p, i32p], ctypes.c_int),
         "vc_server_destroy": ([vp], ctypes.c_int),
         "vc_wg_loads": ([vp, vp, vp, i32, i32p], ctypes.c_int),
+        "vc_abort": ([vp], ctypes.c_int),
+        "vc_workspace_bytes": ([vp, i32, i32, i32, op, ctypes.POINTER(ctypes.c_size_t)],
+                               ctypes.c_int),
+        "vc_batch_workspace_bytes": ([vp, bp, i32, op, ctypes.POINTER(ctypes.c_size_t)],
+                                     ctypes.c_int),
+        "vc_mvc_device_ws": ([vp, gp, op, vp, ctypes.c_size_t, i32p, vp, sp], ctypes.c_int),
+        "vc_pvc_device_ws": ([vp, gp, i32, op, vp, ctypes.c_size_t, i32p, i32p, vp, sp],
+                             ctypes.c_int),
+        "vc_mvc_batch_device_ws": ([vp, bp, op, vp, ctypes.c_size_t, vp, vp, vp, vp, sp],
+                                   ctypes.c_int),
+        "vc_pvc_batch_device_ws": ([vp, bp, vp, op, vp, ctypes.c_size_t, vp, vp, vp, vp, vp, sp],
+                                   ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -216,6 +234,35 @@ def _device_graph(row_ptr, col_idx):
         raise ValueError("row_ptr must hold n+1 entries")
     return _Graph(n, col_idx.numel(), row_ptr.data_ptr(),
                   col_idx.data_ptr() if col_idx.numel() else None)
+
+
+def _device_out(t, name, count, dtype_name):
+    """A device output tensor the library writes `count` elements of (None passes through):
+    on a GPU, of the named dtype, contiguous and long enough."""
+    import torch
+    if t is None:
+        return None
+    dtype = getattr(torch, dtype_name)
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype_name}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+    if t.numel() < count:
+        raise ValueError(f"{name} holds {t.numel()} elements, the call writes {count}")
+    return t.data_ptr()
+
+
+def _workspace(ws):
+    """(pointer, bytes) of a caller workspace: a contiguous uint8 device tensor."""
+    import torch
+    if not isinstance(ws, torch.Tensor) or not ws.is_cuda or ws.dtype != torch.uint8 \
+            or not ws.is_contiguous():
+        raise TypeError("workspace must be a contiguous uint8 device tensor")
+    if ws.data_ptr() % 256:
+        raise ValueError("workspace must be 256-byte aligned")
+    return ws.data_ptr(), ws.numel()
 
 
 def pack_batch(graphs):
@@ -313,10 +360,9 @@ class Solver:
         self._order_after_torch()
         size = ctypes.c_int32()
         st = _Stats()
+        cov = _device_out(cover, "cover", cg.n, "uint8")
         rc = self._lib.vc_mvc_device(self._ctx, ctypes.byref(cg), self._opts(options),
-                                     ctypes.byref(size),
-                                     cover.data_ptr() if cover is not None else None,
-                                     ctypes.byref(st))
+                                     ctypes.byref(size), cov, ctypes.byref(st))
         self._check(rc, "vc_mvc_device")
         return Result(size.value, True, cover, _stats_dict(st))
 
@@ -326,9 +372,9 @@ class Solver:
         self._order_after_torch()
         size, yes = ctypes.c_int32(), ctypes.c_int32()
         st = _Stats()
+        cov = _device_out(cover, "cover", cg.n, "uint8")
         rc = self._lib.vc_pvc_device(self._ctx, ctypes.byref(cg), int(k), self._opts(options),
-                                     ctypes.byref(yes), ctypes.byref(size),
-                                     cover.data_ptr() if cover is not None else None,
+                                     ctypes.byref(yes), ctypes.byref(size), cov,
                                      ctypes.byref(st))
         self._check(rc, "vc_pvc_device")
         return Result(size.value, bool(yes.value), cover, _stats_dict(st))
@@ -390,9 +436,9 @@ class Solver:
         self._order_after_torch()
         status, size, yes, nodes = _batch_arrays(n.size)
         st = _Stats()
+        cov = _device_out(cover, "cover", int(n.sum()), "uint8")
         rc = self._lib.vc_mvc_batch_device(self._ctx, ctypes.byref(cb), self._opts(options),
-                                           status.ctypes.data, size.ctypes.data,
-                                           cover.data_ptr() if cover is not None else None,
+                                           status.ctypes.data, size.ctypes.data, cov,
                                            nodes.ctypes.data, ctypes.byref(st))
         self._check(rc, "vc_mvc_batch_device")
         return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, False)
@@ -406,12 +452,97 @@ class Solver:
         self._order_after_torch()
         status, size, yes, nodes = _batch_arrays(n.size)
         st = _Stats()
+        cov = _device_out(cover, "cover", int(n.sum()), "uint8")
         rc = self._lib.vc_pvc_batch_device(self._ctx, ctypes.byref(cb), _ptr(k),
                                            self._opts(options), status.ctypes.data,
-                                           yes.ctypes.data, size.ctypes.data,
-                                           cover.data_ptr() if cover is not None else None,
+                                           yes.ctypes.data, size.ctypes.data, cov,
                                            nodes.ctypes.data, ctypes.byref(st))
         self._check(rc, "vc_pvc_batch_device")
+        return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, True)
+
+    # ---- caller-owned workspace (vc_*_ws) --------------------------------------------------
+
+    def abort(self):
+        """Stop the call running on this context (from another thread): it returns
+        ERR_BUDGET."""
+        self._check(self._lib.vc_abort(self._ctx), "vc_abort")
+
+    def workspace_bytes(self, n: int, nnz: int, depth: int = 0,
+                        options: Options | None = None) -> int:
+        out = ctypes.c_size_t()
+        self._check(self._lib.vc_workspace_bytes(self._ctx, int(n), int(nnz), int(depth),
+                                                 self._opts(options), ctypes.byref(out)),
+                    "vc_workspace_bytes")
+        return out.value
+
+    def batch_workspace_bytes(self, n, nnz, depth: int = 0,
+                              options: Options | None = None) -> int:
+        n = np.ascontiguousarray(n, dtype=np.int32)
+        nnz = np.ascontiguousarray(nnz, dtype=np.int32)
+        cb = _Batch(n.size, _ptr(n), _ptr(nnz), None, None)
+        out = ctypes.c_size_t()
+        self._check(self._lib.vc_batch_workspace_bytes(self._ctx, ctypes.byref(cb), int(depth),
+                                                       self._opts(options), ctypes.byref(out)),
+                    "vc_batch_workspace_bytes")
+        return out.value
+
+    def mvc_device_ws(self, row_ptr, col_idx, workspace, cover=None,
+                      options: Options | None = None) -> Result:
+        cg = _device_graph(row_ptr, col_idx)
+        wp, wb = _workspace(workspace)
+        cov = _device_out(cover, "cover", cg.n, "uint8")
+        self._order_after_torch()
+        size = ctypes.c_int32()
+        st = _Stats()
+        rc = self._lib.vc_mvc_device_ws(self._ctx, ctypes.byref(cg), self._opts(options), wp, wb,
+                                        ctypes.byref(size), cov, ctypes.byref(st))
+        self._check(rc, "vc_mvc_device_ws")
+        return Result(size.value, True, cover, _stats_dict(st))
+
+    def pvc_device_ws(self, row_ptr, col_idx, k: int, workspace, cover=None,
+                      options: Options | None = None) -> Result:
+        cg = _device_graph(row_ptr, col_idx)
+        wp, wb = _workspace(workspace)
+        cov = _device_out(cover, "cover", cg.n, "uint8")
+        self._order_after_torch()
+        size, yes = ctypes.c_int32(), ctypes.c_int32()
+        st = _Stats()
+        rc = self._lib.vc_pvc_device_ws(self._ctx, ctypes.byref(cg), int(k), self._opts(options),
+                                        wp, wb, ctypes.byref(yes), ctypes.byref(size), cov,
+                                        ctypes.byref(st))
+        self._check(rc, "vc_pvc_device_ws")
+        return Result(size.value, bool(yes.value), cover, _stats_dict(st))
+
+    def mvc_batch_device_ws(self, n, nnz, row_ptr, col_idx, workspace, cover=None,
+                            options: Options | None = None) -> BatchResult:
+        n, nnz, cb = self._device_batch(n, nnz, row_ptr, col_idx)
+        wp, wb = _workspace(workspace)
+        cov = _device_out(cover, "cover", int(n.sum()), "uint8")
+        self._order_after_torch()
+        status, size, yes, nodes = _batch_arrays(n.size)
+        st = _Stats()
+        rc = self._lib.vc_mvc_batch_device_ws(self._ctx, ctypes.byref(cb), self._opts(options),
+                                              wp, wb, status.ctypes.data, size.ctypes.data, cov,
+                                              nodes.ctypes.data, ctypes.byref(st))
+        self._check(rc, "vc_mvc_batch_device_ws")
+        return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, False)
+
+    def pvc_batch_device_ws(self, n, nnz, row_ptr, col_idx, ks, workspace, cover=None,
+                            options: Options | None = None) -> BatchResult:
+        n, nnz, cb = self._device_batch(n, nnz, row_ptr, col_idx)
+        k = np.ascontiguousarray(ks, dtype=np.int32)
+        if k.size != n.size:
+            raise ValueError("one k per graph")
+        wp, wb = _workspace(workspace)
+        cov = _device_out(cover, "cover", int(n.sum()), "uint8")
+        self._order_after_torch()
+        status, size, yes, nodes = _batch_arrays(n.size)
+        st = _Stats()
+        rc = self._lib.vc_pvc_batch_device_ws(self._ctx, ctypes.byref(cb), _ptr(k),
+                                              self._opts(options), wp, wb, status.ctypes.data,
+                                              yes.ctypes.data, size.ctypes.data, cov,
+                                              nodes.ctypes.data, ctypes.byref(st))
+        self._check(rc, "vc_pvc_batch_device_ws")
         return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, True)
 
     def wg_loads(self, cycles: bool = False):
@@ -432,8 +563,8 @@ class Solver:
         cg = _device_graph(row_ptr, col_idx)
         self._order_after_torch()
         size = ctypes.c_int32()
-        rc = self._lib.vc_greedy_device(self._ctx, ctypes.byref(cg), ctypes.byref(size),
-                                        cover.data_ptr() if cover is not None else None)
+        cov = _device_out(cover, "cover", cg.n, "uint8")
+        rc = self._lib.vc_greedy_device(self._ctx, ctypes.byref(cg), ctypes.byref(size), cov)
         self._check(rc, "vc_greedy_device")
         return size.value
 
@@ -441,8 +572,11 @@ class Solver:
         """Reduction rules in place on the int32 device tensor ``deg``; returns the new s."""
         cg = _device_graph(row_ptr, col_idx)
         self._order_after_torch()
+        if deg is None:
+            raise TypeError("deg must be a device tensor")
+        dp = _device_out(deg, "deg", cg.n, "int32")
         sv = ctypes.c_int32(int(s))
-        rc = self._lib.vc_reduce_device(self._ctx, ctypes.byref(cg), deg.data_ptr(),
+        rc = self._lib.vc_reduce_device(self._ctx, ctypes.byref(cg), dp,
                                         ctypes.byref(sv), int(bound), int(flags))
         self._check(rc, "vc_reduce_device")
         return sv.value

@@ -502,7 +502,7 @@ __device__ __forceinline__ bool bits_enqueue(const Params& p, Ctrl& c, const Liv
 // unstarted instance (its root), 0 when the launch is over, -1 when it is being stopped. Queued
 // nodes go first, then roots in instance order; idle polling as in dequeue_begin.
 template <int W>
-__device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pending,
+__device__ __forceinline__ int bits_dequeue(const Params& p, Ctrl& c, Live<W>& L, int& pending,
                                             int& inst) {
   int status = 3;
   uint32_t words[2 * W + 2];
@@ -511,7 +511,7 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pe
     int polls = 0;
     while (status == 3) {
       int32_t* count = ctr_i32(p, kQCount);
-      if ((polls & 3) == 0 && search_stopped(p)) {
+      if ((polls & 3) == 0 && search_stopped(p, c)) {
         status = -1;
       } else if (load_relaxed(count) > 0) {
         if (fetch_add(count, -1) > 0) {
@@ -521,7 +521,7 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Live<W>& L, int& pe
           int wait = 0;
           status = 1;
           while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
-            if (search_stopped(p)) {
+            if (search_stopped(p, c)) {
               status = -1;
               break;
             }
@@ -640,6 +640,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   Rows<W> r;
   ActivityClock<PROF> clk;
   clk.begin();
+  if (tid == 0) watch_begin(c);
 
   constexpr int kStride = bits_stride<W>();
   // Lane 0 alone writes and reads stack entries, in program order, so the ring needs no
@@ -749,7 +750,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           if (tid == 0) release_work(p, cur);
           holding = false;
         }
-        const int got = bits_dequeue<W>(p, L, pending, inst);
+        const int got = bits_dequeue<W>(p, c, L, pending, inst);
         if (got != 1 && got != 2) {
           clk.charge(kActAcquire);
           break;
@@ -809,6 +810,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
       if (p.q_threshold > 0) qraw = load_relaxed(ctr_i32(p, kQCount));
       abort_raw = load_relaxed(ctr_i32(p, kAbort));
       if (PVC) open_raw = load_relaxed(ctr_i32(p, kOpen));
+      if (tid == 0 && watchdog(p, c)) abort_raw = 1;
     }
     if (seen_inst != cur) {
       // a new instance: wait for its header before the reduction

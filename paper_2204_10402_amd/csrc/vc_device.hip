@@ -738,6 +738,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   }
   ActivityClock<PROF> clk;
   clk.begin();
+  if (tid == 0) watch_begin(c);
   uint32_t headers = 0;  // thread 0: node headers read so far
 
   int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * p.stride;
@@ -899,7 +900,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     if (tid == 0) {
       const uint64_t h = inst_header(p, cur);
       const int32_t state = static_cast<int32_t>(h >> 32);
-      if ((headers++ & 15) == 0) c.stop = search_stopped(p);
+      if ((headers++ & 15) == 0) c.stop = search_stopped(p, c);
       c.drop = (state & kInstOutOfBudget) | (PVC ? (state & kInstFound) : 0);
       c.best = static_cast<int32_t>(static_cast<uint32_t>(h));
     }
@@ -1068,6 +1069,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertice
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     res->aborted = *ctr_i32(p, kAbort);
     res->error = *ctr_i32(p, kError);
+    res->stop_reason = *ctr_i32(p, kStopReason);
     res->q_max_count = *ctr_i32(p, kQMaxCount);
   }
 }

@@ -118,6 +118,8 @@ __device__ __forceinline__ int bcast(int x, int lane) { return __builtin_amdgcn_
 // ---- per-workgroup LDS control block ------------------------------------------------------
 
 struct Ctrl {
+  uint64_t t_start;    // thread 0: the device clock when this workgroup started (watchdog)
+  uint64_t t_host;     // thread 0 of workgroup 0: when it last read the host's stop word
   int32_t flag_epoch;  // epoch of the last decide step that marked a vertex
   int32_t status;      // broadcast of a result computed by thread 0
   uint32_t slot;
@@ -185,9 +187,44 @@ __device__ __forceinline__ uint64_t inst_header(const Params& p, int j) {
   return load_relaxed(reinterpret_cast<unsigned long long*>(&p.ist[j].best));
 }
 
-// Is the search being stopped: aborted, or (PVC) every instance answered?
-__device__ __forceinline__ bool search_stopped(const Params& p) {
-  return load_relaxed(ctr_i32(p, kAbort)) != 0 || (p.pvc && load_relaxed(ctr_i32(p, kOpen)) == 0);
+// The device's constant-rate clock (s_memrealtime; its rate is the device's wall-clock rate).
+__device__ __forceinline__ uint64_t realtime() { return __builtin_amdgcn_s_memrealtime(); }
+
+// Ticks of that clock between two reads of the host's stop word by workgroup 0.
+constexpr uint64_t kHostPollTicks = 5000;
+
+// Thread 0, at the start of a traversal workgroup.
+__device__ __forceinline__ void watch_begin(Ctrl& c) {
+  c.t_start = realtime();
+  c.t_host = c.t_start;
+}
+
+// Thread 0: has the launch's time limit run out, or (workgroup 0, every kHostPollTicks) has the
+// host asked to stop? Either raises the launch-wide stop, which every workgroup sees at its next
+// look at the control words; returns whether it did.
+__device__ inline bool watchdog(const Params& p, Ctrl& c) {
+  if (p.timeout_ticks == 0 && p.host_abort == nullptr) return false;
+  const uint64_t now = realtime();
+  int32_t reason = 0;
+  if (p.timeout_ticks != 0 && now - c.t_start > p.timeout_ticks) {
+    reason = kStopTimeout;
+  } else if (p.host_abort != nullptr && blockIdx.x == 0 && now - c.t_host >= kHostPollTicks) {
+    c.t_host = now;
+    if (__hip_atomic_load(p.host_abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) !=
+        p.abort_base)
+      reason = kStopHost;
+  }
+  if (reason == 0) return false;
+  atomicMax(ctr_i32(p, kStopReason), reason);
+  store_relaxed(ctr_i32(p, kAbort), 1);
+  return true;
+}
+
+// Thread 0: is the search being stopped: aborted (an internal error, the host, the time
+// limit), or (PVC) every instance answered?
+__device__ __forceinline__ bool search_stopped(const Params& p, Ctrl& c) {
+  return watchdog(p, c) || load_relaxed(ctr_i32(p, kAbort)) != 0 ||
+         (p.pvc && load_relaxed(ctr_i32(p, kOpen)) == 0);
 }
 
 // Spin lock taken by one thread for a short critical section with no waits inside (an
@@ -228,7 +265,7 @@ __device__ inline int enqueue_reserve(const Params& p, Ctrl& c, int inst) {
   const uint32_t lap = static_cast<uint32_t>(t / p.q_cap);
   int spins = 0;
   while (load_acquire(p.seq + slot) != 2u * lap) {
-    if (search_stopped(p)) return -1;
+    if (search_stopped(p, c)) return -1;
     backoff(spins);
   }
   c.slot = slot;
@@ -265,7 +302,7 @@ __device__ inline int dequeue_begin(const Params& p, Ctrl& c) {
     if (threadIdx.x == 0) {
       int status = 3;  // nothing available yet: retry
       int32_t* count = ctr_i32(p, kQCount);
-      if ((polls & 3) == 0 && search_stopped(p)) {
+      if ((polls & 3) == 0 && search_stopped(p, c)) {
         status = -1;
       } else if (load_relaxed(count) > 0) {
         if (fetch_add(count, -1) > 0) {
@@ -275,7 +312,7 @@ __device__ inline int dequeue_begin(const Params& p, Ctrl& c) {
           int wait = 0;
           status = 1;
           while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
-            if (search_stopped(p)) {
+            if (search_stopped(p, c)) {
               status = -1;
               break;
             }

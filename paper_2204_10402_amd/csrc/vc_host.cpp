@@ -50,9 +50,29 @@ struct vc_ctx {
   // launch runs while its bitset launches run on this one; created on first use.
   vc_ctx* aux = nullptr;
   vc_ctx* stats_src = nullptr;  // the context holding the last traversal's per-workgroup stats
+  // vc_abort: a host-pinned word, mapped for the device; vc_abort increments it and a launch
+  // stops when it differs from its value at the start of the call
+  int32_t* abort_host = nullptr;
+  const int32_t* abort_dev = nullptr;
+  int64_t clock_khz = 0;  // rate of the device's constant clock (s_memrealtime), for timeouts
+  // During a call of a caller-workspace form: the workspace every device buffer is carved from
+  // (no allocation), and whether host staging may use ordinary host memory beyond `pinned`.
+  struct Workspace {
+    char* base = nullptr;
+    size_t bytes = 0;
+    size_t used = 0;
+    bool host_heap = true;
+  };
+  Workspace* ws = nullptr;
+  std::vector<char> host_heap;
 };
 
 namespace {
+
+// Launch groups of one call at most: bitset words 1 to 8, then degree arrays.
+constexpr size_t kMaxGroups = vc::kMaxBitsetWords + 1;
+// Pinned staging made with a context (grown by the allocating forms as batches need).
+constexpr size_t kPinnedStart = size_t(1) << 20;
 
 using vc::DevResult;
 using vc::Instance;
@@ -74,9 +94,26 @@ int hip_fail(vc_ctx* ctx, hipError_t e, const char* what) {
     if (e_ != hipSuccess) return hip_fail((ctx), e_, #call); \
   } while (0)
 
-// Grow-only device buffer.
+// Take `bytes` for b from the caller's workspace (a caller-workspace call): keep b's region if
+// it is large enough, else carve the next one (256-byte aligned).
+int carve(vc_ctx* ctx, DevBuf& b, size_t bytes) {
+  vc_ctx::Workspace& w = *ctx->ws;
+  if (b.ptr && b.bytes >= bytes) return VC_OK;
+  const size_t off = (w.used + 255) / 256 * 256;
+  if (off > w.bytes || bytes > w.bytes - off)
+    return fail(ctx, VC_ERR_NO_MEMORY,
+                "the workspace of " + std::to_string(w.bytes) + " bytes is too small (" +
+                    std::to_string(off + bytes) + " bytes needed so far; see vc_workspace_bytes)");
+  b.ptr = w.base + off;
+  b.bytes = bytes;
+  w.used = off + bytes;
+  return VC_OK;
+}
+
+// Grow-only device buffer (from the caller's workspace during a caller-workspace call).
 int ensure(vc_ctx* ctx, DevBuf& b, size_t bytes) {
   if (bytes == 0) bytes = 256;
+  if (ctx->ws) return carve(ctx, b, bytes);
   if (b.bytes >= bytes) return VC_OK;
   if (b.ptr) {
     hipError_t e = hipFree(b.ptr);
@@ -110,6 +147,29 @@ int ensure_pinned(vc_ctx* ctx, size_t bytes) {
     return hip_fail(ctx, e, "hipHostMalloc");
   }
   ctx->pinned_bytes = bytes;
+  return VC_OK;
+}
+
+// Host staging of `bytes` for a call: the pinned mirror, grown as needed; during a
+// caller-workspace call it is not grown: ordinary host memory takes a larger batch, or (the
+// no-allocation entry point) the call fails.
+int host_staging(vc_ctx* ctx, size_t bytes, char** out) {
+  if (!ctx->ws) {
+    int rc = ensure_pinned(ctx, bytes);
+    if (rc) return rc;
+    *out = static_cast<char*>(ctx->pinned);
+    return VC_OK;
+  }
+  if (ctx->pinned_bytes >= bytes) {
+    *out = static_cast<char*>(ctx->pinned);
+    return VC_OK;
+  }
+  if (!ctx->ws->host_heap)
+    return fail(ctx, VC_ERR_NO_MEMORY,
+                "the batch needs " + std::to_string(bytes) + " bytes of host staging, more than "
+                "the context's " + std::to_string(ctx->pinned_bytes) + " pinned bytes");
+  if (ctx->host_heap.size() < bytes) ctx->host_heap.resize(bytes);
+  *out = ctx->host_heap.data();
   return VC_OK;
 }
 
@@ -173,8 +233,9 @@ int rules_from_flags(int32_t flags) {
 
 int check_options(vc_ctx* ctx, const vc_options* o) {
   if (!o) return VC_OK;
-  for (int32_t r : o->reserved)
-    if (r != 0) return fail(ctx, VC_ERR_INVALID_ARG, "vc_options.reserved must be zero");
+  if (o->reserved != 0) return fail(ctx, VC_ERR_INVALID_ARG, "vc_options.reserved must be zero");
+  if (o->stack_depth < 0 || o->timeout_ms < 0)
+    return fail(ctx, VC_ERR_INVALID_ARG, "stack_depth and timeout_ms must be >= 0");
   if (o->wg_size != 0 && (o->wg_size < 64 || o->wg_size > 1024 || o->wg_size % 64 != 0))
     return fail(ctx, VC_ERR_INVALID_ARG, "wg_size must be 0 or a multiple of 64 in [64, 1024]");
   if (o->num_wg < 0 || o->wl_capacity < 0 || o->wl_threshold < -1 || o->node_budget < 0 ||
@@ -347,9 +408,16 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int64_t nnz_max, int32_t w
 int size_stacks(vc_ctx* ctx, Plan& pl, int32_t depth_cap) {
   const size_t per_wg = static_cast<size_t>(depth_cap) * pl.stride * sizeof(int32_t);
   if (per_wg * static_cast<size_t>(pl.num_wg) <= ctx->stacks.bytes) return VC_OK;
-  size_t free_b = 0, total_b = 0;
-  VC_HIP(ctx, hipMemGetInfo(&free_b, &total_b));
-  const size_t avail = ctx->stacks.bytes + (free_b > (size_t(1) << 30) ? free_b - (size_t(1) << 30) : 0);
+  size_t avail = 0;
+  if (ctx->ws) {
+    // what is left of the caller's workspace
+    const size_t off = (ctx->ws->used + 255) / 256 * 256;
+    avail = off < ctx->ws->bytes ? ctx->ws->bytes - off : 0;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    VC_HIP(ctx, hipMemGetInfo(&free_b, &total_b));
+    avail = ctx->stacks.bytes + (free_b > (size_t(1) << 30) ? free_b - (size_t(1) << 30) : 0);
+  }
   const size_t fit = per_wg ? avail / per_wg : static_cast<size_t>(pl.num_wg);
   if (fit < 1)
     return fail(ctx, VC_ERR_NO_MEMORY, "no room for a single workgroup stack of " +
@@ -432,7 +500,7 @@ std::string bad_row_message(int32_t row) {
 
 // The whole search for every instance of a batch.
 int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, BatchOut& out,
-              std::chrono::steady_clock::time_point t0) {
+              std::chrono::steady_clock::time_point t0, int32_t abort_base) {
   int64_t total_rp = 0, total_n = 0, total_nnz = 0;
   int rc = check_batch(ctx, b, pvc, &total_rp, &total_n, &total_nnz);
   if (rc) return rc;
@@ -482,8 +550,8 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   const int32_t ng = static_cast<int32_t>(groups.size());
   const MetaLayout L = meta_layout(m, ng, out.cover_host ? total_n : 0);
   if ((rc = ensure(ctx, ctx->meta, L.dev_end))) return rc;
-  if ((rc = ensure_pinned(ctx, L.host_end))) return rc;
-  char* host = static_cast<char*>(ctx->pinned);
+  char* host = nullptr;
+  if ((rc = host_staging(ctx, L.host_end, &host))) return rc;
   char* dev = static_cast<char*>(ctx->meta.ptr);
   Instance* h_inst = reinterpret_cast<Instance*>(host + L.inst);
   InstState* h_ist = reinterpret_cast<InstState*>(host + L.ist);
@@ -518,7 +586,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   // launches share the device instead of queueing behind each other. Not when the caller
   // already runs launches side by side on shares of the grid (vc_options.grid_share).
   const bool use_aux = !stack_only && ng >= 2 && groups.back().words == 0 &&
-                       !(o && o->grid_share > 0);
+                       !(o && o->grid_share > 0) && !ctx->ws;
   if (use_aux && !ctx->aux) {
     vc_ctx* a = nullptr;
     if ((rc = vc_create(&a, ctx->device, nullptr)) != VC_OK)
@@ -631,6 +699,14 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     }
     DevResult* dres = d_res + gi;
     p.res = dres;
+    // watchdog: vc_abort's word, and what is left of the call's time limit
+    p.host_abort = ctx->abort_dev;
+    p.abort_base = abort_base;
+    if (o && o->timeout_ms > 0) {
+      const double left_ms = static_cast<double>(o->timeout_ms) - ms_since(t0);
+      if (left_ms <= 0.0) return fail(ctx, VC_ERR_BUDGET, "time limit reached");
+      p.timeout_ticks = std::max<uint64_t>(1, static_cast<uint64_t>(left_ms * ctx->clock_khz));
+    }
 
     VC_HIP(ctx, vc::launch_prepare(p, dres, g.vertices, g.entries, gst));
     if (!pvc) {
@@ -640,11 +716,12 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
       if (g.words) VC_HIP(ctx, vc::launch_bitset_greedy(p, gst));
       else VC_HIP(ctx, vc::launch_greedy(p, gws, gst));
       VC_HIP(ctx, hipEventRecord(e1, gst));
-      if (g.words) {
+      if (g.words || ctx->ws) {
         // A path branches at most best - 1 <= n - 1 times. Bitset nodes are a few dozen bytes,
         // so their stacks are provisioned for that bound straight away instead of waiting on
         // the host for the largest greedy size (the traversal reads each instance's greedy
-        // size from its state as the first best).
+        // size from its state as the first best); so are those of a caller-workspace call,
+        // which was sized for it.
         g.depth_cap = std::max(g.n_max, 1);
       } else {
         VC_HIP(ctx, vc::launch_max_greedy(p, d_greedy + gi, gst));
@@ -656,6 +733,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     } else {
       g.depth_cap = g.k_max + 1;
     }
+    if (o && o->stack_depth > 0) g.depth_cap = o->stack_depth;  // the caller's choice
     if ((rc2 = size_stacks(lc, pl, g.depth_cap))) {
       if (lc != ctx) ctx->last_error = lc->last_error;
       return rc2;
@@ -700,7 +778,7 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   if (stack_only && m > 1)
     return fail(ctx, VC_ERR_INVALID_ARG, "VC_OPT_STACK_ONLY takes one graph per call");
   const bool explicit_knobs = o && (o->wg_size || o->num_wg || o->wl_capacity || o->wl_threshold);
-  const bool autotune = (flags & VC_OPT_AUTOTUNE) && !explicit_knobs && !stack_only;
+  const bool autotune = (flags & VC_OPT_AUTOTUNE) && !explicit_knobs && !stack_only && !ctx->ws;
   for (int32_t step = 0; step < ng; ++step) {
     // with the auxiliary context, the degree-array group (the last) goes first
     const int32_t gi = use_aux ? (step == 0 ? ng - 1 : step - 1) : step;
@@ -808,6 +886,11 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
   // launch-wide failures end the whole call
   for (int32_t gi = 0; gi < ng; ++gi) {
     const DevResult& r = h_res[gi];
+    if (r.stop_reason == vc::kStopHost && !r.error)
+      return fail(ctx, VC_ERR_BUDGET, "stopped by vc_abort");
+    if (r.stop_reason == vc::kStopTimeout && !r.error)
+      return fail(ctx, VC_ERR_BUDGET,
+                  "time limit of " + std::to_string(o ? o->timeout_ms : 0) + " ms reached");
     if (r.error)
       return fail(ctx, VC_ERR_INTERNAL,
                   "device invariant failed (code " + std::to_string(r.error) +
@@ -941,13 +1024,67 @@ int enter(vc_ctx* ctx) {
   return VC_OK;
 }
 
+// vc_abort's word as the call begins: a launch stops once the word differs from it.
+int32_t abort_mark(const vc_ctx* ctx) {
+  return ctx->abort_host ? __atomic_load_n(ctx->abort_host, __ATOMIC_ACQUIRE) : 0;
+}
+
+// A caller-workspace call: for its duration the context's device buffers are empty and every
+// one it needs is carved from the caller's workspace; its own buffers come back afterwards and
+// nothing of the workspace stays referenced (per-workgroup statistics included).
+class WorkspaceScope {
+ public:
+  WorkspaceScope(vc_ctx* ctx, void* base, size_t bytes, bool host_heap) : ctx_(ctx) {
+    if (!base) return;
+    ws_.base = static_cast<char*>(base);
+    ws_.bytes = bytes;
+    ws_.host_heap = host_heap;
+    for (size_t i = 0; i < kBufs; ++i) {
+      saved_[i] = *buf(i);
+      *buf(i) = DevBuf{};
+    }
+    ctx->ws = &ws_;
+    active_ = true;
+  }
+  ~WorkspaceScope() {
+    if (!active_) return;
+    for (size_t i = 0; i < kBufs; ++i) *buf(i) = saved_[i];
+    ctx_->ws = nullptr;
+    // the last launch's workgroup statistics were in the workspace: none to report
+    ctx_->last_num_wg = 0;
+    ctx_->stats_src = nullptr;
+  }
+  WorkspaceScope(const WorkspaceScope&) = delete;
+  WorkspaceScope& operator=(const WorkspaceScope&) = delete;
+
+ private:
+  static constexpr size_t kBufs = 12;
+  DevBuf* buf(size_t i) {
+    DevBuf* all[kBufs] = {&ctx_->rp,     &ctx_->ci,       &ctx_->meta,     &ctx_->payload,
+                          &ctx_->seq,    &ctx_->ctr,      &ctx_->stacks,   &ctx_->covers,
+                          &ctx_->wg_stats, &ctx_->scratch, &ctx_->bits,    &ctx_->gnodes};
+    return all[i];
+  }
+  vc_ctx* ctx_;
+  vc_ctx::Workspace ws_;
+  DevBuf saved_[kBufs];
+  bool active_ = false;
+};
+
+struct WsArgs {
+  void* base = nullptr;    // nullptr: the context's own buffers
+  size_t bytes = 0;
+  bool host_heap = true;   // host staging may grow beyond the pinned buffer
+};
+
 // One graph: a batch of one.
 int solve(vc_ctx* ctx, const vc_graph* g, bool device_graph, bool pvc, int32_t k,
           const vc_options* o, int32_t* yes_out, int32_t* size_out, uint8_t* cover_dev,
-          uint8_t* cover_host, vc_stats* stats) {
+          uint8_t* cover_host, vc_stats* stats, const WsArgs& wsa = WsArgs{}) {
   const auto t0 = std::chrono::steady_clock::now();
   int rc = enter(ctx);
   if (rc) return rc;
+  const int32_t abort_base = abort_mark(ctx);
   if (!size_out || (pvc && !yes_out)) return fail(ctx, VC_ERR_INVALID_ARG, "output pointer is NULL");
   if (pvc && k < 0) return fail(ctx, VC_ERR_INVALID_ARG, "k must be >= 0");
   if ((rc = check_graph_args(ctx, g))) return rc;
@@ -979,7 +1116,10 @@ int solve(vc_ctx* ctx, const vc_graph* g, bool device_graph, bool pvc, int32_t k
   out.cover_dev = cover_dev;
   out.stats = stats;
   out.single = true;
-  if ((rc = run_batch(ctx, b, pvc, o, out, t0))) return rc;
+  {
+    WorkspaceScope scope(ctx, wsa.base, wsa.bytes, wsa.host_heap);
+    if ((rc = run_batch(ctx, b, pvc, o, out, t0, abort_base))) return rc;
+  }
   *size_out = size;
   if (yes_out) *yes_out = yes;
   return VC_OK;
@@ -988,10 +1128,11 @@ int solve(vc_ctx* ctx, const vc_graph* g, bool device_graph, bool pvc, int32_t k
 int solve_batch(vc_ctx* ctx, const vc_batch* batch, bool device_graph, bool pvc,
                 const int32_t* k, const vc_options* o, int32_t* status_out, int32_t* yes_out,
                 int32_t* size_out, uint8_t* cover_dev, uint8_t* cover_host, int64_t* nodes_out,
-                vc_stats* stats) {
+                vc_stats* stats, const WsArgs& wsa = WsArgs{}) {
   const auto t0 = std::chrono::steady_clock::now();
   int rc = enter(ctx);
   if (rc) return rc;
+  const int32_t abort_base = abort_mark(ctx);
   if (!batch) return fail(ctx, VC_ERR_INVALID_ARG, "batch is NULL");
   if (!status_out || !size_out || (pvc && !yes_out))
     return fail(ctx, VC_ERR_INVALID_ARG, "output pointer is NULL");
@@ -1019,7 +1160,73 @@ int solve_batch(vc_ctx* ctx, const vc_batch* batch, bool device_graph, bool pvc,
   out.cover_host = cover_host;
   out.cover_dev = cover_dev;
   out.stats = stats;
-  return run_batch(ctx, b, pvc, o, out, t0);
+  WorkspaceScope scope(ctx, wsa.base, wsa.bytes, wsa.host_heap);
+  return run_batch(ctx, b, pvc, o, out, t0, abort_base);
+}
+
+// Device bytes a caller-workspace call on these graphs needs (an upper bound): the buffers
+// run_batch carves, summed over its launch groups (each group's own worklist, tickets,
+// statistics, adjacency rows, node slots and stacks of `depth` entries, 0 = n + 1), with the
+// larger of the MVC and PVC launch plans.
+int workspace_need(vc_ctx* ctx, int32_t count, const int32_t* n, const int32_t* nnz,
+                   int32_t depth, const vc_options* o, size_t* out) {
+  const int32_t flags = o ? o->flags : 0;
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  struct Fam {
+    int32_t n_max = 0, nnz_max = 0, count = 0;
+    int64_t vertices = 0;
+  };
+  std::map<int32_t, Fam> fams;  // by bitset words (0: degree arrays)
+  int64_t total_n = 0;
+  int32_t m = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    if (n[i] < 0 || nnz[i] < 0) return fail(ctx, VC_ERR_INVALID_ARG, "negative n or nnz");
+    if (n[i] == 0) continue;
+    int32_t words = 0;
+    int rc = choose_words(ctx, n[i], flags, &words);
+    if (rc) return rc;
+    Fam& f = fams[words];
+    f.n_max = std::max(f.n_max, n[i]);
+    f.nnz_max = std::max(f.nnz_max, nnz[i]);
+    f.count += 1;
+    f.vertices += n[i];
+    total_n += n[i];
+    ++m;
+  }
+  size_t total = 256 + al(meta_layout(m, static_cast<int32_t>(fams.size()), 0).dev_end) +
+                 al(static_cast<size_t>(total_n)) +
+                 al(vc::kNumCounters * vc::kCounterStride * sizeof(int32_t));
+  for (const auto& kv : fams) {
+    const int32_t words = kv.first;
+    const Fam& f = kv.second;
+    size_t best = 0;
+    for (bool pvc : {false, true}) {
+      Plan pl;
+      int rc = plan_launch(ctx, pvc, f.n_max, f.nnz_max, words, o, pl);
+      if (rc) return rc;
+      const size_t stride_b = static_cast<size_t>(pl.stride) * sizeof(int32_t);
+      int64_t d = depth > 0 ? depth : static_cast<int64_t>(f.n_max) + 1;
+      if (o && o->stack_depth > 0) d = o->stack_depth;
+      size_t need = al(pl.cap * stride_b) + al(pl.cap * sizeof(uint32_t)) +
+                    al(static_cast<size_t>(pl.num_wg) * sizeof(vc::WgStats)) +
+                    al(static_cast<size_t>(pl.num_wg) * static_cast<size_t>(d) * stride_b);
+      if (words) need += al(static_cast<size_t>(f.vertices) * words * sizeof(uint64_t));
+      if (pl.global_node)
+        need += al(static_cast<size_t>(std::max<int64_t>(pl.num_wg, std::min(f.count, 65535))) *
+                   stride_b);
+      best = std::max(best, need);
+    }
+    total += best;
+  }
+  *out = total;
+  return VC_OK;
+}
+
+int check_workspace(vc_ctx* ctx, void* ws, size_t bytes) {
+  if (!ws || bytes == 0) return fail(ctx, VC_ERR_INVALID_ARG, "workspace is NULL or empty");
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(ctx, VC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  return VC_OK;
 }
 
 // Validate a device CSR (a batch of one) for a one-workgroup kernel (greedy, reduce).
@@ -1143,12 +1350,39 @@ int vc_create(vc_ctx** ctx_out, int device, void* hip_stream) {
       ctx->own_stream = e == hipSuccess;
     }
   }
-  if (e == hipSuccess && ensure_events(ctx, 4) != VC_OK) e = hipErrorUnknown;
+  // Everything a call may need besides its device buffers is made here, so that the
+  // caller-workspace forms allocate nothing: the events of up to kMaxGroups launch groups, a
+  // pinned staging buffer for the instance table of a batch of a few thousand graphs, the
+  // mapped word of vc_abort and the device clock's rate.
+  if (e == hipSuccess && ensure_events(ctx, 4 * kMaxGroups + 4) != VC_OK) e = hipErrorUnknown;
+  if (e == hipSuccess && ensure_pinned(ctx, kPinnedStart) != VC_OK) e = hipErrorUnknown;
+  if (e == hipSuccess) {
+    void* word = nullptr;
+    e = hipHostMalloc(&word, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+      ctx->abort_host = static_cast<int32_t*>(word);
+      *ctx->abort_host = 0;
+      void* dptr = nullptr;
+      e = hipHostGetDevicePointer(&dptr, word, 0);
+      ctx->abort_dev = static_cast<const int32_t*>(dptr);
+    }
+  }
+  if (e == hipSuccess) {
+    int khz = 0;
+    e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
+    ctx->clock_khz = khz > 0 ? khz : 100000;
+  }
   if (e != hipSuccess) {
     vc_destroy(ctx);
     return VC_ERR_DEVICE;
   }
   *ctx_out = ctx;
+  return VC_OK;
+}
+
+int vc_abort(vc_ctx* ctx) {
+  if (!ctx || !ctx->abort_host) return VC_ERR_INVALID_ARG;
+  __atomic_fetch_add(ctx->abort_host, 1, __ATOMIC_RELEASE);
   return VC_OK;
 }
 
@@ -1163,6 +1397,7 @@ int vc_destroy(vc_ctx* ctx) {
   for (DevBuf* b : bufs)
     if (b->ptr) (void)hipFree(b->ptr);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->abort_host) (void)hipHostFree(ctx->abort_host);
   for (hipEvent_t ev : ctx->ev)
     if (ev) (void)hipEventDestroy(ev);
   if (ctx->own_stream && ctx->stream) (void)hipStreamDestroy(ctx->stream);
@@ -1216,6 +1451,70 @@ int vc_pvc_batch_device(vc_ctx* ctx, const vc_batch* batch, const int32_t* k,
                         vc_stats* stats) {
   return solve_batch(ctx, batch, true, true, k, opts, status_out, yes_out, size_out, cover_dev,
                      nullptr, nodes_out, stats);
+}
+
+int vc_workspace_bytes(vc_ctx* ctx, int32_t n, int32_t nnz, int32_t depth,
+                       const vc_options* opts, size_t* bytes_out) {
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if (!bytes_out) return fail(ctx, VC_ERR_INVALID_ARG, "bytes_out is NULL");
+  if (depth < 0) return fail(ctx, VC_ERR_INVALID_ARG, "depth must be >= 0");
+  if ((rc = check_options(ctx, opts))) return rc;
+  return workspace_need(ctx, 1, &n, &nnz, depth, opts, bytes_out);
+}
+
+int vc_batch_workspace_bytes(vc_ctx* ctx, const vc_batch* batch, int32_t depth,
+                             const vc_options* opts, size_t* bytes_out) {
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if (!batch || !bytes_out) return fail(ctx, VC_ERR_INVALID_ARG, "NULL argument");
+  if (batch->count < 0 || (batch->count > 0 && (!batch->n || !batch->nnz)))
+    return fail(ctx, VC_ERR_INVALID_ARG, "bad batch count, n or nnz");
+  if (depth < 0) return fail(ctx, VC_ERR_INVALID_ARG, "depth must be >= 0");
+  if ((rc = check_options(ctx, opts))) return rc;
+  return workspace_need(ctx, batch->count, batch->n, batch->nnz, depth, opts, bytes_out);
+}
+
+int vc_mvc_device_ws(vc_ctx* ctx, const vc_graph* g, const vc_options* opts, void* workspace,
+                     size_t workspace_bytes, int32_t* size_out, uint8_t* cover_dev,
+                     vc_stats* stats) {
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if ((rc = check_workspace(ctx, workspace, workspace_bytes))) return rc;
+  return solve(ctx, g, true, false, 0, opts, nullptr, size_out, cover_dev, nullptr, stats,
+               WsArgs{workspace, workspace_bytes, true});
+}
+
+int vc_pvc_device_ws(vc_ctx* ctx, const vc_graph* g, int32_t k, const vc_options* opts,
+                     void* workspace, size_t workspace_bytes, int32_t* yes_out,
+                     int32_t* size_out, uint8_t* cover_dev, vc_stats* stats) {
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if ((rc = check_workspace(ctx, workspace, workspace_bytes))) return rc;
+  return solve(ctx, g, true, true, k, opts, yes_out, size_out, cover_dev, nullptr, stats,
+               WsArgs{workspace, workspace_bytes, true});
+}
+
+int vc_mvc_batch_device_ws(vc_ctx* ctx, const vc_batch* batch, const vc_options* opts,
+                           void* workspace, size_t workspace_bytes, int32_t* status_out,
+                           int32_t* size_out, uint8_t* cover_dev, int64_t* nodes_out,
+                           vc_stats* stats) {
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if ((rc = check_workspace(ctx, workspace, workspace_bytes))) return rc;
+  return solve_batch(ctx, batch, true, false, nullptr, opts, status_out, nullptr, size_out,
+                     cover_dev, nullptr, nodes_out, stats, WsArgs{workspace, workspace_bytes, true});
+}
+
+int vc_pvc_batch_device_ws(vc_ctx* ctx, const vc_batch* batch, const int32_t* k,
+                           const vc_options* opts, void* workspace, size_t workspace_bytes,
+                           int32_t* status_out, int32_t* yes_out, int32_t* size_out,
+                           uint8_t* cover_dev, int64_t* nodes_out, vc_stats* stats) {
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if ((rc = check_workspace(ctx, workspace, workspace_bytes))) return rc;
+  return solve_batch(ctx, batch, true, true, k, opts, status_out, yes_out, size_out, cover_dev,
+                     nullptr, nodes_out, stats, WsArgs{workspace, workspace_bytes, true});
 }
 
 int vc_greedy_device(vc_ctx* ctx, const vc_graph* g, int32_t* size_out, uint8_t* cover_dev) {

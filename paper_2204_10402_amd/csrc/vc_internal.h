@@ -38,7 +38,14 @@ enum CounterSlot : int {
   kAbort = 6,      // int32: non-zero stops every workgroup (internal error)
   kError = 7,      // int32: internal error code (1 = stack overflow, 2 = node of no instance)
   kQMaxCount = 8,  // int32: largest worklist count seen by a producer
-  kNumCounters = 9,
+  kStopReason = 9, // int32: why the launch was stopped from outside the search (kStop*)
+  kNumCounters = 10,
+};
+
+// Reasons a launch stops before its search ends, other than an internal error.
+enum : int32_t {
+  kStopHost = 1,     // the host asked the context to stop (vc_abort)
+  kStopTimeout = 2,  // the call's time limit (vc_options.timeout_ms) ran out
 };
 constexpr int kCounterStride = 32;  // int32 words per control line (128 bytes)
 
@@ -143,6 +150,12 @@ struct Params {
                         // adjacency matrix (depth_cap nodes), 0 = in `stacks`
   int32_t pvc;          // 1: PVC (instances stop once answered), 0: MVC
   int32_t start_depth;  // > 0: StackOnly traversal of instance 0 from this depth; 0: hybrid
+  // Watchdog: a host-pinned word that workgroup 0 reads every few tens of microseconds of the
+  // device's constant-rate clock (non-zero stops the launch; nullptr: none), and a time limit
+  // in ticks of that clock, measured by every workgroup from its own start (0: none).
+  const int32_t* host_abort;
+  int32_t abort_base;   // the host word's value when the call began; any other value stops
+  uint64_t timeout_ticks;
 };
 
 // Degree-array node, stored and in LDS: deg[0..n_i), s at n_i, pending vertex at n_i + 1, the
@@ -170,7 +183,7 @@ struct DevResult {
   int32_t max_depth;
   int32_t q_max_count;
   int32_t active_wgs;   // workgroups that took any work (only they add their statistics)
-  int32_t pad;
+  int32_t stop_reason;  // kStopHost / kStopTimeout, 0 if the launch was not stopped from outside
   int64_t nodes;
   int64_t wg_nodes_max;
   int64_t wg_nodes_min;

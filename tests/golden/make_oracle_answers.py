@@ -9,6 +9,8 @@ Workloads (all seeded, see graphs.generators):
                  seeds 0-3
 - mvc_reg120:    MVC, random 5-regular n=120, seeds 0-7
 - mvc_er150:     MVC, G(150, 0.08), seeds 0-7
+- pvc_reg120, pvc_er150: PVC with k = tau - 1 on the same graphs (every answer "no"; the search
+                 tree is then the same whatever the schedule, so node counts compare exactly)
 
 Usage: python tests/golden/make_oracle_answers.py [--jobs 8]
 """
@@ -45,9 +47,9 @@ def make_graph(name, seed):
         return G.erdos_renyi(60, 0.10, seed)
     if name == "pvc_planted":
         return G.planted_cover(5000, 400, 40000, 0.75, seed)
-    if name == "mvc_reg120":
+    if name in ("mvc_reg120", "pvc_reg120"):
         return G.random_regular(120, 5, seed)
-    if name == "mvc_er150":
+    if name in ("mvc_er150", "pvc_er150"):
         return G.erdos_renyi(150, 0.08, seed)
     raise KeyError(name)
 
@@ -76,6 +78,10 @@ def main():
     todo = list(cases())
     with ProcessPoolExecutor(a.jobs) as ex:
         res = list(ex.map(solve, todo))
+        # PVC at k = tau - 1 on the hard graphs, tau from the MVC answers just computed
+        hard = [("pvc_" + r["workload"][4:], r["seed"], r["size"] - 1) for r in res
+                if r["workload"] in ("mvc_reg120", "mvc_er150")]
+        res += list(ex.map(solve, hard))
     doc = {"_about": "CPU oracle answers (oracle/vc_oracle.c) on the seeded full-size "
                      "workloads; written by tests/golden/make_oracle_answers.py.",
            "results": res}

@@ -98,3 +98,55 @@ def test_pack_batch_layout():
     assert rp.tolist() == [0, 1, 3, 4, 0, 0, 2, 4, 6, 8]
     assert ci.tolist() == [1, 0, 2, 1, 1, 3, 0, 2, 1, 3, 0, 2]
     assert b._offsets(n).tolist() == [0, 3, 3, 7]
+
+
+def test_null_arguments_of_the_workspace_forms(lib):
+    size = ctypes.c_size_t()
+    assert lib.vc_abort(None) == vc.ERR_INVALID_ARG
+    assert lib.vc_workspace_bytes(None, 10, 20, 0, None, ctypes.byref(size)) == vc.ERR_INVALID_ARG
+    assert lib.vc_batch_workspace_bytes(None, None, 0, None, ctypes.byref(size)) == \
+        vc.ERR_INVALID_ARG
+    assert lib.vc_mvc_device_ws(None, None, None, None, 0, None, None, None) == vc.ERR_INVALID_ARG
+    assert lib.vc_pvc_device_ws(None, None, 1, None, None, 0, None, None, None, None) == \
+        vc.ERR_INVALID_ARG
+    assert lib.vc_mvc_batch_device_ws(None, None, None, None, 0, None, None, None, None,
+                                      None) == vc.ERR_INVALID_ARG
+    assert lib.vc_pvc_batch_device_ws(None, None, None, None, None, 0, None, None, None, None,
+                                      None, None) == vc.ERR_INVALID_ARG
+
+
+def _fake_device(t):
+    """A CPU tensor that reports itself as a GPU tensor, to reach the binding's later checks
+    without a GPU (the library is never called with it)."""
+    import torch
+
+    class FakeCuda(torch.Tensor):
+        @property
+        def is_cuda(self):
+            return True
+
+    return t.as_subclass(FakeCuda)
+
+
+def test_binding_rejects_bad_output_tensors():
+    """Device outputs the library writes through must be GPU tensors of the right dtype,
+    contiguous and long enough; anything else raises before the library sees a pointer."""
+    import torch
+    from paper_2204_10402_amd import _binding as b
+    assert b._device_out(None, "cover", 5, "uint8") is None
+    with pytest.raises(TypeError):
+        b._device_out(torch.zeros(5, dtype=torch.uint8), "cover", 5, "uint8")  # CPU tensor
+    with pytest.raises(TypeError):
+        b._device_out(_fake_device(torch.zeros(5, dtype=torch.int32)), "cover", 5, "uint8")
+    with pytest.raises(TypeError):
+        b._device_out(_fake_device(torch.zeros(10, dtype=torch.uint8)[::2]), "cover", 5, "uint8")
+    with pytest.raises(ValueError):
+        b._device_out(_fake_device(torch.zeros(4, dtype=torch.uint8)), "cover", 5, "uint8")
+    with pytest.raises(TypeError):
+        b._device_out(_fake_device(torch.zeros(5, dtype=torch.uint8)), "deg", 5, "int32")
+    t = _fake_device(torch.zeros(5, dtype=torch.int32))
+    assert b._device_out(t, "deg", 5, "int32") == t.data_ptr()
+    with pytest.raises(TypeError):
+        b._workspace(torch.zeros(1024, dtype=torch.uint8))  # CPU tensor
+    with pytest.raises(TypeError):
+        b._workspace(_fake_device(torch.zeros(256, dtype=torch.int32)))

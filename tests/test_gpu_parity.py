@@ -276,6 +276,21 @@ def test_hard_pvc_no_node_parity(solver, oracle_lib):
     check_cover(g, y.cover, y.size)
 
 
+@pytest.mark.parametrize("kernel", ["bitsets", "degree_arrays"])
+def test_hard_pvc_no_node_parity_all_instances(solver, kernel):
+    """PVC k = tau - 1 on all 16 hard graphs (5-regular n=120 and G(150, 0.08), seeds 0-7) in
+    one batched call per kernel family: every answer no, and every instance's node count equal
+    to the oracle's stored count (the tree does not depend on the schedule)."""
+    want = [r for r in golden() if r["workload"] in ("pvc_reg120", "pvc_er150")]
+    assert len(want) == 16
+    gs = [G.random_regular(120, 5, r["seed"]) if r["workload"] == "pvc_reg120"
+          else G.erdos_renyi(150, 0.08, r["seed"]) for r in want]
+    res = solver.pvc_batch(gs, [r["k"] for r in want], opts(flags=KERNELS[kernel]))
+    for i, r in enumerate(want):
+        assert res.status[i] == 0 and not res.yes[i], (r["workload"], r["seed"])
+        assert res.nodes[i] == r["nodes"], (r["workload"], r["seed"])
+
+
 # ---- edge cases -----------------------------------------------------------------------------
 
 def test_edge_cases(solver, oracle_lib):
