@@ -106,9 +106,10 @@ def test_served_results_equal_solo_results(solver, oracle_lib, workers, max_batc
 
 def test_streamed_arrivals_overlap(solver, oracle_lib):
     """Requests submitted while others run are admitted by free workers: with a stream of
-    arrivals several batches are in flight at once, and answers still equal solo answers."""
+    arrivals several batches are in flight at once (a request of a search of ~2.4e5 nodes
+    first keeps one worker busy while the rest arrive), and answers still equal solo answers."""
     import paper_2204_10402_amd as vc
-    reqs = mixed_requests(9, 60)
+    reqs = [(G.random_regular(100, 5, 7), "mvc")] + mixed_requests(9, 60)
     with vc.Server(0, workers=4, max_batch=16) as srv:
         tickets = []
         for g, problem in reqs:
@@ -125,6 +126,12 @@ def test_streamed_arrivals_overlap(solver, oracle_lib):
     workers = {got[t]["worker"] for t in tickets}
     assert len(workers) >= 2
     assert len(spans) == len(reqs)
+    # two batches of different workers were on the device at the same time
+    rs = [got[t] for t in tickets]
+    overlap = any(a["worker"] != b["worker"] and
+                  max(a["start_ms"], b["start_ms"]) < min(a["done_ms"], b["done_ms"])
+                  for i, a in enumerate(rs) for b in rs[i + 1:])
+    assert overlap, sorted((r["worker"], r["start_ms"], r["done_ms"]) for r in rs)
 
 
 def test_memory_budget_serializes_batches(solver, oracle_lib):
