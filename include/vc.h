@@ -318,6 +318,21 @@ int vc_pvc_batch_device_ws(vc_ctx *ctx, const vc_batch *batch, const int32_t *k,
                            int32_t *status_out, int32_t *yes_out, int32_t *size_out,
                            uint8_t *cover_dev, int64_t *nodes_out, vc_stats *stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): vc_pvc_device (paper §II-A) whose worklist, stacks,
+ * control words and instance state live in a fixed device array of the library, 64 MiB per
+ * device, held by each GPU the library has run on until the process ends. The call allocates
+ * no device or pinned memory and creates no stream (its host bookkeeping uses ordinary heap
+ * memory); graph, k, outputs and errors are those of vc_pvc_device. The launch plan shrinks
+ * (grid, worklist ring) until it fits the array; a graph that does not fit even one workgroup
+ * returns VC_ERR_NO_MEMORY with a message naming the limit. Every call on a device shares
+ * that device's array: calls that overlap on one device -- from different contexts or threads
+ * -- race and must not be made. Each call resets what must start at zero. No autotuning; a
+ * call runs on the context's stream and returns when the search has finished. */
+int vc_pvc_device_noalloc(vc_ctx *ctx, const vc_graph *g, int32_t k, const vc_options *opts,
+                          int32_t *yes_out, int32_t *size_out, uint8_t *cover_dev,
+                          vc_stats *stats);
+
 /* ---- serving: continuous batching of a request stream ----------------------------------
  * A server owns `workers` threads, each with its own context (device workspace and stream).
  * Submitted requests are queued with a copy of their graph. A free worker takes the oldest

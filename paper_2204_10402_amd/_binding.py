@@ -43,7 +43,7 @@ EXPORTS = (
     "vc_pvc_batch_device", "vc_server_create", "vc_server_submit", "vc_server_poll",
     "vc_server_pending", "vc_server_destroy", "vc_wg_loads", "vc_abort", "vc_workspace_bytes",
     "vc_batch_workspace_bytes", "vc_mvc_device_ws", "vc_pvc_device_ws",
-    "vc_mvc_batch_device_ws", "vc_pvc_batch_device_ws",
+    "vc_mvc_batch_device_ws", "vc_pvc_batch_device_ws", "vc_pvc_device_noalloc",
 )
 
 PROBLEM_MVC = 0
@@ -201,6 +201,7 @@ def load_library(path: str = LIB_PATH):
                                    ctypes.c_int),
         "vc_pvc_batch_device_ws": ([vp, bp, vp, op, vp, ctypes.c_size_t, vp, vp, vp, vp, vp, sp],
                                    ctypes.c_int),
+        "vc_pvc_device_noalloc": ([vp, gp, i32, op, i32p, i32p, vp, sp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -544,6 +545,20 @@ class Solver:
                                               nodes.ctypes.data, ctypes.byref(st))
         self._check(rc, "vc_pvc_batch_device_ws")
         return self._batch_result(n.size, n, status, size, yes, nodes, cover, st, True)
+
+    def pvc_device_noalloc(self, row_ptr, col_idx, k: int, cover=None,
+                           options: Options | None = None) -> Result:
+        """vc_pvc_device_noalloc: PVC in the library's fixed device scratch (no allocation)."""
+        cg = _device_graph(row_ptr, col_idx)
+        cov = _device_out(cover, "cover", cg.n, "uint8")
+        self._order_after_torch()
+        size, yes = ctypes.c_int32(), ctypes.c_int32()
+        st = _Stats()
+        rc = self._lib.vc_pvc_device_noalloc(self._ctx, ctypes.byref(cg), int(k),
+                                             self._opts(options), ctypes.byref(yes),
+                                             ctypes.byref(size), cov, ctypes.byref(st))
+        self._check(rc, "vc_pvc_device_noalloc")
+        return Result(size.value, bool(yes.value), cover, _stats_dict(st))
 
     def wg_loads(self, cycles: bool = False):
         """Nodes visited by each workgroup of the last traversal launch; with cycles=True also

@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libvc.so")
-SOURCES = ["vc_device.hip", "vc_bitset.hip", "vc_host.cpp", "vc_server.cpp"]
+SOURCES = ["vc_device.hip", "vc_bitset.hip", "vc_host.cpp", "vc_server.cpp", "vc_noalloc.hip"]
 ARCH = os.environ.get("VC_OFFLOAD_ARCH", "gfx950")
 
 

@@ -305,6 +305,8 @@ int choose_words(vc_ctx* ctx, int32_t n, int32_t flags, int32_t* words) {
   return VC_OK;
 }
 
+void size_worklist(Plan& pl, const vc_options* o, uint64_t min_cap);
+
 // Workgroup size and count for one launch (paper §IV-E, adapted): a power-of-two workgroup of
 // about n_max/4 threads; as many workgroups as can be resident at once, fewer if their stacks
 // do not fit in device memory (size_stacks).
@@ -386,12 +388,18 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int64_t nnz_max, int32_t w
   if (o && o->grid_share > 0) pl.num_wg = std::max(1, pl.num_wg / o->grid_share);
   if (o && o->num_wg > 0) pl.num_wg = std::min(pl.num_wg, o->num_wg);
 
-  // Worklist: capacity and donation threshold (§IV-A). A producer only reserves a slot after
-  // reading fewer than `threshold` reserved entries; at most num_wg producers can be past that
-  // check at once, and consumers giving back a lost reservation can hide at most num_wg more,
-  // so threshold + 2 * num_wg <= cap keeps every reservation inside the ring.
+  size_worklist(pl, o, 4096);
+  return VC_OK;
+}
+
+// Worklist capacity and donation threshold (§IV-A) for pl.num_wg workgroups, at least
+// `min_cap` entries unless the caller chose the capacity. A producer only reserves a slot after
+// reading fewer than `threshold` reserved entries; at most num_wg producers can be past that
+// check at once, and consumers giving back a lost reservation can hide at most num_wg more, so
+// threshold + 2 * num_wg <= cap keeps every reservation inside the ring.
+void size_worklist(Plan& pl, const vc_options* o, uint64_t min_cap) {
   uint64_t cap = o && o->wl_capacity ? static_cast<uint64_t>(o->wl_capacity)
-                                     : std::max<uint64_t>(8ull * pl.num_wg, 4096);
+                                     : std::max<uint64_t>(8ull * pl.num_wg, min_cap);
   cap = std::max<uint64_t>(cap, 4ull * pl.num_wg);
   pl.cap = next_pow2(cap);
   uint64_t thr;
@@ -400,6 +408,37 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int64_t nnz_max, int32_t w
   else thr = std::max<uint64_t>(64, static_cast<uint64_t>(pl.num_wg) / 4);
   thr = std::min<uint64_t>(thr, pl.cap - 2ull * static_cast<uint64_t>(pl.num_wg));
   pl.threshold = static_cast<uint32_t>(thr);
+}
+
+// A caller-workspace call: halve the grid, and with it the worklist ring, until one launch's
+// buffers -- worklist slots and tickets, workgroup statistics, adjacency rows, node slots and
+// at least one workgroup's stack of `depth` entries -- fit in what is left of the workspace.
+// (size_stacks then shrinks the grid further if all stacks do not fit.)
+int fit_plan_to_workspace(vc_ctx* ctx, Plan& pl, const vc_options* o, int32_t words,
+                          int64_t vertices, int64_t count, int32_t depth) {
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  const size_t stride_b = static_cast<size_t>(pl.stride) * sizeof(int32_t);
+  auto need = [&](const Plan& q) {
+    size_t b = al(q.cap * stride_b) + al(q.cap * sizeof(uint32_t)) +
+               al(static_cast<size_t>(q.num_wg) * sizeof(vc::WgStats)) +
+               al(static_cast<size_t>(depth) * stride_b);
+    if (words) b += al(static_cast<size_t>(vertices) * words * sizeof(uint64_t));
+    if (q.global_node)
+      b += al(static_cast<size_t>(std::max<int64_t>(q.num_wg, std::min<int64_t>(count, 65535))) *
+              stride_b);
+    return b;
+  };
+  const size_t off = (ctx->ws->used + 255) / 256 * 256;
+  const size_t left = off < ctx->ws->bytes ? ctx->ws->bytes - off : 0;
+  while (need(pl) > left && pl.num_wg > 1) {
+    pl.num_wg = (pl.num_wg + 1) / 2;
+    size_worklist(pl, o, 64);
+  }
+  if (need(pl) > left)
+    return fail(ctx, VC_ERR_NO_MEMORY,
+                "the workspace of " + std::to_string(ctx->ws->bytes) +
+                    " bytes cannot hold one workgroup's worklist share and stack (" +
+                    std::to_string(off + need(pl)) + " bytes needed)");
   return VC_OK;
 }
 
@@ -653,6 +692,14 @@ int run_batch(vc_ctx* ctx, const BatchIn& b, bool pvc, const vc_options* o, Batc
     if (thr_div > 0)
       pl.threshold = static_cast<uint32_t>(std::min<int64_t>(
           std::max<int64_t>(16, pl.num_wg / thr_div), static_cast<int64_t>(pl.cap) - 2 * pl.num_wg));
+    if (ctx->ws) {
+      // the stack depth this launch will use (see below), then a plan that fits
+      const int32_t d = (o && o->stack_depth > 0) ? o->stack_depth
+                        : pvc                     ? g.k_max + 1
+                                                  : std::max(g.n_max, 1);
+      if ((rc2 = fit_plan_to_workspace(ctx, pl, go, g.words, g.vertices, g.end - g.begin, d)))
+        return rc2;
+    }
     const size_t stride_b = static_cast<size_t>(pl.stride) * sizeof(int32_t);
     if ((rc2 = ensure(ctx, lc->payload, static_cast<size_t>(pl.cap) * stride_b))) return rc2;
     if ((rc2 = ensure(ctx, lc->seq, static_cast<size_t>(pl.cap) * sizeof(uint32_t)))) return rc2;
@@ -1289,6 +1336,26 @@ int setup_single(vc_ctx* ctx, const vc_graph* g, int rules, int32_t flags, uint8
 
 }  // namespace
 
+namespace vc {
+
+int context_device(const vc_ctx* ctx) { return ctx->device; }
+
+int pvc_device_in(vc_ctx* ctx, const vc_graph* g, int32_t k, const vc_options* opts, void* ws,
+                  size_t bytes, int32_t* yes_out, int32_t* size_out, uint8_t* cover_dev,
+                  vc_stats* stats) {
+  int rc = enter(ctx);
+  if (rc) return rc;
+  if ((rc = check_workspace(ctx, ws, bytes))) return rc;
+  rc = solve(ctx, g, true, true, k, opts, yes_out, size_out, cover_dev, nullptr, stats,
+             WsArgs{ws, bytes, false});
+  if (rc == VC_ERR_NO_MEMORY)
+    ctx->last_error = "the graph is too large for the no-allocation entry point, whose device "
+                      "scratch holds " + std::to_string(bytes) + " bytes: " + ctx->last_error;
+  return rc;
+}
+
+}  // namespace vc
+
 extern "C" {
 
 const char* vc_version(void) { return "0.3.0"; }
@@ -1372,6 +1439,7 @@ int vc_create(vc_ctx** ctx_out, int device, void* hip_stream) {
     e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device);
     ctx->clock_khz = khz > 0 ? khz : 100000;
   }
+  if (e == hipSuccess && vc::noalloc_setup(device) != VC_OK) e = hipErrorUnknown;
   if (e != hipSuccess) {
     vc_destroy(ctx);
     return VC_ERR_DEVICE;

@@ -13,6 +13,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "vc.h"
+
 namespace vc {
 
 // Reduction rules switched on for a node (bit set = rule on).
@@ -234,5 +236,16 @@ hipError_t bitset_occupancy(int words, bool pvc, bool prof, size_t lds, int* blo
 size_t bitset_lds_bytes(int n_max, int words);
 size_t bitset_traverse_lds_bytes(const Params& p);
 int bitset_stride(int words);
+
+// vc_host.cpp: the device a context runs on.
+int context_device(const vc_ctx* ctx);
+// vc_host.cpp: vc_pvc_device with every device buffer carved from `ws` (`bytes` long) and host
+// staging limited to the context's pinned buffer: no device, pinned or stream allocation.
+int pvc_device_in(vc_ctx* ctx, const vc_graph* g, int32_t k, const vc_options* opts, void* ws,
+                  size_t bytes, int32_t* yes_out, int32_t* size_out, uint8_t* cover_dev,
+                  vc_stats* stats);
+// vc_noalloc.hip: resolve the device address of the no-allocation scratch on `device` (current),
+// once per device.
+int noalloc_setup(int device);
 
 }  // namespace vc
