@@ -41,7 +41,12 @@
 namespace vc {
 
 constexpr int32_t kFlag = 0x40000000;     // "decided this pass" mark on a live entry
-constexpr int32_t kDegMask = 0x3FFFFFFF;  // degree bits of a live entry
+// "degree two, and its two live neighbours are not adjacent" on a live entry. Along a path of
+// the search tree vertices are only removed, so a vertex that still has degree two has the same
+// two neighbours: the mark stays true in every descendant node (stored nodes keep it) and the
+// triangle rule checks each degree-two vertex once per path instead of once per pass.
+constexpr int32_t kNoTri = 0x20000000;
+constexpr int32_t kDegMask = 0x1FFFFFFF;  // degree bits of a live entry
 
 // ---- node operations on the LDS degree array -------------------------------------------------
 // st[0..n) degrees (kSent = in cover), st[n] = s, st[n+1] = pending vertex (-1 = none).
@@ -235,7 +240,8 @@ __device__ void decide_triangle(const Node nd, Ctrl& c, int epoch) {
   constexpr int kLaneRow = 32;
   int32_t* st = nd.st;
   const int lane = lane_id();
-  for_each_batch(st, nd.n, [](int, int32_t d) { return d >= 0 && (d & kDegMask) == 2; },
+  for_each_batch(st, nd.n,
+                 [](int, int32_t d) { return d >= 0 && (d & kDegMask) == 2 && !(d & kNoTri); },
                  [&](int cv, int count) {
                    const bool mine = lane < count;
                    const int beg = mine ? nd.rp[cv] : 0, end = mine ? nd.rp[cv + 1] : 0;
@@ -280,7 +286,12 @@ __device__ void decide_triangle(const Node nd, Ctrl& c, int epoch) {
                    const int ab = nd.rp[a], ae = nd.rp[a + 1];
                    const int bb = nd.rp[b], be = nd.rp[b + 1];
                    const bool in_a = ae - ab <= be - bb;
-                   if (!row_contains(nd.ci, in_a ? ab : bb, in_a ? ae : be, in_a ? b : a)) return;
+                   if (!row_contains(nd.ci, in_a ? ab : bb, in_a ? ae : be, in_a ? b : a)) {
+                     // no triangle through cv: no other lane flags cv in this pass (a firing
+                     // vertex flags only the two vertices of its own triangle)
+                     atomicOr(&st[cv], kNoTri);
+                     return;
+                   }
                    const int32_t da = st[a] & kDegMask, db = st[b] & kDegMask;
                    if ((da == 2 && a < cv) || (db == 2 && b < cv)) return;
                    atomicOr(&st[a], kFlag);
@@ -381,8 +392,9 @@ __device__ void max_degree_and_sum(const Node nd, Ctrl& c, int& vmax, int& dmax,
   uint64_t key = 0;
   int32_t sum = 0;
   for (int v = threadIdx.x; v < n; v += blockDim.x) {
-    const int32_t d = st[v];
-    if (d >= 0) {
+    const int32_t raw = st[v];
+    if (raw >= 0) {
+      const int32_t d = raw & kDegMask;
       sum += d;
       key = umax64(key, (static_cast<uint64_t>(static_cast<uint32_t>(d)) << 32) |
                             static_cast<uint32_t>(~static_cast<uint32_t>(v)));
@@ -1095,7 +1107,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, in
   __syncthreads();
   int epoch = 0;
   reduce_node(nd, c, bound, p.rules, epoch);
-  for (int v = threadIdx.x; v < n; v += blockDim.x) deg[v] = st[v];
+  for (int v = threadIdx.x; v < n; v += blockDim.x) deg[v] = st[v] < 0 ? st[v] : (st[v] & kDegMask);
   if (threadIdx.x == 0) *s = st[n];
 }
 
