@@ -98,8 +98,8 @@ __device__ __forceinline__ void drop_neighbour(const Rows<W>& r, int w, int b, D
 }
 
 // Remove the set F from the node: |S| grows by the number of live vertices in F (§IV-B, with
-// the |S| counter) and the degrees follow, one neighbour at a time for a few removed vertices,
-// from scratch for more.
+// the |S| counter) and the degrees follow, one removed vertex at a time for fewer than W of
+// them, from scratch for more.
 template <int W>
 __device__ __forceinline__ int remove_set(const Rows<W>& r, Live<W>& L, const uint64_t (&F)[W],
                                           Degrees<W>& D) {
@@ -112,7 +112,8 @@ __device__ __forceinline__ int remove_set(const Rows<W>& r, Live<W>& L, const ui
     L.bits[w] &= ~R[w];
   }
   L.s += removed;
-  if (removed > 2 * W) {
+  // one removed vertex costs 3W VALU and about 7 scalar instructions, a full count 4W^2 VALU
+  if (removed >= W) {
     degrees_full(r, L, D);
   } else if (removed > 0) {
 #pragma unroll
@@ -270,19 +271,19 @@ __device__ __forceinline__ int pass_triangle(const Rows<W>& r, Live<W>& L, Degre
 // High-degree rule (§II-B): degree above r = bound - |S| (r >= 0 here).
 template <int W>
 __device__ __forceinline__ int pass_high_degree(const Rows<W>& r, Live<W>& L, Degrees<W>& D,
-                                                int64_t rr) {
-  const int32_t r32 = rr > 0x7FFFFFFF ? 0x7FFFFFFF : static_cast<int32_t>(rr);
+                                                int32_t rr) {
   uint64_t F[W];
 #pragma unroll
-  for (int w = 0; w < W; ++w) F[w] = ballot(D.deg[w] > r32) & L.bits[w];
+  for (int w = 0; w < W; ++w) F[w] = ballot(D.deg[w] > rr) & L.bits[w];
   return remove_set(r, L, F, D);
 }
 
 // The rules until the graph stops changing or |S| exceeds bound (same order as the
-// degree-array kernels).
+// degree-array kernels). Callers clamp bound to [-1, n]: a larger bound (PVC with k >= n)
+// removes and prunes exactly as n does, since no live degree reaches n - |S|.
 template <int W>
 __device__ __forceinline__ void reduce_bits(const Rows<W>& r, Live<W>& L, Degrees<W>& D,
-                                            const uint64_t* adj_lds, int64_t bound, int rules) {
+                                            const uint64_t* adj_lds, int32_t bound, int rules) {
   // A pass is skipped when nothing has been removed since it last found nothing (its inputs
   // are unchanged), as in the degree-array kernels.
   int changes = 0, quiet1 = -1, quiet2 = -1, quiet3 = -1;
@@ -573,7 +574,7 @@ __global__ void __launch_bounds__(64) bitset_greedy_kernel(Params p) {
     Degrees<W> D;
     root_bits<W>(L, n);
     enter_node<W>(r, L, D, -1, adj_lds);
-    const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
+    const int32_t unbounded = 0x3FFFFFFF;
     for (;;) {
       reduce_bits<W>(r, L, D, adj_lds, unbounded, kRuleDeg1 | kRuleTri);
       int vmax;
@@ -615,11 +616,11 @@ __device__ __forceinline__ void bits_publish(const Params& p, int j, int32_t s) 
 }
 
 // Lane 0: add `count` nodes to instance j; returns 1 if that used up the instance's budget.
-__device__ __forceinline__ int bits_report_nodes(const Params& p, int j, int64_t count) {
-  if (count <= 0) return 0;
+__device__ __forceinline__ int bits_report_nodes(const Params& p, int j, uint32_t count) {
+  if (count == 0) return 0;
   unsigned long long* total = reinterpret_cast<unsigned long long*>(&p.ist[j].nodes);
   const unsigned long long before = fetch_add(total, static_cast<unsigned long long>(count));
-  if (p.node_budget > 0 && static_cast<int64_t>(before) + count >= p.node_budget) {
+  if (p.node_budget > 0 && static_cast<int64_t>(before + count) >= p.node_budget) {
     atomicOr(&p.ist[j].state, kInstOutOfBudget);
     return 1;
   }
@@ -657,8 +658,11 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   bool have = false, holding = false;
   int cur = -1, cur_n = 0;
   int32_t cur_k = 0, cur_vtx = 0;
+  // Statistics: nodes and stack traffic are counted in 32 bits since the last flush (instance
+  // switch, budget report, or every 2^30 nodes) and folded into 64-bit totals there.
   int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0, insts = 0;
-  int64_t unreported = 0;
+  uint32_t unreported = 0, pushes32 = 0, pops32 = 0;  // since the last flush
+  const uint32_t flush_at = p.node_budget > 0 ? static_cast<uint32_t>(p.budget_chunk) : (1u << 30);
   int max_depth = 0;
   uint32_t headers = 0;  // node headers read so far
   uint32_t so_path = 0;  // StackOnly: the current path index
@@ -677,7 +681,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         --top;
         top_slot = top_slot == 0 ? cap - 1 : top_slot - 1;
         bits_load<W>(stack + static_cast<size_t>(top_slot) * kStride, L, pending, inst);
-        ++pops;
+        ++pops32;
         clk.charge(kActAcquire);
       } else if constexpr (SO) {
         // StackOnly (the comparison method of §V-A): no worklist. This workgroup's sub-trees
@@ -689,7 +693,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           cur_n = load_adjacency<W>(p, 0, adj_lds, r);
           const Instance in = p.inst[0];
           cur = 0;
-          cur_k = in.k;
+          cur_k = min(in.k, cur_n);  // a k beyond n acts as n (see reduce_bits)
           cur_vtx = in.vtx_off;
           ++insts;
           so_path = static_cast<uint32_t>(wg);
@@ -714,17 +718,17 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
             reached = false;
             break;
           }
-          const int64_t bound = PVC ? static_cast<int64_t>(cur_k)
-                                    : static_cast<int64_t>(static_cast<int32_t>(h)) - 1;
-          ++nodes;
-          if (owner) ++unreported;
+          const int32_t bound = PVC ? cur_k : static_cast<int32_t>(h) - 1;
+          if (owner) ++unreported;  // counted for the instance (and the workgroup) at the flush
+          else ++nodes;             // a walk through a node another path owns
           reduce_bits<W>(r, L, D, adj_lds, bound, p.rules);
-          const int64_t rr = bound - L.s;
+          const int32_t rr = bound - L.s;
           int vmax = 0;
           int32_t degsum = 0;
           if (rr >= 0) bits_max_degree<W>(L, D, vmax, degsum);
-          const int64_t edges = degsum / 2;
-          if (rr < 0 || ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > rr * rr)) {
+          const int32_t edges = degsum / 2;
+          if (rr < 0 || ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && rr < cur_n &&
+                         edges > rr * rr)) {
             reached = false;
           } else if (edges == 0) {  // a cover: recorded once, on the owning path
             if (owner) {
@@ -767,11 +771,14 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         }
         if (inst != cur) {
           if (tid == 0 && cur >= 0) bits_report_nodes(p, cur, unreported);
-          unreported = 0;
+          nodes += unreported;
+          pushes += pushes32;
+          pops += pops32;
+          unreported = pushes32 = pops32 = 0;
           cur_n = load_adjacency<W>(p, inst, adj_lds, r);
           const Instance in = p.inst[inst];
           cur = inst;
-          cur_k = in.k;
+          cur_k = min(in.k, cur_n);  // a k beyond n acts as n (see reduce_bits)
           cur_vtx = in.vtx_off;
           ++insts;
         }
@@ -818,7 +825,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
       seen_inst = cur;
       inst_done = false;
     }
-    const int64_t early = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(seen_best) - 1;
+    const int32_t early = PVC ? cur_k : seen_best - 1;
     reduce_bits<W>(r, L, D, adj_lds, early, p.rules);
 
     if (poll) {
@@ -838,22 +845,23 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
       continue;
     }
 
-    ++nodes;
-    ++unreported;
-    if (p.node_budget > 0 && unreported >= p.budget_chunk) {
+    if (++unreported >= flush_at) {
       int spent = 0;
-      if (tid == 0) spent = bits_report_nodes(p, cur, unreported);
-      unreported = 0;
+      if (tid == 0 && p.node_budget > 0) spent = bits_report_nodes(p, cur, unreported);
+      nodes += unreported;
+      pushes += pushes32;
+      pops += pops32;
+      unreported = pushes32 = pops32 = 0;
       if (__builtin_amdgcn_readfirstlane(spent)) inst_done = true;
     }
 
-    const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(seen_best) - 1;
+    const int32_t bound = PVC ? cur_k : seen_best - 1;
     if (!PVC && bound < early) {
       reduce_bits<W>(r, L, D, adj_lds, bound, p.rules);
       clk.charge(kActReduce);
     }
 
-    const int64_t rr = bound - L.s;
+    const int32_t rr = bound - L.s;
     if (rr < 0) {
       have = false;
       continue;
@@ -862,8 +870,9 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     int32_t degsum;
     bits_max_degree<W>(L, D, vmax, degsum);
     clk.charge(kActBranch);
-    const int64_t edges = degsum / 2;
-    if ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && edges > rr * rr) {
+    // (rr >= n - |S| leaves no room for the prune: |E| < (n - |S|)^2 / 2)
+    const int32_t edges = degsum / 2;
+    if ((p.rules & kPruneEdges) && (p.rules & kRuleHigh) && rr < cur_n && edges > rr * rr) {
       have = false;
       continue;
     }
@@ -911,7 +920,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
       bits_store<W>(stack + static_cast<size_t>(top_slot) * kStride, L, vmax, cur);
       ++top;
       top_slot = top_slot + 1 == cap ? 0 : top_slot + 1;
-      ++pushes;
+      ++pushes32;
       if (top - bot > max_depth) max_depth = top - bot;
     }
     clk.charge(kActDonate);
@@ -923,9 +932,9 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   if (tid == 0) {
     if (cur >= 0) bits_report_nodes(p, cur, unreported);
     WgStats w{};
-    w.nodes = nodes;
-    w.pushes = pushes;
-    w.pops = pops;
+    w.nodes = nodes + unreported;
+    w.pushes = pushes + pushes32;
+    w.pops = pops + pops32;
     w.enqueues = enqueues;
     w.dequeues = dequeues;
     w.max_depth = max_depth;
@@ -953,7 +962,9 @@ __global__ void __launch_bounds__(64) bitset_reduce_kernel(Params p, int32_t* de
   L.s = __builtin_amdgcn_readfirstlane(*s);
   Degrees<W> D;
   enter_node<W>(r, L, D, -1, adj_lds);
-  reduce_bits<W>(r, L, D, adj_lds, bound, p.rules);
+  // a bound beyond n removes and prunes exactly as n does (see reduce_bits)
+  const int32_t b32 = bound < -1 ? -1 : (bound > n ? n : static_cast<int32_t>(bound));
+  reduce_bits<W>(r, L, D, adj_lds, b32, p.rules);
 #pragma unroll
   for (int w = 0; w < W; ++w) {
     const int v = w * 64 + lane_id();
