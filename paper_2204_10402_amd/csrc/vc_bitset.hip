@@ -60,17 +60,19 @@ __device__ __forceinline__ bool bit_of(const uint64_t (&M)[W], int x) {
   return (word >> (x & 63)) & 1ull;
 }
 
-// Per-lane cached degrees of the held vertices, and a wavefront-uniform cache of degree-two
-// vertices already known to lie in no triangle. Invariant at every rule pass: for each live
-// held vertex v, deg = |N(v) ∩ L| (entries of removed vertices are stale; every use masks them
-// with L). Along one root-to-leaf path vertices are only ever removed, so a vertex that still
-// has degree two still has the same two neighbours, and if they were not adjacent they still
-// are not: no_tri stays valid down a path and is cleared whenever the node is replaced by one
-// that is not its descendant (a pop, a dequeue, a root).
+// Per-lane cached degrees of the held vertices, and per-lane marks of held degree-two vertices
+// already known to lie in no triangle (bit wv of no_tri: the lane's vertex of word wv; kept in
+// a vector register rather than as W uniform masks, which would add to the scalar registers
+// the traversal loop holds). Invariant at every rule pass: for each live held vertex v,
+// deg = |N(v) ∩ L| (entries of removed vertices are stale; every use masks them with L). Along
+// one root-to-leaf path vertices are only ever removed, so a vertex that still has degree two
+// still has the same two neighbours, and if they were not adjacent they still are not: the
+// marks stay valid down a path and are cleared whenever the node is replaced by one that is
+// not its descendant (a pop, a dequeue, a root).
 template <int W>
 struct Degrees {
   int32_t deg[W];
-  uint64_t no_tri[W];
+  uint32_t no_tri;
 };
 
 // All degrees from scratch: deg(v) = popcount(adj(v) & L) over W words.
@@ -194,23 +196,23 @@ __device__ __forceinline__ int lowest_bit(const uint64_t (&N)[W]) {
 // Degree-two-triangle rule (§II-B, tie-break §IV-D). A live v of degree two whose neighbours
 // a < b are adjacent fires unless a or b is a degree-two vertex with a smaller id; the live
 // neighbours of firing vertices (exactly their a and b) are removed. Degree-two vertices not
-// yet in D.no_tri are checked (row a of the adjacency matrix against {a, b}); the pass ends
+// yet marked in D.no_tri are checked (row a of the adjacency matrix against {a, b}); the pass ends
 // there unless one of them lies in a triangle.
 template <int W>
 __device__ __forceinline__ int pass_triangle(const Rows<W>& r, Live<W>& L, Degrees<W>& D,
                                              const uint64_t* __restrict__ adj_lds) {
-  uint64_t D2[W], A[W];
+  uint64_t C[W], A[W];
   uint64_t any = 0;
 #pragma unroll
   for (int w = 0; w < W; ++w) {
-    D2[w] = ballot(D.deg[w] == 2) & L.bits[w];
-    any |= D2[w] & ~D.no_tri[w];
+    C[w] = ballot(D.deg[w] == 2 && !((D.no_tri >> w) & 1u)) & L.bits[w];
+    any |= C[w];
   }
   if (!any) return 0;
   uint64_t anytri = 0;
 #pragma unroll
   for (int wv = 0; wv < W; ++wv) {
-    const uint64_t check = D2[wv] & ~D.no_tri[wv];
+    const uint64_t check = C[wv];
     A[wv] = 0;
     if (check) {
       bool adjacent = false;
@@ -228,12 +230,15 @@ __device__ __forceinline__ int pass_triangle(const Rows<W>& r, Live<W>& L, Degre
         adjacent = hit != 0;
       }
       A[wv] = ballot(adjacent) & check;
-      D.no_tri[wv] |= check & ~A[wv];
+      if (lane_in(check & ~A[wv])) D.no_tri |= 1u << wv;
       anytri |= A[wv];
     }
   }
   if (!anytri) return 0;
   // A degree-two vertex lies in a triangle: the firing decisions with their tie-breaks.
+  uint64_t D2[W];
+#pragma unroll
+  for (int w = 0; w < W; ++w) D2[w] = ballot(D.deg[w] == 2) & L.bits[w];
   const int lane = lane_id();
   uint64_t Fire[W];
 #pragma unroll
@@ -377,8 +382,7 @@ __device__ __forceinline__ void enter_node(const Rows<W>& r, Live<W>& L, Degrees
     L.s += removed;
   }
   degrees_full(r, L, D);
-#pragma unroll
-  for (int w = 0; w < W; ++w) D.no_tri[w] = 0;
+  D.no_tri = 0;
 }
 
 
@@ -430,6 +434,17 @@ __device__ __forceinline__ void bits_load(const int32_t* src, Live<W>& L, int& p
 #pragma unroll
     for (int i = 0; i < 2 * W + 2; ++i) x[i] = static_cast<uint32_t>(src[i]);
   }
+  bits_unpack<W>(x, L, pending, inst);
+}
+
+// The same from an LDS stack entry: every lane reads the same words (an LDS broadcast, no
+// exec mask to set up), and the reads are LDS instructions that wait only for LDS.
+template <int W>
+__device__ __forceinline__ void bits_load_lds(const int32_t* src, Live<W>& L, int& pending,
+                                              int& inst) {
+  uint32_t x[2 * W + 2];
+#pragma unroll
+  for (int i = 0; i < 2 * W + 2; ++i) x[i] = static_cast<uint32_t>(src[i]);
   bits_unpack<W>(x, L, pending, inst);
 }
 
@@ -628,7 +643,7 @@ __device__ __forceinline__ int bits_report_nodes(const Params& p, int j, uint32_
 }
 
 // Nodes between two reads of the node header (a power of two).
-constexpr uint32_t kPollNodes = 8;
+constexpr uint32_t kPollNodes = 16;
 
 // The hybrid traversal (§IV-A, Fig. 4; termination §IV-C) on bitset nodes, over every instance
 // of the launch (as traverse_kernel).
@@ -636,18 +651,29 @@ template <int W, bool PVC, bool PROF, bool SO>
 __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   extern __shared__ uint64_t adj_lds[];
   __shared__ Ctrl c;
+  // 64-bit statistics, kept by lane 0 in LDS: the loop's scalar registers hold only the 32-bit
+  // counts since the last flush
+  __shared__ WgStats tally;
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
   Rows<W> r;
   ActivityClock<PROF> clk;
   clk.begin();
-  if (tid == 0) watch_begin(c);
+  if (tid == 0) {
+    watch_begin(c);
+    tally = WgStats{};
+  }
 
   constexpr int kStride = bits_stride<W>();
   // Lane 0 alone writes and reads stack entries, in program order, so the ring needs no
   // barrier in LDS either.
-  int32_t* stack = p.stack_lds ? reinterpret_cast<int32_t*>(adj_lds + static_cast<size_t>(p.n_max) * W)
-                               : p.stacks + static_cast<size_t>(wg) * p.depth_cap * kStride;
+  // The ring lives in LDS after the adjacency matrix (stack_lds) or in device memory. The two
+  // are addressed through separate pointers, each access under a uniform branch, so that LDS
+  // entries are read and written with LDS instructions rather than flat ones (a flat access
+  // waits for every outstanding memory operation, the node header's load included).
+  const bool stack_lds = p.stack_lds != 0;
+  int32_t* const lstack = reinterpret_cast<int32_t*>(adj_lds + static_cast<size_t>(p.n_max) * W);
+  int32_t* const gstack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * kStride;
   // The stack is a ring of depth_cap entries holding [bot, top): pops take the top, donations
   // take the bottom (the oldest deferred child, nearest its sub-tree root). Every entry belongs
   // to the instance of the sub-tree being walked.
@@ -659,8 +685,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
   int cur = -1, cur_n = 0;
   int32_t cur_k = 0, cur_vtx = 0;
   // Statistics: nodes and stack traffic are counted in 32 bits since the last flush (instance
-  // switch, budget report, or every 2^30 nodes) and folded into 64-bit totals there.
-  int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0, insts = 0;
+  // switch, budget report, or every 2^30 nodes) and folded into `tally` there.
   uint32_t unreported = 0, pushes32 = 0, pops32 = 0;  // since the last flush
   const uint32_t flush_at = p.node_budget > 0 ? static_cast<uint32_t>(p.budget_chunk) : (1u << 30);
   int max_depth = 0;
@@ -680,7 +705,8 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
       if (top > bot) {
         --top;
         top_slot = top_slot == 0 ? cap - 1 : top_slot - 1;
-        bits_load<W>(stack + static_cast<size_t>(top_slot) * kStride, L, pending, inst);
+        if (stack_lds) bits_load_lds<W>(lstack + top_slot * kStride, L, pending, inst);
+        else bits_load<W>(gstack + static_cast<size_t>(top_slot) * kStride, L, pending, inst);
         ++pops32;
         clk.charge(kActAcquire);
       } else if constexpr (SO) {
@@ -695,7 +721,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           cur = 0;
           cur_k = min(in.k, cur_n);  // a k beyond n acts as n (see reduce_bits)
           cur_vtx = in.vtx_off;
-          ++insts;
+          if (tid == 0) ++tally.instances;
           so_path = static_cast<uint32_t>(wg);
         } else {
           so_path += static_cast<uint32_t>(p.num_wg);
@@ -720,7 +746,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           }
           const int32_t bound = PVC ? cur_k : static_cast<int32_t>(h) - 1;
           if (owner) ++unreported;  // counted for the instance (and the workgroup) at the flush
-          else ++nodes;             // a walk through a node another path owns
+          else if (tid == 0) ++tally.nodes;  // a walk through a node another path owns
           reduce_bits<W>(r, L, D, adj_lds, bound, p.rules);
           const int32_t rr = bound - L.s;
           int vmax = 0;
@@ -760,7 +786,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           break;
         }
         holding = true;
-        if (got == 1) ++dequeues;
+        if (got == 1 && tid == 0) ++tally.dequeues;
         clk.charge(kActAcquire);
         if (inst < 0 || inst >= p.num_inst) {  // cannot happen: every stored node names its instance
           if (tid == 0) {
@@ -770,17 +796,19 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           break;
         }
         if (inst != cur) {
-          if (tid == 0 && cur >= 0) bits_report_nodes(p, cur, unreported);
-          nodes += unreported;
-          pushes += pushes32;
-          pops += pops32;
+          if (tid == 0) {
+            if (cur >= 0) bits_report_nodes(p, cur, unreported);
+            tally.nodes += unreported;
+            tally.pushes += pushes32;
+            tally.pops += pops32;
+            ++tally.instances;
+          }
           unreported = pushes32 = pops32 = 0;
           cur_n = load_adjacency<W>(p, inst, adj_lds, r);
           const Instance in = p.inst[inst];
           cur = inst;
           cur_k = min(in.k, cur_n);  // a k beyond n acts as n (see reduce_bits)
           cur_vtx = in.vtx_off;
-          ++insts;
         }
         if (got == 2) {
           const int rejected = __builtin_amdgcn_readfirstlane(
@@ -847,10 +875,12 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
 
     if (++unreported >= flush_at) {
       int spent = 0;
-      if (tid == 0 && p.node_budget > 0) spent = bits_report_nodes(p, cur, unreported);
-      nodes += unreported;
-      pushes += pushes32;
-      pops += pops32;
+      if (tid == 0) {
+        if (p.node_budget > 0) spent = bits_report_nodes(p, cur, unreported);
+        tally.nodes += unreported;
+        tally.pushes += pushes32;
+        tally.pops += pops32;
+      }
       unreported = pushes32 = pops32 = 0;
       if (__builtin_amdgcn_readfirstlane(spent)) inst_done = true;
     }
@@ -899,9 +929,11 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
     if (p.q_threshold > 0 && seen_count < static_cast<int32_t>(p.q_threshold)) {
       const bool from_stack = top > bot;
       const int32_t* oldest =
-          from_stack ? stack + static_cast<size_t>(bot_slot) * kStride : nullptr;
+          !from_stack ? nullptr
+          : stack_lds ? lstack + bot_slot * kStride
+                      : gstack + static_cast<size_t>(bot_slot) * kStride;
       if (bits_enqueue<W>(p, c, L, vmax, oldest, cur)) {
-        ++enqueues;
+        if (tid == 0) ++tally.enqueues;
         if (from_stack) {
           ++bot;
           bot_slot = bot_slot + 1 == cap ? 0 : bot_slot + 1;
@@ -917,7 +949,8 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
         }
         break;
       }
-      bits_store<W>(stack + static_cast<size_t>(top_slot) * kStride, L, vmax, cur);
+      if (stack_lds) bits_store<W>(lstack + top_slot * kStride, L, vmax, cur);
+      else bits_store<W>(gstack + static_cast<size_t>(top_slot) * kStride, L, vmax, cur);
       ++top;
       top_slot = top_slot + 1 == cap ? 0 : top_slot + 1;
       ++pushes32;
@@ -931,14 +964,11 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
 
   if (tid == 0) {
     if (cur >= 0) bits_report_nodes(p, cur, unreported);
-    WgStats w{};
-    w.nodes = nodes + unreported;
-    w.pushes = pushes + pushes32;
-    w.pops = pops + pops32;
-    w.enqueues = enqueues;
-    w.dequeues = dequeues;
+    WgStats w = tally;
+    w.nodes += unreported;
+    w.pushes += pushes32;
+    w.pops += pops32;
     w.max_depth = max_depth;
-    w.instances = static_cast<int32_t>(insts);
     for (int a = 0; a < kNumActivities; ++a) w.cycles[a] = static_cast<int64_t>(clk.cycles[a]);
     publish_wg_stats(p, wg, w);
   }
