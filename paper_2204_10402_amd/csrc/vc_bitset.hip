@@ -526,42 +526,24 @@ __device__ __forceinline__ int bits_dequeue(const Params& p, Ctrl& c, Live<W>& L
   if (lane_id() == 0) {
     int polls = 0;
     while (status == 3) {
-      int32_t* count = ctr_i32(p, kQCount);
-      if ((polls & 3) == 0 && search_stopped(p, c)) {
-        status = -1;
-      } else if (load_relaxed(count) > 0) {
-        if (fetch_add(count, -1) > 0) {
-          const unsigned long long h = fetch_add(ctr_u64(p, kQHead), 1ull);
-          const uint32_t slot = static_cast<uint32_t>(h) & (p.q_cap - 1);
-          const uint32_t lap = static_cast<uint32_t>(h / p.q_cap);
-          int wait = 0;
-          status = 1;
-          while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
-            if (search_stopped(p, c)) {
-              status = -1;
-              break;
-            }
-            backoff(wait);
+      uint32_t slot = 0, lap = 0;
+      status = worklist_take(p, c, (polls & 3) == 0, &slot, &lap, &root);
+      if (status == 1) {
+        int wait = 0;
+        while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
+          if (search_stopped(p, c)) {
+            status = -1;
+            break;
           }
-          if (status == 1) {
-            const int32_t* src = p.payload + static_cast<size_t>(slot) * p.stride;
+          backoff(wait);
+        }
+        if (status == 1) {
+          const int32_t* src = p.payload + static_cast<size_t>(slot) * p.stride;
 #pragma unroll
-            for (int i = 0; i < 2 * W + 2; ++i) words[i] = static_cast<uint32_t>(src[i]);
-            store_release(p.seq + slot, 2u * (lap + 1u));
-          }
-        } else {
-          fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
+          for (int i = 0; i < 2 * W + 2; ++i) words[i] = static_cast<uint32_t>(src[i]);
+          store_release(p.seq + slot, 2u * (lap + 1u));
         }
-      } else if (load_relaxed(ctr_i32(p, kRootNext)) < p.num_inst) {
-        const int32_t r = fetch_add(ctr_i32(p, kRootNext), 1);
-        if (r < p.num_inst) {
-          status = 2;
-          root = r;
-        }
-      } else if (load_relaxed(ctr_i32(p, kWork)) == 0) {
-        status = 0;  // nothing queued, held or unstarted: the launch is over
-      }
-      if (status == 3) {
+      } else if (status == 3) {
         const int units = 1 << (polls < 5 ? polls : 5);
         for (int i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(16);
         ++polls;
@@ -795,6 +777,8 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           }
           break;
         }
+        // a root's input check is loaded now, while the instance is being staged
+        const int32_t err_row = got == 2 ? load_relaxed(&p.ist[inst].err_row) : kNoRow;
         if (inst != cur) {
           if (tid == 0) {
             if (cur >= 0) bits_report_nodes(p, cur, unreported);
@@ -811,8 +795,7 @@ __global__ void __launch_bounds__(64) bitset_traverse_kernel(Params p) {
           cur_vtx = in.vtx_off;
         }
         if (got == 2) {
-          const int rejected = __builtin_amdgcn_readfirstlane(
-              load_relaxed(&p.ist[inst].err_row) != kNoRow);
+          const int rejected = __builtin_amdgcn_readfirstlane(err_row != kNoRow);
           if (rejected) {  // rejected input: no search (PVC: the instance is settled)
             if (PVC && tid == 0) fetch_add(ctr_i32(p, kOpen), -1);
             continue;

@@ -4,15 +4,18 @@
 // branch-and-reduce search tree depth first with its own stack in device memory, and hands
 // branches to a global worklist while the worklist holds fewer entries than a threshold
 // (§IV-A). An intermediate graph is a degree array over one read-only CSR (§IV-B): one int32
-// per vertex holding its degree, or -1 once the vertex is in the cover, followed by the cover
-// size s (the |S| counter of §IV-B) and a pending branch vertex (see below).
+// per vertex holding its degree, or a negative value once the vertex is in the cover, followed
+// by the cover size s (the |S| counter of §IV-B) and a pending branch vertex (see below).
 //
 // gfx950 mapping:
 //  - the node being worked on lives in LDS; every rule pass, the max-degree search and the
-//    vertex removals read and update it there (LDS atomics for degree decrements);
+//    vertex removals read and update it there (LDS atomics for degree decrements); the row
+//    pointers, and the column indices too when they fit, are staged in LDS after it. Where
+//    each of them lives is a template parameter of the kernels, so every access compiles to
+//    an LDS or a device-memory instruction, never a generic one;
 //  - vertices are processed in 64-vertex chunks, one chunk per wavefront at a time; a
-//    ballot over the chunk yields the candidates, and each candidate's CSR row is then
-//    scanned by the whole wavefront (coalesced 64-wide loads from the L2-resident CSR);
+//    ballot over the chunk yields the candidates; a candidate's CSR row is walked by its own
+//    lane when it is short, and in 64-entry pieces by the whole wavefront when it is long;
 //  - the maximum-degree vertex and the degree sum come from one pass reduced with DPP row
 //    operations inside each wavefront and one LDS step across wavefronts;
 //  - a deferred child is stored as its parent's reduced degree array plus the vertex whose
@@ -49,75 +52,66 @@ constexpr int32_t kNoTri = 0x20000000;
 constexpr int32_t kDegMask = 0x1FFFFFFF;  // degree bits of a live entry
 
 // ---- node operations on the LDS degree array -------------------------------------------------
-// st[0..n) degrees (kSent = in cover), st[n] = s, st[n+1] = pending vertex (-1 = none).
+// st[0..n) degrees (negative = in the cover), st[n] = s, st[n+1] = pending vertex (-1 = none).
+
+// Entries of the removal list: the vertices one removal step takes out, gathered from every
+// wavefront's part of the node so that the wavefronts can share their rows evenly.
+constexpr int kListCap = 1024;
 
 struct Node {
   int32_t* st;
   int n;
   const int32_t* __restrict__ rp;
   const int32_t* __restrict__ ci;
-  int32_t* heads;  // 64 LDS words per wavefront for wave_expand_rows
+  int32_t* list;  // kListCap LDS words: the removal list
 };
 
-// Inclusive max-scan over the 64 lanes (DPP, as wave_incl_scan), identity -1.
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int32_t dpp_or_minus1(int32_t x) {
-  return __builtin_amdgcn_update_dpp(-1, x, CTRL, ROW_MASK, 0xF, false);
-}
-__device__ __forceinline__ int32_t wave_incl_max(int32_t x) {
-  x = max(x, dpp_or_minus1<0x111, 0xF>(x));
-  x = max(x, dpp_or_minus1<0x112, 0xF>(x));
-  x = max(x, dpp_or_minus1<0x114, 0xF>(x));
-  x = max(x, dpp_or_minus1<0x118, 0xF>(x));
-  x = max(x, dpp_or_minus1<0x142, 0xA>(x));
-  x = max(x, dpp_or_minus1<0x143, 0xC>(x));
-  return x;
-}
+// Walk the CSR rows [beg, end) held by the lanes of a wavefront (empty where beg >= end).
+// fn(x, tag, j) runs for every entry x = ci[j], with `tag` the value the row's owner lane
+// passed in; it runs in divergent code. A row of at most kLaneRow entries is walked by its own
+// lane, eight entries per round. Longer rows are cut into 64-entry pieces that the whole
+// wavefront walks one after another, eight pieces per round, with the cursor (row bounds, tag,
+// position) in scalar registers. Either way a lane has eight independent loads in flight
+// before it uses the first, and no step needs the owner of an entry to be looked up.
+constexpr int kLaneRow = 32;
 
-// Walk the CSR rows [beg, end) held by the lanes of a wavefront (empty where beg >= end) as one
-// list, 64 consecutive entries per step, so rows of any length keep every lane busy and
-// neighbouring lanes read neighbouring entries. fn(x, tag, j) runs for every entry x = ci[j],
-// with `tag` the value the row's owner lane passed in; it runs in divergent code. The owner of each entry of a step comes from
-// head flags: every row writes its lane into `heads` (this wavefront's 64 LDS words) at its
-// first position in the step, and a max-scan over the lanes carries it forward. Eight steps
-// are issued together, with unconditional loads (an index past the list reads entry 0, whose
-// value is discarded), so eight loads are in flight before the first is used.
 template <typename Fn>
-__device__ __forceinline__ void wave_expand_rows(const int32_t* __restrict__ ci, int32_t* heads,
-                                                 int beg, int end, int tag, Fn fn) {
+__device__ __forceinline__ void walk_rows(const int32_t* __restrict__ ci, int beg, int end,
+                                          int tag, Fn fn) {
   const int lane = lane_id();
   const int len = end > beg ? end - beg : 0;
-  const int incl = wave_incl_scan(len);
-  const int excl = incl - len;
-  const int total = __builtin_amdgcn_readlane(incl, 63);
-  constexpr int kUnroll = 8;
-  for (int t0 = 0; t0 < total; t0 += 64 * kUnroll) {
-    int xs[kUnroll], tags[kUnroll], js[kUnroll];
-    bool ok[kUnroll];
+  const bool own = len <= kLaneRow;
+  for (int j0 = 0; __builtin_amdgcn_ballot_w64(own && j0 < len); j0 += 8) {
+    int xs[8];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      ok[u] = false;
-      const int s0 = t0 + u * 64;
-      if (s0 < total) {  // uniform: only as many steps as the rows need
-        heads[lane] = -1;
-        __builtin_amdgcn_wave_barrier();
-        if (len > 0 && excl < s0 + 64 && incl > s0) heads[excl > s0 ? excl - s0 : 0] = lane;
-        __builtin_amdgcn_wave_barrier();
-        const int i = wave_incl_max(heads[lane]);  // owner of entry s0 + lane
-        __builtin_amdgcn_wave_barrier();
-        const int t = s0 + lane;
-        const int src = i < 0 ? 0 : i;  // i < 0 only past the end of the list
-        const int ob = shfl(beg, src);
-        const int oe = shfl(excl, src);
-        tags[u] = shfl(tag, src);
-        ok[u] = t < total;
-        js[u] = ok[u] ? ob + (t - oe) : 0;
-        xs[u] = ci[js[u]];  // not read until every step has issued
+    for (int u = 0; u < 8; ++u) xs[u] = own && j0 + u < len ? ci[beg + j0 + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (own && j0 + u < len) fn(xs[u], tag, beg + j0 + u);
+  }
+  uint64_t longs = __builtin_amdgcn_ballot_w64(!own);
+  int rb = 0, re = 0, rt = 0;  // the piece cursor: next entry, end and tag of the current row
+  while (longs || rb < re) {
+    int xs[8], js[8], ts[8];
+    bool ok[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (rb >= re && longs) {
+        const int o = first_lane(longs);
+        longs &= longs - 1;
+        rb = __builtin_amdgcn_readlane(beg, o);
+        re = __builtin_amdgcn_readlane(end, o);
+        rt = __builtin_amdgcn_readlane(tag, o);
       }
+      js[u] = rb + lane;
+      ok[u] = js[u] < re;
+      ts[u] = rt;
+      xs[u] = ok[u] ? ci[js[u]] : 0;
+      rb += 64;
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      if (ok[u]) fn(xs[u], tags[u], js[u]);
+    for (int u = 0; u < 8; ++u)
+      if (ok[u]) fn(xs[u], ts[u], js[u]);
   }
 }
 
@@ -151,56 +145,91 @@ __device__ __forceinline__ void for_each_batch(const int32_t* st, int n, Pred pr
 
 // Remove every marked vertex (paper §IV-B): marked vertices become kSent and s grows by their
 // number; each live unmarked neighbour of a marked vertex loses one degree per marked
-// neighbour. A marked vertex is set to kSent by the lane that finds it in the same scan that
-// collects the rows to walk: the walks only decrement entries that are live and unmarked, so
-// a vertex seen as marked or as kSent is skipped either way. Called right after a barrier that
-// ends a decide step; ends with a barrier.
-__device__ void apply_marks(const Node nd) {
+// neighbour. The scan sets each marked vertex to kSent and appends it to the workgroup's
+// removal list; after a barrier the wavefronts take the list's rows round-robin (list entry i
+// goes to wavefront i mod waves), so a few marked vertices with long rows in one wavefront's
+// part of the node do not leave the others idle. Vertices beyond the list's capacity are
+// walked by the wavefront that found them. The walks only decrement entries that are live and
+// unmarked (a marked vertex is set to kSent by the scan, whichever of the two happens first),
+// which also keeps the LDS atomics off the entries of vertices already removed. Called right
+// after a barrier that ends a decide step (or a mark step); ends with a barrier. Two calls are
+// always separated by another barrier (a decide step), which orders the reset of the list
+// count before the next call's appends.
+__device__ __forceinline__ void apply_marks(const Node nd, Ctrl& c) {
   const int n = nd.n;
   int32_t* st = nd.st;
-  int cnt = 0;
-  for_each_batch(st, n,
-                 [&](int v, int32_t d) {
-                   const bool marked = d >= 0 && (d & kFlag);
-                   if (marked) {
-                     st[v] = kSent;
-                     ++cnt;
-                   }
-                   return marked;
-                 },
-                 [&](int f, int count) {
-                   const bool mine = lane_id() < count;
-                   wave_expand_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[f] : 0,
-                                    mine ? nd.rp[f + 1] : 0, f,
-                                    [&](int x, int, int) {
-                                      const int32_t dx = st[x];
-                                      if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
-                                    });
-                 });
-  cnt = wave_sum(cnt);
-  if (lane_id() == 0 && cnt) atomicAdd(&st[n], cnt);
+  const int lane = lane_id();
+  const auto walk = [&](int f, bool mine) {
+    walk_rows(nd.ci, mine ? nd.rp[f] : 0, mine ? nd.rp[f + 1] : 0, f,
+              [&](int x, int, int) {
+                const int32_t dx = st[x];
+                if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
+              });
+  };
+  int held = -1, count = 0;  // this wavefront's overflow batch
+  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
+    const int v = base + lane;
+    const int32_t d = v < n ? st[v] : kSent;
+    const bool marked = v < n && d >= 0 && (d & kFlag);
+    const uint64_t mask = __builtin_amdgcn_ballot_w64(marked);
+    if (!mask) continue;
+    int at = 0;
+    if (lane == 0) at = atomicAdd(&c.list_n, __popcll(mask));
+    at = __builtin_amdgcn_readfirstlane(at);
+    const int rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+    const bool fits = at + rank < kListCap;
+    if (marked) {
+      st[v] = kSent;
+      if (fits) nd.list[at + rank] = v;
+    }
+    const uint64_t over = __builtin_amdgcn_ballot_w64(marked && !fits);
+    if (over) {  // rare: more marked vertices than the list holds
+      const int cnt = __popcll(over);
+      if (count + cnt > 64) {
+        walk(held, lane < count);
+        held = -1;
+        count = 0;
+      }
+      const int k = lane - count;
+      const bool take = k >= 0 && k < cnt;
+      const int got = shfl(v, take ? kth_set_bit(over, k) : lane);
+      if (take) held = got;
+      count += cnt;
+    }
+  }
+  if (count) walk(held, lane < count);
   __syncthreads();
+  const int total = c.list_n;
+  const int listed = total < kListCap ? total : kListCap;
+  const int waves = blockDim.x >> 6;
+  for (int i0 = wave_id(); i0 < listed; i0 += waves * 64) {
+    const int i = i0 + waves * lane;
+    walk(i < listed ? nd.list[i] : 0, i < listed);
+  }
+  if (threadIdx.x == 0) st[n] += total;
+  __syncthreads();
+  if (threadIdx.x == 0) c.list_n = 0;
 }
 
 // Degree-one rule (§II-B): v with one live neighbour u puts u in the cover; of two adjacent
 // degree-one vertices only the smaller id is removed, and a shared neighbour once (§IV-D).
 // The rows of all degree-one vertices are walked together; the one live entry of a row names
 // u, and the lane that reads it makes the decision for that row's owner.
-__device__ void decide_degree_one(const Node nd, Ctrl& c, int epoch) {
+__device__ __forceinline__ void decide_degree_one(const Node nd, Ctrl& c, int epoch) {
   int32_t* st = nd.st;
   for_each_batch(st, nd.n, [](int, int32_t d) { return d >= 0 && (d & kDegMask) == 1; },
                  [&](int cv, int count) {
                    const bool mine = lane_id() < count;
-                   wave_expand_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[cv] : 0,
-                                    mine ? nd.rp[cv + 1] : 0, cv,
-                                    [&](int u, int v, int) {
-                                      const int32_t du = st[u];
-                                      if (du < 0) return;  // not the live neighbour of v
-                                      if ((du & kDegMask) != 1 || u < v) {
-                                        atomicOr(&st[u], kFlag);
-                                        c.flag_epoch = epoch;
-                                      }
-                                    });
+                   walk_rows(nd.ci, mine ? nd.rp[cv] : 0, mine ? nd.rp[cv + 1] : 0, cv,
+                             [&](int u, int v, int) {
+                               const int32_t du = st[u];
+                               if (du < 0) return;  // not the live neighbour of v
+                               if ((du & kDegMask) != 1 || u < v) {
+                                 atomicOr(&st[u], kFlag);
+                                 c.flag_epoch = epoch;
+                               }
+                             });
                  });
 }
 
@@ -236,7 +265,7 @@ __device__ __forceinline__ bool row_contains(const int32_t* __restrict__ ci, int
 // Each lane takes one degree-two vertex: it finds the two live neighbours in its own row (rows
 // longer than kLaneRow are searched by the whole wavefront), then searches the shorter of the
 // two neighbours' rows for the other.
-__device__ void decide_triangle(const Node nd, Ctrl& c, int epoch) {
+__device__ __forceinline__ void decide_triangle(const Node nd, Ctrl& c, int epoch) {
   constexpr int kLaneRow = 32;
   int32_t* st = nd.st;
   const int lane = lane_id();
@@ -302,7 +331,7 @@ __device__ void decide_triangle(const Node nd, Ctrl& c, int epoch) {
 
 // High-degree rule (§II-B): a vertex whose degree exceeds r = bound - s is in every cover of
 // size <= bound (bound = best - 1 for MVC, k for PVC).
-__device__ void decide_high_degree(const Node nd, Ctrl& c, int epoch, int64_t r) {
+__device__ __forceinline__ void decide_high_degree(const Node nd, Ctrl& c, int epoch, int64_t r) {
   int32_t* st = nd.st;
   for (int v = threadIdx.x; v < nd.n; v += blockDim.x) {
     const int32_t d = st[v];
@@ -319,73 +348,71 @@ struct NoClock {
 };
 
 // The reduction rules until the graph stops changing (§II-B, §IV-D), or until s > bound.
-// Precondition: the node in LDS is consistent and visible to the whole workgroup.
+// Precondition: the node is visible to the whole workgroup. With `marked`, the vertices that
+// mark_vertex / mark_neighbourhood flagged (a branch's removal) are removed first. The three
+// rules take turns through one loop, so that the removal step, the longest code, is compiled
+// once per kernel.
 template <typename Clock>
-__device__ void reduce_node(const Node nd, Ctrl& c, int64_t bound, int rules, int& epoch,
-                            Clock& clk) {
+__device__ __forceinline__ void reduce_node(const Node nd, Ctrl& c, int64_t bound, int rules,
+                                            int& epoch, Clock& clk, bool marked) {
   const int n = nd.n;
   int32_t* st = nd.st;
+  if (marked) {
+    apply_marks(nd, c);
+    clk.charge(kActBranch);
+  }
   // A rule pass is skipped when nothing has been removed since it last found nothing: its
   // inputs (the graph, and |S| for the high-degree rule) are then unchanged, so it would find
   // nothing again. This drops the empty passes of the final round, not any decision.
-  int changes = 0;                             // removal steps applied in this call
-  int quiet1 = -1, quiet2 = -1, quiet3 = -1;   // `changes` when each rule last found nothing
-  for (;;) {
-    const int32_t s0 = st[n];
-    if (s0 > bound) return;
-    if ((rules & kRuleDeg1) && quiet1 != changes) {
-      ++epoch;
+  int changes = 0;                   // removal steps applied in this call
+  int quiet[3] = {-1, -1, -1};       // `changes` when each rule last found nothing
+  int32_t s0 = st[n];                // s at the start of the current round
+  if (s0 > bound) return;
+  for (int rule = 0;; rule = rule == 2 ? 0 : rule + 1) {
+    if (rule == 0 && changes > 0) {  // a new round: stop if the last one removed nothing
+      const int32_t s1 = st[n];
+      if (s1 == s0) return;
+      s0 = s1;
+    }
+    if (!(rules & (kRuleDeg1 << rule)) || quiet[rule] == changes) {
+      if (rule == 2 && changes == 0) return;  // a first round that found nothing
+      continue;
+    }
+    ++epoch;
+    if (rule == 0) {
       decide_degree_one(nd, c, epoch);
       __syncthreads();
       clk.charge(kActDeg1);
-      if (c.flag_epoch == epoch) {
-        apply_marks(nd);
-        ++changes;
-        clk.charge(kActApply);
-        if (st[n] > bound) return;
-      } else {
-        quiet1 = changes;
-      }
-    }
-    if ((rules & kRuleTri) && quiet2 != changes) {
-      ++epoch;
+    } else if (rule == 1) {
       decide_triangle(nd, c, epoch);
       __syncthreads();
       clk.charge(kActTri);
-      if (c.flag_epoch == epoch) {
-        apply_marks(nd);
-        ++changes;
-        clk.charge(kActApply);
-        if (st[n] > bound) return;
-      } else {
-        quiet2 = changes;
-      }
-    }
-    if ((rules & kRuleHigh) && quiet3 != changes) {
-      ++epoch;
+    } else {
       decide_high_degree(nd, c, epoch, bound - st[n]);
       __syncthreads();
       clk.charge(kActHigh);
-      if (c.flag_epoch == epoch) {
-        apply_marks(nd);
-        ++changes;
-        clk.charge(kActApply);
-      } else {
-        quiet3 = changes;
-      }
     }
-    if (st[n] == s0) return;
+    if (c.flag_epoch != epoch) {
+      quiet[rule] = changes;
+      if (rule == 2 && changes == 0) return;
+      continue;
+    }
+    apply_marks(nd, c);
+    ++changes;
+    clk.charge(kActApply);
+    if (st[n] > bound) return;
   }
 }
 
-__device__ void reduce_node(const Node nd, Ctrl& c, int64_t bound, int rules, int& epoch) {
+__device__ __forceinline__ void reduce_node(const Node nd, Ctrl& c, int64_t bound, int rules,
+                                            int& epoch, bool marked = false) {
   NoClock none;
-  reduce_node(nd, c, bound, rules, epoch, none);
+  reduce_node(nd, c, bound, rules, epoch, none, marked);
 }
 
 // One pass over the degree array: the sum of live degrees (= 2|E|) and the live vertex of
 // maximum degree, smallest id on ties (§IV-B). Results are the same in every thread.
-__device__ void max_degree_and_sum(const Node nd, Ctrl& c, int& vmax, int& dmax,
+__device__ __forceinline__ void max_degree_and_sum(const Node nd, Ctrl& c, int& vmax, int& dmax,
                                    int32_t& degsum) {
   const int n = nd.n;
   const int32_t* st = nd.st;
@@ -419,8 +446,9 @@ __device__ void max_degree_and_sum(const Node nd, Ctrl& c, int& vmax, int& dmax,
   degsum = sum;
 }
 
-// Mark every live neighbour of v (the "N(v) in the cover" child, §II-B) and remove them.
-__device__ void remove_neighbourhood(const Node nd, int v) {
+// Flag every live neighbour of v (the "N(v) in the cover" child, §II-B); the next reduce_node
+// (marked = true) removes them. Ends with a barrier.
+__device__ __forceinline__ void mark_neighbourhood(const Node nd, int v) {
   int32_t* st = nd.st;
   const int lane = lane_id();
   if (wave_id() == 0) {
@@ -431,20 +459,19 @@ __device__ void remove_neighbourhood(const Node nd, int v) {
     }
   }
   __syncthreads();
-  apply_marks(nd);
 }
 
-// Mark v alone (the "v in the cover" child, §II-B) and remove it.
-__device__ void remove_vertex(const Node nd, int v) {
+// Flag v alone (the "v in the cover" child, §II-B); the next reduce_node (marked = true)
+// removes it. Ends with a barrier.
+__device__ __forceinline__ void mark_vertex(const Node nd, int v) {
   if (threadIdx.x == 0) nd.st[v] |= kFlag;
   __syncthreads();
-  apply_marks(nd);
 }
 
 // Copy a node between LDS and device memory, 16 bytes per thread per step. The same thread
 // always handles the same words, so a node written to the workgroup's own stack is read back
 // by the threads that wrote it. `pending` replaces word n+1 on the way out.
-__device__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int stride, int n,
+__device__ __forceinline__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int stride, int n,
                            int pending) {
   const int4* s4 = reinterpret_cast<const int4*>(st);
   int4* d4 = reinterpret_cast<int4*>(dst);
@@ -464,13 +491,13 @@ __device__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int str
 
 // Copy a stored node between two device-memory slots with the same thread-to-word mapping as
 // node_store / node_load, so each thread reads back words it wrote itself.
-__device__ void node_copy(int32_t* __restrict__ dst, const int32_t* __restrict__ src, int stride) {
+__device__ __forceinline__ void node_copy(int32_t* __restrict__ dst, const int32_t* __restrict__ src, int stride) {
   const int4* s4 = reinterpret_cast<const int4*>(src);
   int4* d4 = reinterpret_cast<int4*>(dst);
   for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
 }
 
-__device__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stride) {
+__device__ __forceinline__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stride) {
   const int4* s4 = reinterpret_cast<const int4*>(src);
   int4* d4 = reinterpret_cast<int4*>(st);
   for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
@@ -481,9 +508,19 @@ __device__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stri
 // node array. The node operations take a plain pointer, so one body serves both; in device
 // memory their reads, writes and atomics are global-memory accesses, ordered inside the
 // workgroup by the same barriers.
-template <bool GLOBAL>
+// Where a launch keeps the node being worked on and the CSR it reads. Fixed per kernel
+// instantiation, so that every access compiles to an LDS (ds_*) or a device-memory (global_*)
+// instruction rather than a generic one that has to test its address.
+enum MemMode : int {
+  kMemGlobal = 0,  // node in device memory (graphs too large for LDS); CSR in device memory
+  kMemLds = 1,     // node in LDS; CSR in device memory
+  kMemLdsRp = 2,   // node and row pointers in LDS; column indices in device memory
+  kMemLdsCsr = 3,  // node and the whole CSR in LDS
+};
+
+template <int MEM>
 __device__ __forceinline__ int32_t* node_base(const Params& p, int slot) {
-  if constexpr (GLOBAL) {
+  if constexpr (MEM == kMemGlobal) {
     return p.gnodes + static_cast<size_t>(slot) * p.stride;
   } else {
     extern __shared__ int4 lds4[];
@@ -504,19 +541,23 @@ __device__ __forceinline__ int32_t* node_base(const Params& p, int slot) {
 // passes find them in this XCD's L2.
 constexpr int32_t kTouchMaxEntries = 1 << 18;
 
-__device__ Node load_instance(const Params& p, int j, int32_t* st, int32_t* heads) {
+template <int MEM>
+__device__ __forceinline__ Node load_instance(const Params& p, int j, int32_t* st,
+                                              int32_t* list) {
   const Instance in = p.inst[j];
   const int32_t* rp = p.rp_all + in.rp_off;
   const int32_t* ci = p.ci_all + in.ci_off;
-  if (p.rp_lds != 2 && !p.gnodes && in.nnz <= kTouchMaxEntries) {
-    int32_t acc = 0;
-    for (int i = threadIdx.x * 32; i < in.nnz; i += blockDim.x * 32) acc ^= ci[i];
-    asm volatile("" ::"v"(acc));
+  if constexpr (MEM == kMemLds || MEM == kMemLdsRp) {
+    if (in.nnz <= kTouchMaxEntries) {
+      int32_t acc = 0;
+      for (int i = threadIdx.x * 32; i < in.nnz; i += blockDim.x * 32) acc ^= ci[i];
+      asm volatile("" ::"v"(acc));
+    }
   }
-  if (p.rp_lds) {
+  if constexpr (MEM >= kMemLdsRp) {
     int32_t* dst = st + p.stride;
     for (int i = threadIdx.x; i <= in.n; i += blockDim.x) dst[i] = rp[i];
-    if (p.rp_lds == 2) {
+    if constexpr (MEM == kMemLdsCsr) {
       int32_t* dci = dst + rp_lds_words(p.n_max);
       for (int i = threadIdx.x; i < in.nnz; i += blockDim.x) dci[i] = ci[i];
       ci = dci;
@@ -524,12 +565,23 @@ __device__ Node load_instance(const Params& p, int j, int32_t* st, int32_t* head
     __syncthreads();
     rp = dst;
   }
-  return Node{st, in.n, rp, ci, heads};
+  return Node{st, in.n, rp, ci, list};
+}
+
+// A node with no instance yet, whose CSR pointers already point where this memory mode keeps
+// them (so that the compiler sees one kind of memory behind each pointer).
+template <int MEM>
+__device__ __forceinline__ Node empty_node(const Params& p, int32_t* st, int32_t* list) {
+  const int32_t* rp = p.rp_all;
+  const int32_t* ci = p.ci_all;
+  if constexpr (MEM >= kMemLdsRp) rp = st + p.stride;
+  if constexpr (MEM == kMemLdsCsr) ci = st + p.stride + rp_lds_words(p.n_max);
+  return Node{st, 0, rp, ci, list};
 }
 
 // Whole workgroup: the root of instance j in LDS -- the input's degree array, s = 0, nothing
 // pending, the instance in the last word. Ends with a barrier.
-__device__ void build_root(const Params& p, const Node nd, int j) {
+__device__ __forceinline__ void build_root(const Params& p, const Node nd, int j) {
   for (int v = threadIdx.x; v < p.stride; v += blockDim.x) {
     int32_t x = 0;
     if (v < nd.n) x = nd.rp[v + 1] - nd.rp[v];
@@ -565,7 +617,7 @@ __device__ __forceinline__ int instance_of_entry(const Params& p, int64_t i) {
 // Whole workgroup: donate a deferred child of instance `inst` to the worklist; true if the
 // worklist took it. The child is the stored node at `oldest` (the bottom of this workgroup's
 // stack) when that is not null, else the node in LDS with `pending` as its branch vertex.
-__device__ bool try_enqueue(const Params& p, const Node nd, Ctrl& c, int pending,
+__device__ __forceinline__ bool try_enqueue(const Params& p, const Node nd, Ctrl& c, int pending,
                             const int32_t* oldest, int inst) {
   if (!enqueue_begin(p, c, inst)) return false;
   int32_t* dst = p.payload + static_cast<size_t>(c.slot) * p.stride;
@@ -661,12 +713,15 @@ __global__ void prepare_kernel(Params p, DevResult* res, int64_t vertices, int64
 // §IV-E): degree-one and degree-two-triangle rules, then a maximum-degree vertex into the
 // cover, until no edge is left. One workgroup per instance (a grid-stride loop over the
 // launch's instances); the cover goes to the instance's cover output.
-template <bool GLOBAL>
+template <int MEM>
 __global__ void __launch_bounds__(1024) greedy_kernel(Params p) {
   __shared__ Ctrl c;
-  __shared__ int32_t heads[kMaxWaves * 64];
-  int32_t* st = node_base<GLOBAL>(p, blockIdx.x);
-  if (threadIdx.x == 0) c.flag_epoch = -1;
+  __shared__ int32_t rm_list[kListCap];
+  int32_t* st = node_base<MEM>(p, blockIdx.x);
+  if (threadIdx.x == 0) {
+    c.flag_epoch = -1;
+    c.list_n = 0;
+  }
   int epoch = 0;
   for (int j = blockIdx.x; j < p.num_inst; j += gridDim.x) {
     if (threadIdx.x == 0) c.err = load_relaxed(&p.ist[j].err_row) != kNoRow;
@@ -674,20 +729,20 @@ __global__ void __launch_bounds__(1024) greedy_kernel(Params p) {
     const bool skip = c.err;
     __syncthreads();  // every thread has read c.err before thread 0 writes it again
     if (skip) continue;
-    const Node nd = load_instance(p, j, st, heads);
+    const Node nd = load_instance<MEM>(p, j, st, rm_list);
     build_root(p, nd, j);
     const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
-    for (;;) {
-      reduce_node(nd, c, unbounded, kRuleDeg1 | kRuleTri, epoch);
+    for (bool marked = false;; marked = true) {
+      reduce_node(nd, c, unbounded, kRuleDeg1 | kRuleTri, epoch, marked);
       int vmax, dmax;
       int32_t degsum;
       max_degree_and_sum(nd, c, vmax, dmax, degsum);
       if (degsum == 0) break;
-      remove_vertex(nd, vmax);
+      mark_vertex(nd, vmax);
     }
     const int s = st[nd.n];
     uint8_t* cov = p.covers + p.inst[j].vtx_off;
-    for (int v = threadIdx.x; v < nd.n; v += blockDim.x) cov[v] = st[v] == kSent;
+    for (int v = threadIdx.x; v < nd.n; v += blockDim.x) cov[v] = st[v] < 0;
     if (threadIdx.x == 0) {
       p.ist[j].best = s;
       p.ist[j].greedy = s;
@@ -701,7 +756,7 @@ __global__ void __launch_bounds__(1024) greedy_kernel(Params p) {
 // the winner then takes the instance's lock, and keeps it only if no smaller cover has been
 // claimed meanwhile, so the last cover written under the lock is one of the final best size.
 template <bool PVC>
-__device__ int claim_solution(const Params& p, int j, int32_t s) {
+__device__ __forceinline__ int claim_solution(const Params& p, int j, int32_t s) {
   InstState* is = p.ist + j;
   if (PVC) return (atomicOr(&is->state, kInstFound) & kInstFound) == 0;
   if (atomicMin(&is->best, s) <= s) return 0;
@@ -713,7 +768,7 @@ __device__ int claim_solution(const Params& p, int j, int32_t s) {
 
 // Thread 0, after the whole workgroup has written the cover and fenced it: finish the claim.
 template <bool PVC>
-__device__ void publish_solution(const Params& p, int j, int32_t s) {
+__device__ __forceinline__ void publish_solution(const Params& p, int j, int32_t s) {
   InstState* is = p.ist + j;
   if (PVC) {
     store_relaxed(&is->best, s);
@@ -737,21 +792,24 @@ __device__ __forceinline__ void report_nodes(const Params& p, int j, int64_t cou
 // instance of the launch. A workgroup takes the root of an unstarted instance or a node from
 // the worklist, walks that node's sub-tree depth first with its stack, and loads an instance
 // (row pointers) only when the node it takes belongs to another one than the last.
-template <bool PVC, bool PROF, bool GLOBAL, bool SO>
+template <bool PVC, bool PROF, int MEM, bool SO>
 __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   __shared__ Ctrl c;
-  __shared__ int32_t heads[kMaxWaves * 64];
-  int32_t* st = node_base<GLOBAL>(p, blockIdx.x);
+  __shared__ int32_t rm_list[kListCap];
+  int32_t* st = node_base<MEM>(p, blockIdx.x);
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
   if (tid == 0) {
     c.flag_epoch = -1;
     c.stop = 0;
+    c.list_n = 0;
   }
   ActivityClock<PROF> clk;
   clk.begin();
   if (tid == 0) watch_begin(c);
   uint32_t headers = 0;  // thread 0: node headers read so far
+  uint64_t root_header = 0;   // thread 0: a root's header, loaded when the root was taken
+  bool header_ready = false;
 
   int32_t* stack = p.stacks + static_cast<size_t>(wg) * p.depth_cap * p.stride;
   // The stack is a ring of depth_cap entries holding [bot, top): pops take the top, donations
@@ -760,9 +818,10 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   int top = 0, bot = 0;
   bool have = false;      // a node is in LDS and still to be visited
   bool holding = false;   // this workgroup holds a sub-tree (a root or a worklist node)
+  bool marked = false;    // the node in LDS has flagged vertices still to be removed
   int cur = -1;           // instance of the node in LDS
   int32_t cur_k = 0, cur_vtx = 0;
-  Node nd{st, 0, nullptr, nullptr, heads};
+  Node nd = empty_node<MEM>(p, st, rm_list);
   int epoch = 0;
   int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0, insts = 0;
   int64_t unreported = 0;  // nodes on `cur` not yet added to its counter
@@ -771,6 +830,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
 
   for (;;) {
     if (!have) {
+      marked = false;   // whatever node comes next replaces the one in LDS
       __syncthreads();  // every thread has read the last broadcast before thread 0 writes
       if (top > bot) {
         --top;
@@ -782,7 +842,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         // StackOnly (the comparison method of §V-A), as in bitset_traverse_kernel: walk this
         // workgroup's next path down from the root, then take the node at the start depth.
         if (cur < 0) {
-          nd = load_instance(p, 0, st, heads);
+          nd = load_instance<MEM>(p, 0, st, rm_list);
           const Instance in = p.inst[0];
           cur = 0;
           cur_k = in.k;
@@ -816,7 +876,8 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
           const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(c.best) - 1;
           ++nodes;
           if (owner) ++unreported;
-          reduce_node(nd, c, bound, p.rules, epoch, clk);
+          reduce_node(nd, c, bound, p.rules, epoch, clk, marked);
+          marked = false;
           const int32_t s = st[nd.n];
           const int64_t r = bound - s;
           int vmax = 0, dmax = 0;
@@ -831,17 +892,17 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
               __syncthreads();
               if (c.status) {
                 uint8_t* cov = p.covers + cur_vtx;
-                for (int v = tid; v < nd.n; v += blockDim.x) cov[v] = st[v] == kSent;
+                for (int v = tid; v < nd.n; v += blockDim.x) cov[v] = st[v] < 0;
                 __threadfence();
                 __syncthreads();
                 if (tid == 0) publish_solution<PVC>(p, cur, s);
               }
             }
             reached = false;
-          } else if ((so_path >> d) & 1u) {
-            remove_neighbourhood(nd, vmax);
           } else {
-            remove_vertex(nd, vmax);
+            if ((so_path >> d) & 1u) mark_neighbourhood(nd, vmax);
+            else mark_vertex(nd, vmax);
+            marked = true;
           }
           __syncthreads();  // every thread has read c.* before thread 0 writes it again
         }
@@ -875,10 +936,18 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         }
         holding = true;
         clk.charge(kActAcquire);
+        // a root: its input check and its first header are loaded now, while the instance is
+        // being staged, instead of one after the other once it is
+        int32_t err_row = kNoRow;
+        if (got == 2 && tid == 0) {
+          err_row = load_relaxed(&p.ist[j].err_row);
+          root_header = inst_header(p, j);
+          header_ready = true;
+        }
         if (j != cur) {
           if (tid == 0 && cur >= 0) report_nodes(p, cur, unreported);
           unreported = 0;
-          nd = load_instance(p, j, st, heads);
+          nd = load_instance<MEM>(p, j, st, rm_list);
           const Instance in = p.inst[j];
           cur = j;
           cur_k = in.k;
@@ -887,10 +956,11 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         }
         if (got == 2) {
           // c.err, not c.status: slow waves may still be reading the dequeue status
-          if (tid == 0) c.err = load_relaxed(&p.ist[j].err_row) != kNoRow;
+          if (tid == 0) c.err = err_row != kNoRow;
           __syncthreads();
           if (c.err) {  // rejected input: no search (PVC: the instance is settled)
             if (PVC && tid == 0) fetch_add(ctr_i32(p, kOpen), -1);
+            header_ready = false;
             continue;
           }
           build_root(p, nd, j);
@@ -901,7 +971,8 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       if (pending >= 0) {
         __syncthreads();  // every thread has read the pending vertex
         if (tid == 0) st[nd.n + 1] = -1;
-        remove_neighbourhood(nd, pending);
+        mark_neighbourhood(nd, pending);
+        marked = true;
       }
       clk.charge(kActBranch);
       have = true;
@@ -910,7 +981,8 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     // node header: the instance's flags and current best (one load), and every 16 nodes
     // the launch-wide stop (idle workgroups also look at it while they wait for work)
     if (tid == 0) {
-      const uint64_t h = inst_header(p, cur);
+      const uint64_t h = header_ready ? root_header : inst_header(p, cur);
+      header_ready = false;
       const int32_t state = static_cast<int32_t>(h >> 32);
       if ((headers++ & 15) == 0) c.stop = search_stopped(p, c);
       c.drop = (state & kInstOutOfBudget) | (PVC ? (state & kInstFound) : 0);
@@ -933,7 +1005,8 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
     }
 
     const int64_t bound = PVC ? static_cast<int64_t>(cur_k) : static_cast<int64_t>(c.best) - 1;
-    reduce_node(nd, c, bound, p.rules, epoch, clk);
+    reduce_node(nd, c, bound, p.rules, epoch, clk, marked);
+    marked = false;
     clk.charge(kActReduce);
 
     // stopping condition (§II-B): no cover of size <= bound below this node if r < 0 or
@@ -959,7 +1032,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       __syncthreads();
       if (c.status) {
         uint8_t* cov = p.covers + cur_vtx;
-        for (int v = tid; v < n; v += blockDim.x) cov[v] = st[v] == kSent;
+        for (int v = tid; v < n; v += blockDim.x) cov[v] = st[v] < 0;
         __threadfence();
         __syncthreads();
         if (tid == 0) publish_solution<PVC>(p, cur, s);
@@ -998,7 +1071,8 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
       __syncthreads();  // the copy has read the node before it changes below
     }
     clk.charge(kActDonate);
-    remove_vertex(nd, vmax);
+    mark_vertex(nd, vmax);
+    marked = true;
     clk.charge(kActBranch);
   }
   clk.end();
@@ -1044,7 +1118,6 @@ __device__ void add_grouped(int32_t* dst, int32_t x) {
 // to the result block themselves.) Packed entry offsets must fit in int32.
 __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertices,
                                                        int64_t entries, DevResult* res) {
-  __shared__ int32_t heads[4 * 64];
   (void)entries;
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
   for (int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id();
@@ -1074,7 +1147,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertice
       ones_dst = &p.ist[j].cover_count;
     }
     add_grouped(ones_dst, one);
-    wave_expand_rows(p.ci_all, heads + 64 * wave_id(), beg, end, j, [&](int u, int jj, int) {
+    walk_rows(p.ci_all, beg, end, j, [&](int u, int jj, int) {
       if (p.covers[p.inst[jj].vtx_off + u] == 0) atomicAdd(&p.ist[jj].uncovered, 1);
     });
   }
@@ -1088,26 +1161,27 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertice
 
 // The reduction rules of one node, alone, on a degree array in device memory (instance 0 of
 // the launch, one workgroup). A rejected input leaves the degree array alone.
-template <bool GLOBAL>
+template <int MEM>
 __global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, int32_t* s,
                                                       int64_t bound) {
   __shared__ Ctrl c;
-  __shared__ int32_t heads[kMaxWaves * 64];
-  int32_t* st = node_base<GLOBAL>(p, 0);
+  __shared__ int32_t rm_list[kListCap];
+  int32_t* st = node_base<MEM>(p, 0);
   if (threadIdx.x == 0) {
     c.err = load_relaxed(&p.ist[0].err_row) != kNoRow;
     c.flag_epoch = -1;
+    c.list_n = 0;
   }
   __syncthreads();
   if (c.err) return;
-  const Node nd = load_instance(p, 0, st, heads);
+  const Node nd = load_instance<MEM>(p, 0, st, rm_list);
   const int n = nd.n;
   for (int v = threadIdx.x; v < p.stride; v += blockDim.x)
     st[v] = v < n ? deg[v] : (v == n ? *s : (v == n + 1 ? -1 : 0));
   __syncthreads();
   int epoch = 0;
   reduce_node(nd, c, bound, p.rules, epoch);
-  for (int v = threadIdx.x; v < n; v += blockDim.x) deg[v] = st[v] < 0 ? st[v] : (st[v] & kDegMask);
+  for (int v = threadIdx.x; v < n; v += blockDim.x) deg[v] = st[v] < 0 ? kSent : (st[v] & kDegMask);
   if (threadIdx.x == 0) *s = st[n];
 }
 
@@ -1151,30 +1225,55 @@ hipError_t launch_prepare(const Params& p, DevResult* res, int64_t vertices, int
 // node array needs this many slots.
 int greedy_grid(const Params& p) { return p.num_inst < 65535 ? p.num_inst : 65535; }
 
+// Memory mode of a launch: node in device memory, else in LDS with the row pointers (rp_lds 1)
+// or the whole CSR (rp_lds 2) staged after it.
+static int mem_mode(bool global_node, int32_t rp_lds) {
+  if (global_node) return kMemGlobal;
+  return rp_lds >= 2 ? kMemLdsCsr : (rp_lds == 1 ? kMemLdsRp : kMemLds);
+}
+
+template <int MEM>
+static size_t launch_lds(const Params& p) {
+  return MEM == kMemGlobal ? 0 : node_lds_bytes(p.stride, p.n_max, p.rp_lds, p.nnz_max);
+}
+
+template <int MEM>
+static void greedy_on(const Params& p, int32_t wg_size, hipStream_t stream) {
+  hipLaunchKernelGGL(greedy_kernel<MEM>, dim3(greedy_grid(p)), dim3(wg_size), launch_lds<MEM>(p),
+                     stream, p);
+}
+
 hipError_t launch_greedy(const Params& p, int32_t wg_size, hipStream_t stream) {
-  if (p.gnodes) {
-    hipLaunchKernelGGL(greedy_kernel<true>, dim3(greedy_grid(p)), dim3(wg_size), 0, stream, p);
-  } else {
-    const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds, p.nnz_max);
-    hipLaunchKernelGGL(greedy_kernel<false>, dim3(greedy_grid(p)), dim3(wg_size), lds, stream, p);
+  switch (mem_mode(p.gnodes != nullptr, p.rp_lds)) {
+    case kMemGlobal: greedy_on<kMemGlobal>(p, wg_size, stream); break;
+    case kMemLds: greedy_on<kMemLds>(p, wg_size, stream); break;
+    case kMemLdsRp: greedy_on<kMemLdsRp>(p, wg_size, stream); break;
+    default: greedy_on<kMemLdsCsr>(p, wg_size, stream); break;
   }
   return hipGetLastError();
 }
 
-template <bool GLOBAL, bool SO>
-static const void* traverse_fn_g(bool pvc, bool prof) {
-  if (pvc) return prof ? reinterpret_cast<const void*>(&traverse_kernel<true, true, GLOBAL, SO>)
-                       : reinterpret_cast<const void*>(&traverse_kernel<true, false, GLOBAL, SO>);
-  return prof ? reinterpret_cast<const void*>(&traverse_kernel<false, true, GLOBAL, SO>)
-              : reinterpret_cast<const void*>(&traverse_kernel<false, false, GLOBAL, SO>);
+template <int MEM, bool SO>
+static const void* traverse_fn_m(bool pvc, bool prof) {
+  if (pvc) return prof ? reinterpret_cast<const void*>(&traverse_kernel<true, true, MEM, SO>)
+                       : reinterpret_cast<const void*>(&traverse_kernel<true, false, MEM, SO>);
+  return prof ? reinterpret_cast<const void*>(&traverse_kernel<false, true, MEM, SO>)
+              : reinterpret_cast<const void*>(&traverse_kernel<false, false, MEM, SO>);
 }
 
 // The StackOnly walk-down is a separate instantiation, so the hybrid kernels carry none of its
 // registers.
-static const void* traverse_fn(bool pvc, bool prof, bool global_node, bool stack_only = false) {
-  if (stack_only)
-    return global_node ? traverse_fn_g<true, true>(pvc, prof) : traverse_fn_g<false, true>(pvc, prof);
-  return global_node ? traverse_fn_g<true, false>(pvc, prof) : traverse_fn_g<false, false>(pvc, prof);
+template <bool SO>
+static const void* traverse_fn_s(bool pvc, bool prof, int mem) {
+  switch (mem) {
+    case kMemGlobal: return traverse_fn_m<kMemGlobal, SO>(pvc, prof);
+    case kMemLds: return traverse_fn_m<kMemLds, SO>(pvc, prof);
+    case kMemLdsRp: return traverse_fn_m<kMemLdsRp, SO>(pvc, prof);
+    default: return traverse_fn_m<kMemLdsCsr, SO>(pvc, prof);
+  }
+}
+static const void* traverse_fn(bool pvc, bool prof, int mem, bool stack_only = false) {
+  return stack_only ? traverse_fn_s<true>(pvc, prof, mem) : traverse_fn_s<false>(pvc, prof, mem);
 }
 
 // A plain launch: the grid is sized by the occupancy API so that all workgroups are normally
@@ -1188,8 +1287,8 @@ hipError_t launch_traverse(bool pvc, bool prof, const Params& p, int32_t wg_size
   const size_t lds = global_node ? 0 : node_lds_bytes(p.stride, p.n_max, p.rp_lds, p.nnz_max);
   Params args = p;
   void* kargs[] = {&args};
-  return hipLaunchKernel(traverse_fn(pvc, prof, global_node, p.start_depth > 0), dim3(p.num_wg),
-                         dim3(wg_size), kargs, lds, stream);
+  return hipLaunchKernel(traverse_fn(pvc, prof, mem_mode(global_node, p.rp_lds), p.start_depth > 0),
+                         dim3(p.num_wg), dim3(wg_size), kargs, lds, stream);
 }
 
 hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, DevResult* res,
@@ -1200,13 +1299,20 @@ hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, D
   return hipGetLastError();
 }
 
+template <int MEM>
+static void reduce_on(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s, int64_t bound,
+                      hipStream_t stream) {
+  hipLaunchKernelGGL(reduce_kernel<MEM>, dim3(1), dim3(wg_size), launch_lds<MEM>(p), stream, p, deg,
+                     s, bound);
+}
+
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
                          int64_t bound, hipStream_t stream) {
-  if (p.gnodes) {
-    hipLaunchKernelGGL(reduce_kernel<true>, dim3(1), dim3(wg_size), 0, stream, p, deg, s, bound);
-  } else {
-    const size_t lds = node_lds_bytes(p.stride, p.n_max, p.rp_lds, p.nnz_max);
-    hipLaunchKernelGGL(reduce_kernel<false>, dim3(1), dim3(wg_size), lds, stream, p, deg, s, bound);
+  switch (mem_mode(p.gnodes != nullptr, p.rp_lds)) {
+    case kMemGlobal: reduce_on<kMemGlobal>(p, wg_size, deg, s, bound, stream); break;
+    case kMemLds: reduce_on<kMemLds>(p, wg_size, deg, s, bound, stream); break;
+    case kMemLdsRp: reduce_on<kMemLdsRp>(p, wg_size, deg, s, bound, stream); break;
+    default: reduce_on<kMemLdsCsr>(p, wg_size, deg, s, bound, stream); break;
   }
   return hipGetLastError();
 }
@@ -1216,20 +1322,32 @@ hipError_t launch_max_greedy(const Params& p, int32_t* out, hipStream_t stream) 
   return hipGetLastError();
 }
 
-hipError_t traverse_occupancy(bool pvc, bool prof, bool global_node, int32_t wg_size,
-                              size_t lds_bytes, int* blocks_per_cu) {
-  const void* fn = traverse_fn(pvc, prof, global_node);
+hipError_t traverse_occupancy(bool pvc, bool prof, bool global_node, int32_t rp_lds,
+                              int32_t wg_size, size_t lds_bytes, int* blocks_per_cu) {
+  const void* fn = traverse_fn(pvc, prof, mem_mode(global_node, rp_lds));
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn, wg_size, lds_bytes);
 }
 
 hipError_t set_lds_limit(size_t lds_bytes) {
-  const void* fns[] = {traverse_fn(true, false, false), traverse_fn(false, false, false),
-                       traverse_fn(true, true, false), traverse_fn(false, true, false),
-                       traverse_fn(true, false, false, true), traverse_fn(false, false, false, true),
-                       traverse_fn(true, true, false, true), traverse_fn(false, true, false, true),
-                       reinterpret_cast<const void*>(&greedy_kernel<false>),
-                       reinterpret_cast<const void*>(&reduce_kernel<false>)};
-  for (const void* fn : fns) {
+  for (int mem = kMemLds; mem <= kMemLdsCsr; ++mem) {
+    const void* fns[] = {traverse_fn(true, false, mem), traverse_fn(false, false, mem),
+                         traverse_fn(true, true, mem), traverse_fn(false, true, mem),
+                         traverse_fn(true, false, mem, true), traverse_fn(false, false, mem, true),
+                         traverse_fn(true, true, mem, true), traverse_fn(false, true, mem, true)};
+    for (const void* fn : fns) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                         static_cast<int>(lds_bytes));
+      if (e != hipSuccess) return e;
+    }
+  }
+  const void* others[] = {
+      reinterpret_cast<const void*>(&greedy_kernel<kMemLds>),
+      reinterpret_cast<const void*>(&greedy_kernel<kMemLdsRp>),
+      reinterpret_cast<const void*>(&greedy_kernel<kMemLdsCsr>),
+      reinterpret_cast<const void*>(&reduce_kernel<kMemLds>),
+      reinterpret_cast<const void*>(&reduce_kernel<kMemLdsRp>),
+      reinterpret_cast<const void*>(&reduce_kernel<kMemLdsCsr>)};
+  for (const void* fn : others) {
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        static_cast<int>(lds_bytes));
     if (e != hipSuccess) return e;

@@ -128,6 +128,7 @@ struct Ctrl {
   int32_t stop;        // broadcast: the launch is being stopped
   int32_t err;         // broadcast: the instance's input graph was rejected
   int32_t drop;        // broadcast: the current instance is answered or out of budget
+  int32_t list_n;      // degree-array removal step: vertices appended to the removal list
   uint64_t red_key[kMaxWaves];
   int32_t red_sum[kMaxWaves];
 };
@@ -223,8 +224,9 @@ __device__ inline bool watchdog(const Params& p, Ctrl& c) {
 // Thread 0: is the search being stopped: aborted (an internal error, the host, the time
 // limit), or (PVC) every instance answered?
 __device__ __forceinline__ bool search_stopped(const Params& p, Ctrl& c) {
-  return watchdog(p, c) || load_relaxed(ctr_i32(p, kAbort)) != 0 ||
-         (p.pvc && load_relaxed(ctr_i32(p, kOpen)) == 0);
+  const int32_t aborted = load_relaxed(ctr_i32(p, kAbort));  // both words in one round trip
+  const int32_t open = p.pvc ? load_relaxed(ctr_i32(p, kOpen)) : 1;
+  return watchdog(p, c) || aborted != 0 || open == 0;
 }
 
 // Spin lock taken by one thread for a short critical section with no waits inside (an
@@ -290,49 +292,71 @@ __device__ inline void enqueue_publish(const Params& p, const Ctrl& c) {
   if (threadIdx.x == 0) store_release(p.seq + slot, 2u * lap + 1u);
 }
 
+// Thread 0: one look for work. Returns 1 with *slot / *lap set when it has claimed a worklist
+// ticket (the caller then waits for that slot to be filled), 2 with *root set to an instance
+// whose search has not started, 0 when the launch is finished, -1 when it is being stopped
+// (looked at only with check_stop), 3 when nothing is available yet. Queued nodes of started
+// instances go first; roots are taken in instance order. The entry count, the root counter
+// and the stop words are loaded together (one round trip); the outstanding-work counter, a
+// line that every finished sub-tree updates, is read only when neither of the first two
+// offers work.
+__device__ inline int worklist_take(const Params& p, Ctrl& c, bool check_stop, uint32_t* slot,
+                                    uint32_t* lap, int32_t* root) {
+  int32_t* count = ctr_i32(p, kQCount);
+  int32_t* root_next = ctr_i32(p, kRootNext);
+  const int32_t queued = load_relaxed(count);
+  const int32_t next = load_relaxed(root_next);
+  const int32_t aborted = check_stop ? load_relaxed(ctr_i32(p, kAbort)) : 0;
+  const int32_t open = check_stop && p.pvc ? load_relaxed(ctr_i32(p, kOpen)) : 1;
+  if (check_stop && (aborted != 0 || open == 0 || watchdog(p, c))) return -1;
+  if (queued > 0) {
+    if (fetch_add(count, -1) > 0) {
+      const unsigned long long h = fetch_add(ctr_u64(p, kQHead), 1ull);
+      *slot = static_cast<uint32_t>(h) & (p.q_cap - 1);
+      *lap = static_cast<uint32_t>(h / p.q_cap);
+      return 1;
+    }
+    fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
+    return 3;
+  }
+  if (next < p.num_inst) {
+    const int32_t r = fetch_add(root_next, 1);
+    if (r < p.num_inst) {
+      *root = r;
+      return 2;
+    }
+    return 3;
+  }
+  // nothing queued, held or unstarted: the launch is over
+  return load_relaxed(ctr_i32(p, kWork)) == 0 ? 0 : 3;
+}
+
 // Whole workgroup: wait for work. Returns 1 with c.slot / c.lap set for a worklist entry (the
 // caller reads the node, then calls dequeue_finish), 2 with c.slot set to an instance whose
 // search has not started (its root), 0 when the whole launch is finished, -1 when it is being
-// stopped. Queued nodes of started instances go first; roots are taken in instance order. An
-// idle workgroup polls the entry count (and, while the list is empty, the outstanding-work
-// counter) with exponential back-off, and looks at the stop flags every fourth poll.
+// stopped. An idle workgroup looks again with exponential back-off, and at the stop flags every
+// fourth look.
 __device__ inline int dequeue_begin(const Params& p, Ctrl& c) {
   int polls = 0;
   for (;;) {
     if (threadIdx.x == 0) {
-      int status = 3;  // nothing available yet: retry
-      int32_t* count = ctr_i32(p, kQCount);
-      if ((polls & 3) == 0 && search_stopped(p, c)) {
-        status = -1;
-      } else if (load_relaxed(count) > 0) {
-        if (fetch_add(count, -1) > 0) {
-          const unsigned long long h = fetch_add(ctr_u64(p, kQHead), 1ull);
-          const uint32_t slot = static_cast<uint32_t>(h) & (p.q_cap - 1);
-          const uint32_t lap = static_cast<uint32_t>(h / p.q_cap);
-          int wait = 0;
-          status = 1;
-          while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
-            if (search_stopped(p, c)) {
-              status = -1;
-              break;
-            }
-            backoff(wait);
+      uint32_t slot = 0, lap = 0;
+      int32_t root = 0;
+      int status = worklist_take(p, c, (polls & 3) == 0, &slot, &lap, &root);
+      if (status == 1) {
+        int wait = 0;
+        while (load_acquire(p.seq + slot) != 2u * lap + 1u) {
+          if (search_stopped(p, c)) {
+            status = -1;
+            break;
           }
-          c.slot = slot;
-          c.lap = lap;
-        } else {
-          fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
+          backoff(wait);
         }
-      } else if (load_relaxed(ctr_i32(p, kRootNext)) < p.num_inst) {
-        const int32_t r = fetch_add(ctr_i32(p, kRootNext), 1);
-        if (r < p.num_inst) {
-          status = 2;
-          c.slot = static_cast<uint32_t>(r);
-        }
-      } else if (load_relaxed(ctr_i32(p, kWork)) == 0) {
-        status = 0;  // nothing queued, held or unstarted: the launch is over
-      }
-      if (status == 3) {
+        c.slot = slot;
+        c.lap = lap;
+      } else if (status == 2) {
+        c.slot = static_cast<uint32_t>(root);
+      } else if (status == 3) {
         const int units = 1 << (polls < 5 ? polls : 5);
         for (int i = 0; i < units; ++i) __builtin_amdgcn_s_sleep(16);
         ++polls;

@@ -279,8 +279,8 @@ struct Plan {
 
 // Resident workgroups per CU, from the occupancy API, remembered per context.
 int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, int n_max,
-              int* out, bool global_node = false) {
-  const int family = words ? 1 : (global_node ? 2 : 0);
+              int* out, bool global_node = false, int rp_lds = 0) {
+  const int family = words ? 1 : (global_node ? 2 : 3 + rp_lds);
   const auto key = std::make_tuple(family, pvc ? 1 : 0, prof ? 1 : 0, ws, words, lds);
   const auto it = ctx->occupancy.find(key);
   if (it != ctx->occupancy.end()) {
@@ -288,7 +288,7 @@ int occupancy(vc_ctx* ctx, int words, bool pvc, bool prof, int ws, size_t lds, i
     return VC_OK;
   }
   if (words) VC_HIP(ctx, vc::bitset_occupancy(words, pvc, prof, lds, out));
-  else VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, global_node, ws, lds, out));
+  else VC_HIP(ctx, vc::traverse_occupancy(pvc, prof, global_node, rp_lds, ws, lds, out));
   ctx->occupancy[key] = *out;
   return VC_OK;
 }
@@ -359,7 +359,7 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int64_t nnz_max, int32_t w
     // Keep row_ptr in LDS too when that costs no resident workgroup.
     if (!pl.global_node && lds_rp + 1024 <= lds_cap) {
       int occ_rp = 0;
-      if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_rp, n_max, &occ_rp))) return rc;
+      if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_rp, n_max, &occ_rp, false, 1))) return rc;
       if (occ_rp == best_occ) {
         pl.rp_lds = 1;
         pl.lds = lds_rp;
@@ -369,7 +369,8 @@ int plan_launch(vc_ctx* ctx, bool pvc, int32_t n_max, int64_t nnz_max, int32_t w
     // rule pass is a chain of dependent row walks, which then read LDS instead of L2 or HBM.
     if (csr_fits) {
       int occ_csr = 0;
-      if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_csr, n_max, &occ_csr))) return rc;
+      if ((rc = occupancy(ctx, 0, pvc, prof, best_ws, lds_csr, n_max, &occ_csr, false, 2)))
+        return rc;
       if (occ_csr >= 1 && 2 * occ_csr >= best_occ) {
         pl.rp_lds = 2;
         pl.lds = lds_csr;

@@ -212,8 +212,8 @@ hipError_t launch_finalize(const Params& p, int64_t vertices, int64_t entries, D
                            hipStream_t stream);
 hipError_t launch_reduce(const Params& p, int32_t wg_size, int32_t* deg, int32_t* s,
                          int64_t bound, hipStream_t stream);
-hipError_t traverse_occupancy(bool pvc, bool prof, bool global_node, int32_t wg_size,
-                              size_t lds_bytes, int* blocks_per_cu);
+hipError_t traverse_occupancy(bool pvc, bool prof, bool global_node, int32_t rp_lds,
+                              int32_t wg_size, size_t lds_bytes, int* blocks_per_cu);
 hipError_t set_lds_limit(size_t lds_bytes);
 hipError_t launch_max_greedy(const Params& p, int32_t* out, hipStream_t stream);
 
