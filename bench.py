@@ -498,13 +498,13 @@ def cpu_baseline(workload, insts):
             r = oracle.mvc(g)
             dt = time.perf_counter() - t
             nodes += r.nodes
-            fam[label] = {"seed": seed, "nodes": r.nodes, "seconds": round(dt, 3),
+            fam[label] = {"seed": seed, "nodes": r.nodes, "seconds": round(dt, 6),
                           "nodes_per_s": r.nodes / dt, "size": r.size}
         dt = time.perf_counter() - t0
         return {"value": nodes / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
                 "sample": "whole searches of one instance per family: "
                           + ", ".join(f"{k} seed {v['seed']}" for k, v in fam.items()),
-                "seconds": round(dt, 3), "families": fam,
+                "seconds": round(dt, 6), "families": fam,
                 "instances_per_s": len(fam) / dt,
                 "time_to_solve_ms": round(1000 * dt / len(fam), 3)}
     t0 = time.perf_counter()
@@ -520,7 +520,7 @@ def cpu_baseline(workload, insts):
     dt = time.perf_counter() - t0
     return {"value": nodes / dt, "unit": "nodes/s", "cores": 1, "kind": "oracle",
             "sample": f"all {len(insts)} instances of the workload, {passes} passes",
-            "seconds": round(dt, 3), "instances_per_s": solved / dt,
+            "seconds": round(dt, 6), "instances_per_s": solved / dt,
             "time_to_solve_ms": round(1000 * dt / solved, 4)}
 
 
