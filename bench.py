@@ -442,9 +442,13 @@ def summarize_trace(workload, directory, steps):
         trows = list(csv.DictReader(fh))
     per = {}
     for r in trows:
-        if "traverse_kernel" in r["Kernel_Name"]:
-            per.setdefault(r["Kernel_Name"], []).append(
-                (int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        name = r["Kernel_Name"]
+        if "traverse_kernel" in name:
+            # one launch per kernel family and call: the degree-array kernel's instantiations
+            # (its memory-mode argument differs between the autotuner's trials) are one family
+            key = ("degree arrays: " + name.split("<")[0]) if "bitset" not in name else name
+            per.setdefault(key, []).append(
+                (int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]), name))
     lines = [f"# Kernel trace: {workload}\n",
              "Command (from /tmp, with TMPDIR=/tmp):\n",
              "```",
@@ -460,11 +464,12 @@ def summarize_trace(workload, directory, steps):
         name = r["Name"] if len(r["Name"]) <= 80 else r["Name"][:77] + "..."
         lines.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f} |")
-    lines += ["", f"Timed steps only (the last {steps} dispatches of each traversal kernel):", "",
-              "| kernel | average over the timed steps (us) |", "|---|---|"]
+    lines += ["", f"Timed steps only (the last {steps} dispatches of each traversal kernel family):",
+              "", "| kernel | average over the timed steps (us) |", "|---|---|"]
     for k, v in sorted(per.items()):
         v = sorted(v)[-steps:]
-        lines.append(f"| `{k}` | {statistics.mean(d for _, d in v) / 1e3:.1f} |")
+        names = sorted({n for _, _, n in v})
+        lines.append(f"| `{' / '.join(names)}` | {statistics.mean(d for _, d, _ in v) / 1e3:.1f} |")
     text = "\n".join(lines) + "\n"
     with open(os.path.join(ROOT, "profiles", f"kernel_trace_{workload}.md"), "w") as f:
         f.write(text)

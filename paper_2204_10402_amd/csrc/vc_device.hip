@@ -57,39 +57,89 @@ constexpr int32_t kDegMask = 0x1FFFFFFF;  // degree bits of a live entry
 // Entries of the removal list: the vertices one removal step takes out, gathered from every
 // wavefront's part of the node so that the wavefronts can share their rows evenly.
 constexpr int kListCap = 1024;
+// Workgroups of fewer wavefronts than this skip the removal list (one or two wavefronts have
+// little to balance, and the list's append and read-back lengthen every removal step).
+constexpr int kListWaves = 4;
 
 struct Node {
   int32_t* st;
   int n;
   const int32_t* __restrict__ rp;
   const int32_t* __restrict__ ci;
-  int32_t* list;  // kListCap LDS words: the removal list
+  int32_t* list;   // kListCap LDS words: the removal list
+  int32_t* heads;  // 64 LDS words per wavefront for walk_rows
 };
+
+// Inclusive max-scan over the 64 lanes (DPP, as wave_incl_scan), identity -1.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ int32_t dpp_or_minus1(int32_t x) {
+  return __builtin_amdgcn_update_dpp(-1, x, CTRL, ROW_MASK, 0xF, false);
+}
+__device__ __forceinline__ int32_t wave_incl_max(int32_t x) {
+  x = max(x, dpp_or_minus1<0x111, 0xF>(x));
+  x = max(x, dpp_or_minus1<0x112, 0xF>(x));
+  x = max(x, dpp_or_minus1<0x114, 0xF>(x));
+  x = max(x, dpp_or_minus1<0x118, 0xF>(x));
+  x = max(x, dpp_or_minus1<0x142, 0xA>(x));
+  x = max(x, dpp_or_minus1<0x143, 0xC>(x));
+  return x;
+}
+
+// Rows longer than this are walked in 64-entry pieces; shorter ones are packed together.
+constexpr int kLongRow = 64;
 
 // Walk the CSR rows [beg, end) held by the lanes of a wavefront (empty where beg >= end).
 // fn(x, tag, j) runs for every entry x = ci[j], with `tag` the value the row's owner lane
-// passed in; it runs in divergent code. A row of at most kLaneRow entries is walked by its own
-// lane, eight entries per round. Longer rows are cut into 64-entry pieces that the whole
-// wavefront walks one after another, eight pieces per round, with the cursor (row bounds, tag,
-// position) in scalar registers. Either way a lane has eight independent loads in flight
-// before it uses the first, and no step needs the owner of an entry to be looked up.
-constexpr int kLaneRow = 32;
-
+// passed in; it runs in divergent code. `heads` is this wavefront's 64 LDS words.
+//  - Rows of at most kLongRow entries are walked as one list, 64 consecutive entries per step,
+//    so many short rows fill one step and neighbouring lanes read neighbouring entries. The
+//    owner of each entry of a step comes from head flags: every row writes its lane into
+//    `heads` at its first position in the step, and a max-scan over the lanes carries it
+//    forward. Eight steps are issued together, with unconditional loads (an index past the
+//    list reads entry 0, whose value is discarded).
+//  - Longer rows are cut into 64-entry pieces that the whole wavefront walks one after
+//    another, eight pieces per round, with the cursor (row bounds, tag, position) in scalar
+//    registers: a piece needs no owner lookup.
 template <typename Fn>
-__device__ __forceinline__ void walk_rows(const int32_t* __restrict__ ci, int beg, int end,
-                                          int tag, Fn fn) {
+__device__ __forceinline__ void walk_rows(const int32_t* __restrict__ ci, int32_t* heads, int beg,
+                                          int end, int tag, Fn fn) {
   const int lane = lane_id();
-  const int len = end > beg ? end - beg : 0;
-  const bool own = len <= kLaneRow;
-  for (int j0 = 0; __builtin_amdgcn_ballot_w64(own && j0 < len); j0 += 8) {
-    int xs[8];
+  const int full = end > beg ? end - beg : 0;
+  const bool longrow = full > kLongRow;
+  const int len = longrow ? 0 : full;
+  const int incl = wave_incl_scan(len);
+  const int excl = incl - len;
+  const int total = __builtin_amdgcn_readlane(incl, 63);
+  constexpr int kUnroll = 8;
+  for (int t0 = 0; t0 < total; t0 += 64 * kUnroll) {
+    int xs[kUnroll], tags[kUnroll], js[kUnroll];
+    bool ok[kUnroll];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) xs[u] = own && j0 + u < len ? ci[beg + j0 + u] : 0;
+    for (int u = 0; u < kUnroll; ++u) {
+      ok[u] = false;
+      const int s0 = t0 + u * 64;
+      if (s0 < total) {  // uniform: only as many steps as the rows need
+        heads[lane] = -1;
+        __builtin_amdgcn_wave_barrier();
+        if (len > 0 && excl < s0 + 64 && incl > s0) heads[excl > s0 ? excl - s0 : 0] = lane;
+        __builtin_amdgcn_wave_barrier();
+        const int i = wave_incl_max(heads[lane]);  // owner of entry s0 + lane
+        __builtin_amdgcn_wave_barrier();
+        const int t = s0 + lane;
+        const int src = i < 0 ? 0 : i;  // i < 0 only past the end of the list
+        const int ob = shfl(beg, src);
+        const int oe = shfl(excl, src);
+        tags[u] = shfl(tag, src);
+        ok[u] = t < total;
+        js[u] = ok[u] ? ob + (t - oe) : 0;
+        xs[u] = ci[js[u]];  // not read until every step has issued
+      }
+    }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (own && j0 + u < len) fn(xs[u], tag, beg + j0 + u);
+    for (int u = 0; u < kUnroll; ++u)
+      if (ok[u]) fn(xs[u], tags[u], js[u]);
   }
-  uint64_t longs = __builtin_amdgcn_ballot_w64(!own);
+  uint64_t longs = __builtin_amdgcn_ballot_w64(longrow);
   int rb = 0, re = 0, rt = 0;  // the piece cursor: next entry, end and tag of the current row
   while (longs || rb < re) {
     int xs[8], js[8], ts[8];
@@ -148,8 +198,9 @@ __device__ __forceinline__ void for_each_batch(const int32_t* st, int n, Pred pr
 // neighbour. The scan sets each marked vertex to kSent and appends it to the workgroup's
 // removal list; after a barrier the wavefronts take the list's rows round-robin (list entry i
 // goes to wavefront i mod waves), so a few marked vertices with long rows in one wavefront's
-// part of the node do not leave the others idle. Vertices beyond the list's capacity are
-// walked by the wavefront that found them. The walks only decrement entries that are live and
+// part of the node do not leave the others idle. Marked vertices beyond the list's capacity
+// stay marked and are taken by further rounds of scan and walk. Workgroups of fewer than
+// kListWaves wavefronts skip the list: each wavefront walks the rows it finds. The walks only decrement entries that are live and
 // unmarked (a marked vertex is set to kSent by the scan, whichever of the two happens first),
 // which also keeps the LDS atomics off the entries of vertices already removed. Called right
 // after a barrier that ends a decide step (or a mark step); ends with a barrier. Two calls are
@@ -159,56 +210,67 @@ __device__ __forceinline__ void apply_marks(const Node nd, Ctrl& c) {
   const int n = nd.n;
   int32_t* st = nd.st;
   const int lane = lane_id();
-  const auto walk = [&](int f, bool mine) {
-    walk_rows(nd.ci, mine ? nd.rp[f] : 0, mine ? nd.rp[f + 1] : 0, f,
-              [&](int x, int, int) {
-                const int32_t dx = st[x];
-                if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
-              });
-  };
-  int held = -1, count = 0;  // this wavefront's overflow batch
-  for (int base = wave_id() * 64; base < n; base += blockDim.x) {
-    const int v = base + lane;
-    const int32_t d = v < n ? st[v] : kSent;
-    const bool marked = v < n && d >= 0 && (d & kFlag);
-    const uint64_t mask = __builtin_amdgcn_ballot_w64(marked);
-    if (!mask) continue;
-    int at = 0;
-    if (lane == 0) at = atomicAdd(&c.list_n, __popcll(mask));
-    at = __builtin_amdgcn_readfirstlane(at);
-    const int rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
-    const bool fits = at + rank < kListCap;
-    if (marked) {
-      st[v] = kSent;
-      if (fits) nd.list[at + rank] = v;
-    }
-    const uint64_t over = __builtin_amdgcn_ballot_w64(marked && !fits);
-    if (over) {  // rare: more marked vertices than the list holds
-      const int cnt = __popcll(over);
-      if (count + cnt > 64) {
-        walk(held, lane < count);
-        held = -1;
-        count = 0;
-      }
-      const int k = lane - count;
-      const bool take = k >= 0 && k < cnt;
-      const int got = shfl(v, take ? kth_set_bit(over, k) : lane);
-      if (take) held = got;
-      count += cnt;
-    }
-  }
-  if (count) walk(held, lane < count);
-  __syncthreads();
-  const int total = c.list_n;
-  const int listed = total < kListCap ? total : kListCap;
   const int waves = blockDim.x >> 6;
-  for (int i0 = wave_id(); i0 < listed; i0 += waves * 64) {
-    const int i = i0 + waves * lane;
-    walk(i < listed ? nd.list[i] : 0, i < listed);
+  const auto decrement = [&](int x, int, int) {
+    const int32_t dx = st[x];
+    if (dx >= 0 && !(dx & kFlag)) atomicSub(&st[x], 1);
+  };
+  if (waves < kListWaves) {
+    // few wavefronts, little to balance: each walks the rows of the marked vertices it finds
+    int cnt = 0;
+    for_each_batch(st, n,
+                   [&](int v, int32_t d) {
+                     const bool marked = d >= 0 && (d & kFlag);
+                     if (marked) {
+                       st[v] = kSent;
+                       ++cnt;
+                     }
+                     return marked;
+                   },
+                   [&](int f, int count) {
+                     const bool mine = lane < count;
+                     walk_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[f] : 0,
+                               mine ? nd.rp[f + 1] : 0, f, decrement);
+                   });
+    cnt = wave_sum(cnt);
+    if (lane == 0 && cnt) atomicAdd(&st[n], cnt);
+    __syncthreads();
+    return;
   }
-  if (threadIdx.x == 0) st[n] += total;
-  __syncthreads();
+  for (;;) {
+    for (int base = wave_id() * 64; base < n; base += blockDim.x) {
+      const int v = base + lane;
+      const int32_t d = v < n ? st[v] : kSent;
+      const bool marked = v < n && d >= 0 && (d & kFlag);
+      const uint64_t mask = __builtin_amdgcn_ballot_w64(marked);
+      if (!mask) continue;
+      int at = 0;
+      if (lane == 0) at = atomicAdd(&c.list_n, __popcll(mask));
+      at = __builtin_amdgcn_readfirstlane(at);
+      const int rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+      if (marked && at + rank < kListCap) {  // beyond the list: left marked for the next round
+        st[v] = kSent;
+        nd.list[at + rank] = v;
+      }
+    }
+    __syncthreads();
+    const int total = c.list_n;
+    const int listed = total < kListCap ? total : kListCap;
+    for (int i0 = wave_id(); i0 < listed; i0 += waves * 64) {
+      const int i = i0 + waves * lane;
+      const bool mine = i < listed;
+      const int f = mine ? nd.list[i] : 0;
+      walk_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[f] : 0, mine ? nd.rp[f + 1] : 0, f,
+                decrement);
+    }
+    if (threadIdx.x == 0) st[n] += listed;
+    __syncthreads();
+    if (total <= kListCap) break;
+    // rare: more marked vertices than the list holds; the rest go in another round
+    if (threadIdx.x == 0) c.list_n = 0;
+    __syncthreads();
+  }
   if (threadIdx.x == 0) c.list_n = 0;
 }
 
@@ -221,7 +283,8 @@ __device__ __forceinline__ void decide_degree_one(const Node nd, Ctrl& c, int ep
   for_each_batch(st, nd.n, [](int, int32_t d) { return d >= 0 && (d & kDegMask) == 1; },
                  [&](int cv, int count) {
                    const bool mine = lane_id() < count;
-                   walk_rows(nd.ci, mine ? nd.rp[cv] : 0, mine ? nd.rp[cv + 1] : 0, cv,
+                   walk_rows(nd.ci, nd.heads + 64 * wave_id(), mine ? nd.rp[cv] : 0,
+                             mine ? nd.rp[cv + 1] : 0, cv,
                              [&](int u, int v, int) {
                                const int32_t du = st[u];
                                if (du < 0) return;  // not the live neighbour of v
@@ -543,7 +606,7 @@ constexpr int32_t kTouchMaxEntries = 1 << 18;
 
 template <int MEM>
 __device__ __forceinline__ Node load_instance(const Params& p, int j, int32_t* st,
-                                              int32_t* list) {
+                                              int32_t* list, int32_t* heads) {
   const Instance in = p.inst[j];
   const int32_t* rp = p.rp_all + in.rp_off;
   const int32_t* ci = p.ci_all + in.ci_off;
@@ -565,18 +628,19 @@ __device__ __forceinline__ Node load_instance(const Params& p, int j, int32_t* s
     __syncthreads();
     rp = dst;
   }
-  return Node{st, in.n, rp, ci, list};
+  return Node{st, in.n, rp, ci, list, heads};
 }
 
 // A node with no instance yet, whose CSR pointers already point where this memory mode keeps
 // them (so that the compiler sees one kind of memory behind each pointer).
 template <int MEM>
-__device__ __forceinline__ Node empty_node(const Params& p, int32_t* st, int32_t* list) {
+__device__ __forceinline__ Node empty_node(const Params& p, int32_t* st, int32_t* list,
+                                           int32_t* heads) {
   const int32_t* rp = p.rp_all;
   const int32_t* ci = p.ci_all;
   if constexpr (MEM >= kMemLdsRp) rp = st + p.stride;
   if constexpr (MEM == kMemLdsCsr) ci = st + p.stride + rp_lds_words(p.n_max);
-  return Node{st, 0, rp, ci, list};
+  return Node{st, 0, rp, ci, list, heads};
 }
 
 // Whole workgroup: the root of instance j in LDS -- the input's degree array, s = 0, nothing
@@ -717,6 +781,7 @@ template <int MEM>
 __global__ void __launch_bounds__(1024) greedy_kernel(Params p) {
   __shared__ Ctrl c;
   __shared__ int32_t rm_list[kListCap];
+  __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = node_base<MEM>(p, blockIdx.x);
   if (threadIdx.x == 0) {
     c.flag_epoch = -1;
@@ -729,7 +794,7 @@ __global__ void __launch_bounds__(1024) greedy_kernel(Params p) {
     const bool skip = c.err;
     __syncthreads();  // every thread has read c.err before thread 0 writes it again
     if (skip) continue;
-    const Node nd = load_instance<MEM>(p, j, st, rm_list);
+    const Node nd = load_instance<MEM>(p, j, st, rm_list, heads);
     build_root(p, nd, j);
     const int64_t unbounded = 0x3FFFFFFFFFFFFFFFll;
     for (bool marked = false;; marked = true) {
@@ -796,6 +861,7 @@ template <bool PVC, bool PROF, int MEM, bool SO>
 __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   __shared__ Ctrl c;
   __shared__ int32_t rm_list[kListCap];
+  __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = node_base<MEM>(p, blockIdx.x);
   const int wg = blockIdx.x;
   const int tid = threadIdx.x;
@@ -821,7 +887,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
   bool marked = false;    // the node in LDS has flagged vertices still to be removed
   int cur = -1;           // instance of the node in LDS
   int32_t cur_k = 0, cur_vtx = 0;
-  Node nd = empty_node<MEM>(p, st, rm_list);
+  Node nd = empty_node<MEM>(p, st, rm_list, heads);
   int epoch = 0;
   int64_t nodes = 0, pushes = 0, pops = 0, enqueues = 0, dequeues = 0, insts = 0;
   int64_t unreported = 0;  // nodes on `cur` not yet added to its counter
@@ -842,7 +908,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         // StackOnly (the comparison method of §V-A), as in bitset_traverse_kernel: walk this
         // workgroup's next path down from the root, then take the node at the start depth.
         if (cur < 0) {
-          nd = load_instance<MEM>(p, 0, st, rm_list);
+          nd = load_instance<MEM>(p, 0, st, rm_list, heads);
           const Instance in = p.inst[0];
           cur = 0;
           cur_k = in.k;
@@ -947,7 +1013,7 @@ __global__ void __launch_bounds__(1024) traverse_kernel(Params p) {
         if (j != cur) {
           if (tid == 0 && cur >= 0) report_nodes(p, cur, unreported);
           unreported = 0;
-          nd = load_instance<MEM>(p, j, st, rm_list);
+          nd = load_instance<MEM>(p, j, st, rm_list, heads);
           const Instance in = p.inst[j];
           cur = j;
           cur_k = in.k;
@@ -1118,6 +1184,7 @@ __device__ void add_grouped(int32_t* dst, int32_t x) {
 // to the result block themselves.) Packed entry offsets must fit in int32.
 __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertices,
                                                        int64_t entries, DevResult* res) {
+  __shared__ int32_t heads[4 * 64];
   (void)entries;
   const int64_t waves = static_cast<int64_t>(gridDim.x) * (blockDim.x >> 6);
   for (int64_t w = static_cast<int64_t>(blockIdx.x) * (blockDim.x >> 6) + wave_id();
@@ -1147,7 +1214,7 @@ __global__ void __launch_bounds__(256) finalize_kernel(Params p, int64_t vertice
       ones_dst = &p.ist[j].cover_count;
     }
     add_grouped(ones_dst, one);
-    walk_rows(p.ci_all, beg, end, j, [&](int u, int jj, int) {
+    walk_rows(p.ci_all, heads + 64 * wave_id(), beg, end, j, [&](int u, int jj, int) {
       if (p.covers[p.inst[jj].vtx_off + u] == 0) atomicAdd(&p.ist[jj].uncovered, 1);
     });
   }
@@ -1166,6 +1233,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, in
                                                       int64_t bound) {
   __shared__ Ctrl c;
   __shared__ int32_t rm_list[kListCap];
+  __shared__ int32_t heads[kMaxWaves * 64];
   int32_t* st = node_base<MEM>(p, 0);
   if (threadIdx.x == 0) {
     c.err = load_relaxed(&p.ist[0].err_row) != kNoRow;
@@ -1174,7 +1242,7 @@ __global__ void __launch_bounds__(1024) reduce_kernel(Params p, int32_t* deg, in
   }
   __syncthreads();
   if (c.err) return;
-  const Node nd = load_instance<MEM>(p, 0, st, rm_list);
+  const Node nd = load_instance<MEM>(p, 0, st, rm_list, heads);
   const int n = nd.n;
   for (int v = threadIdx.x; v < p.stride; v += blockDim.x)
     st[v] = v < n ? deg[v] : (v == n ? *s : (v == n + 1 ? -1 : 0));

@@ -224,9 +224,8 @@ __device__ inline bool watchdog(const Params& p, Ctrl& c) {
 // Thread 0: is the search being stopped: aborted (an internal error, the host, the time
 // limit), or (PVC) every instance answered?
 __device__ __forceinline__ bool search_stopped(const Params& p, Ctrl& c) {
-  const int32_t aborted = load_relaxed(ctr_i32(p, kAbort));  // both words in one round trip
-  const int32_t open = p.pvc ? load_relaxed(ctr_i32(p, kOpen)) : 1;
-  return watchdog(p, c) || aborted != 0 || open == 0;
+  return watchdog(p, c) || load_relaxed(ctr_i32(p, kAbort)) != 0 ||
+         (p.pvc && load_relaxed(ctr_i32(p, kOpen)) == 0);
 }
 
 // Spin lock taken by one thread for a short critical section with no waits inside (an
@@ -296,20 +295,15 @@ __device__ inline void enqueue_publish(const Params& p, const Ctrl& c) {
 // ticket (the caller then waits for that slot to be filled), 2 with *root set to an instance
 // whose search has not started, 0 when the launch is finished, -1 when it is being stopped
 // (looked at only with check_stop), 3 when nothing is available yet. Queued nodes of started
-// instances go first; roots are taken in instance order. The entry count, the root counter
-// and the stop words are loaded together (one round trip); the outstanding-work counter, a
-// line that every finished sub-tree updates, is read only when neither of the first two
-// offers work.
+// instances go first; roots are taken in instance order. The words are read one after
+// another, each only when the ones before it offered nothing: loading them together shortened
+// a look but made the thousands of idle workgroups of a small search poll the shared control
+// lines harder, which slowed the workgroups doing the work more than it saved.
 __device__ inline int worklist_take(const Params& p, Ctrl& c, bool check_stop, uint32_t* slot,
                                     uint32_t* lap, int32_t* root) {
   int32_t* count = ctr_i32(p, kQCount);
-  int32_t* root_next = ctr_i32(p, kRootNext);
-  const int32_t queued = load_relaxed(count);
-  const int32_t next = load_relaxed(root_next);
-  const int32_t aborted = check_stop ? load_relaxed(ctr_i32(p, kAbort)) : 0;
-  const int32_t open = check_stop && p.pvc ? load_relaxed(ctr_i32(p, kOpen)) : 1;
-  if (check_stop && (aborted != 0 || open == 0 || watchdog(p, c))) return -1;
-  if (queued > 0) {
+  if (check_stop && search_stopped(p, c)) return -1;
+  if (load_relaxed(count) > 0) {
     if (fetch_add(count, -1) > 0) {
       const unsigned long long h = fetch_add(ctr_u64(p, kQHead), 1ull);
       *slot = static_cast<uint32_t>(h) & (p.q_cap - 1);
@@ -319,8 +313,8 @@ __device__ inline int worklist_take(const Params& p, Ctrl& c, bool check_stop, u
     fetch_add(count, 1);  // lost the race for the last entry: give the reservation back
     return 3;
   }
-  if (next < p.num_inst) {
-    const int32_t r = fetch_add(root_next, 1);
+  if (load_relaxed(ctr_i32(p, kRootNext)) < p.num_inst) {
+    const int32_t r = fetch_add(ctr_i32(p, kRootNext), 1);
     if (r < p.num_inst) {
       *root = r;
       return 2;

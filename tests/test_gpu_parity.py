@@ -185,6 +185,35 @@ def test_reduce_fixpoint_parity(solver, oracle_lib, torch_cuda, seed, kernel):
         assert np.array_equal(dd.cpu().numpy(), od), (bound, flags)
 
 
+@pytest.mark.parametrize("kernel", ["degree_arrays", "csr_global", "global_nodes"])
+@pytest.mark.parametrize("shape", ["matching", "triangles"])
+def test_removal_step_beyond_the_list(solver, oracle_lib, torch_cuda, kernel, shape):
+    """One removal step of more than 1,024 vertices, the capacity of a workgroup's removal list
+    (the rest are taken in further rounds): 1,500 disjoint edges, where the degree-one rule
+    removes one end of every edge in a single pass, or 1,100 disjoint triangles, where the
+    triangle rule removes two vertices of each. The fixpoint equals the oracle's element by
+    element; MVC gives tau and a valid cover; PVC at tau - 1 visits the oracle's node count."""
+    import paper_2204_10402_amd as vc
+    torch = torch_cuda
+    if shape == "matching":
+        g, tau = G.disjoint_union(*([G.path(2)] * 1500)), 1500
+    else:
+        g, tau = G.disjoint_union(*([G.complete(3)] * 1100)), 2200
+    deg = np.diff(g.row_ptr).astype(np.int32)
+    od, os_ = oracle.reduce(g, deg, 0, 10**9, oracle.ALL & ~(oracle.RULE_HIGH | oracle.PRUNE_EDGES))
+    assert os_ == tau
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    dd = torch.from_numpy(deg.copy()).cuda()
+    assert solver.reduce_device(rp, ci, dd, 0, 10**9, 0x4 | KERNELS[kernel]) == tau
+    assert np.array_equal(dd.cpu().numpy(), od)
+    r = solver.mvc(g, vc.Options(flags=KERNELS[kernel]))
+    assert r.size == tau
+    check_cover(g, r.cover, tau)
+    p = solver.pvc(g, tau - 1, vc.Options(flags=KERNELS[kernel]))
+    assert not p.yes and p.stats["nodes"] == oracle.pvc(g, tau - 1).nodes
+
+
 @pytest.mark.parametrize("n,p,seed", [(60, 0.1, 0), (150, 0.08, 1), (500, 0.02, 2),
                                       (2000, 0.004, 3), (5000, 0.0016, 4)])
 def test_greedy_parity(solver, oracle_lib, torch_cuda, n, p, seed):

@@ -131,16 +131,13 @@ bool try_enqueue(Shared& s, Jitter& j, Node n) {
 }
 
 // Consumer (the device's worklist_take / dequeue_begin / dequeue_finish): 1 with a queued node,
-// 2 with a root, 0 when the launch is over. As on the device, the entry count and the root
-// counter are both read before either is used (with jitter in between), and only an atomic
-// claims anything; the outstanding-work counter is read last, when neither offered work.
+// 2 with a root, 0 when the launch is over. As on the device, the entry count, the root
+// counter and the outstanding-work counter are read in that order, each only when the ones
+// before it offered nothing, and only an atomic claims anything.
 int dequeue(Shared& s, Jitter& j, Node* out) {
   for (;;) {
     if (s.failed.load(std::memory_order_relaxed)) return 0;
-    const int32_t queued = s.count.load(std::memory_order_relaxed);
-    j();
-    const int32_t next = s.root_next.load(std::memory_order_relaxed);
-    if (queued > 0) {
+    if (s.count.load(std::memory_order_relaxed) > 0) {
       if (s.count.fetch_add(-1, std::memory_order_relaxed) > 0) {
         const uint64_t h = s.head.fetch_add(1, std::memory_order_relaxed);
         const uint32_t slot = static_cast<uint32_t>(h) & (s.cap - 1);
@@ -154,7 +151,7 @@ int dequeue(Shared& s, Jitter& j, Node* out) {
         return 1;
       }
       s.count.fetch_add(1, std::memory_order_relaxed);  // lost the race: give it back
-    } else if (next < s.num_inst) {
+    } else if (s.root_next.load(std::memory_order_relaxed) < s.num_inst) {
       const int32_t r = s.root_next.fetch_add(1, std::memory_order_relaxed);
       if (r < s.num_inst) {
         out->inst = r;
