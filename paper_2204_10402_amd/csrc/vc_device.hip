@@ -200,12 +200,12 @@ __device__ __forceinline__ void for_each_batch(const int32_t* st, int n, Pred pr
 // goes to wavefront i mod waves), so a few marked vertices with long rows in one wavefront's
 // part of the node do not leave the others idle. Marked vertices beyond the list's capacity
 // stay marked and are taken by further rounds of scan and walk. Workgroups of fewer than
-// kListWaves wavefronts skip the list: each wavefront walks the rows it finds. The walks only decrement entries that are live and
-// unmarked (a marked vertex is set to kSent by the scan, whichever of the two happens first),
-// which also keeps the LDS atomics off the entries of vertices already removed. Called right
-// after a barrier that ends a decide step (or a mark step); ends with a barrier. Two calls are
-// always separated by another barrier (a decide step), which orders the reset of the list
-// count before the next call's appends.
+// kListWaves wavefronts skip the list: each wavefront walks the rows it finds. The walks only
+// decrement entries that are live and unmarked (a marked vertex is set to kSent by the scan,
+// whichever of the two happens first), which also keeps the LDS atomics off the entries of
+// vertices already removed. Called right after a barrier that ends a decide step (or a mark
+// step); ends with a barrier. Two calls are always separated by another barrier (a decide
+// step), which orders the reset of the list count before the next call's appends.
 __device__ __forceinline__ void apply_marks(const Node nd, Ctrl& c) {
   const int n = nd.n;
   int32_t* st = nd.st;
@@ -247,8 +247,8 @@ __device__ __forceinline__ void apply_marks(const Node nd, Ctrl& c) {
       int at = 0;
       if (lane == 0) at = atomicAdd(&c.list_n, __popcll(mask));
       at = __builtin_amdgcn_readfirstlane(at);
-      const int rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32),
-                                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0));
+      const uint32_t below = __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mask), 0);
+      const int rank = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(mask >> 32), below);
       if (marked && at + rank < kListCap) {  // beyond the list: left marked for the next round
         st[v] = kSent;
         nd.list[at + rank] = v;
@@ -534,7 +534,8 @@ __device__ __forceinline__ void mark_vertex(const Node nd, int v) {
 // Copy a node between LDS and device memory, 16 bytes per thread per step. The same thread
 // always handles the same words, so a node written to the workgroup's own stack is read back
 // by the threads that wrote it. `pending` replaces word n+1 on the way out.
-__device__ __forceinline__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int stride, int n,
+__device__ __forceinline__ void node_store(int32_t* __restrict__ dst, const int32_t* st, int stride,
+                                           int n,
                            int pending) {
   const int4* s4 = reinterpret_cast<const int4*>(st);
   int4* d4 = reinterpret_cast<int4*>(dst);
@@ -554,13 +555,15 @@ __device__ __forceinline__ void node_store(int32_t* __restrict__ dst, const int3
 
 // Copy a stored node between two device-memory slots with the same thread-to-word mapping as
 // node_store / node_load, so each thread reads back words it wrote itself.
-__device__ __forceinline__ void node_copy(int32_t* __restrict__ dst, const int32_t* __restrict__ src, int stride) {
+__device__ __forceinline__ void node_copy(int32_t* __restrict__ dst, const int32_t* __restrict__ src,
+                                          int stride) {
   const int4* s4 = reinterpret_cast<const int4*>(src);
   int4* d4 = reinterpret_cast<int4*>(dst);
   for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
 }
 
-__device__ __forceinline__ void node_load(int32_t* st, const int32_t* __restrict__ src, int stride) {
+__device__ __forceinline__ void node_load(int32_t* st, const int32_t* __restrict__ src,
+                                          int stride) {
   const int4* s4 = reinterpret_cast<const int4*>(src);
   int4* d4 = reinterpret_cast<int4*>(st);
   for (int i = threadIdx.x; i < (stride >> 2); i += blockDim.x) d4[i] = s4[i];
