@@ -186,6 +186,33 @@ def test_reduce_fixpoint_parity(solver, oracle_lib, torch_cuda, seed, kernel):
 
 
 @pytest.mark.parametrize("kernel", ["degree_arrays", "csr_global", "global_nodes"])
+@pytest.mark.parametrize("bound,flags", [(60, 0), (100, 0), (200, 0), (10**9, 0x4), (10**9, 0x5)])
+def test_reduce_fixpoint_planted_full_size(solver, oracle_lib, torch_cuda, kernel, bound, flags):
+    """The root reduction of a 5,000-vertex planted graph (rows of about 125 entries, walked in
+    64-entry pieces by a 1,024-thread workgroup through its removal list), element by element
+    against the oracle's fixpoint, on every degree-array memory placement. Bounds 60 and 200
+    stop the cascade midway; at bound 100 the high-degree rule removes 1,488 vertices, more
+    than the removal list holds; without the high-degree rule, and with the triangle rule
+    alone, the fixpoints differ again."""
+    torch = torch_cuda
+    g = G.planted_cover(5000, 400, 40000, 0.75, 1)
+    deg = np.diff(g.row_ptr).astype(np.int32)
+    mask = oracle.ALL
+    if flags & 0x1:
+        mask &= ~oracle.RULE_DEG1
+    if flags & 0x2:
+        mask &= ~oracle.RULE_TRI
+    if flags & 0x4:
+        mask &= ~(oracle.RULE_HIGH | oracle.PRUNE_EDGES)
+    od, os_ = oracle.reduce(g, deg, 0, bound, mask)
+    rp = torch.from_numpy(g.row_ptr).cuda()
+    ci = torch.from_numpy(g.col_idx).cuda()
+    dd = torch.from_numpy(deg.copy()).cuda()
+    assert solver.reduce_device(rp, ci, dd, 0, bound, flags | KERNELS[kernel]) == os_
+    assert np.array_equal(dd.cpu().numpy(), od)
+
+
+@pytest.mark.parametrize("kernel", ["degree_arrays", "csr_global", "global_nodes"])
 @pytest.mark.parametrize("shape", ["matching", "triangles"])
 def test_removal_step_beyond_the_list(solver, oracle_lib, torch_cuda, kernel, shape):
     """One removal step of more than 1,024 vertices, the capacity of a workgroup's removal list
